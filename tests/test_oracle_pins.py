@@ -1,0 +1,301 @@
+"""Pins on the oracle's heuristic (Fig. 1 with Section III.B.3), each checked
+against something other than the oracle itself: hand-worked examples, closed
+forms that hold for any random stream, brute-force re-derivation of every
+step, an independent rescoring of every alignment, and the Smith-Waterman
+upper bound."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+B = O.blosum62().astype(np.int64)
+M64 = 2**64 - 1
+
+
+# ----------------------------------------------------------------------------
+# helpers written independently of the oracle
+# ----------------------------------------------------------------------------
+def rescore(qrow, trow, gop, gep, pgp):
+    """SCORE of two aligned ASCII rows, from the wording of Section III.B.1:
+    letter pairs from BLOSUM62; in each row, leading/trailing gap columns cost
+    PGP each, any other maximal gap run costs GOP + (len - 1) * GEP."""
+    al = O.alphabet()
+    s = 0
+    for a, b in zip(qrow, trow):
+        if a != "-" and b != "-":
+            s += int(B[al.index(a), al.index(b)])
+    for row in (qrow, trow):
+        core = row.strip("-")
+        lead = len(row) - len(row.lstrip("-"))
+        trail = len(row) - len(row.rstrip("-"))
+        s -= pgp * (lead + trail) if core else pgp * len(row)
+        for m in re.finditer(r"-+", core):
+            s -= gop + (len(m.group()) - 1) * gep
+    return s
+
+
+def ungap(row):
+    return row.replace("-", "")
+
+
+def rand_seq(rng, n, letters=20):
+    return rng.integers(0, letters, size=n).astype(np.uint8)
+
+
+def rand_params(rng, pgp=None):
+    return O.Params(gop=int(rng.integers(0, 15)), gep=int(rng.integers(0, 8)),
+                    pgp=int(rng.integers(0, 4)) if pgp is None else pgp,
+                    lfactor_q16=int(rng.integers(0, 65537)),
+                    sfactor_q16=int(rng.integers(0, 65537)),
+                    minfactor_q16=int(rng.integers(0, 65537)),
+                    rounds=int(rng.integers(1, 4)), seed=int(rng.integers(0, 2**63)))
+
+
+def numpy_draw(seed, tid, rnd, d):
+    """random() of (target, round), from numpy's own Philox4x64-10 (which
+    steps its 256-bit counter by one before each block, so start one below)."""
+    c = [tid, rnd, d // 16, 0]
+    for i in range(4):          # 256-bit decrement with borrow
+        c[i] = (c[i] - 1) & M64
+        if c[i] != M64:
+            break
+    g = np.random.Philox(counter=np.array(c, dtype=np.uint64),
+                         key=np.array([seed, 0], dtype=np.uint64))
+    w = g.random_raw(4)
+    return (int(w[(d // 4) % 4]) >> (16 * (d % 4))) & 0xFFFF
+
+
+# ----------------------------------------------------------------------------
+# hand-worked examples
+# ----------------------------------------------------------------------------
+def _examples():
+    ex, cur = [], None
+    for line in open(os.path.join(GOLD, "worked_examples.txt")):
+        line = line.rstrip("\n")
+        if line.startswith("#") or not line.strip():
+            continue
+        key, _, val = line.partition(" ")
+        if key == "example":
+            cur = {}
+        elif key == "end":
+            ex.append(cur)
+        else:
+            cur[key] = val
+    return ex
+
+
+@pytest.mark.parametrize("ex", _examples(), ids=lambda e: e["query"])
+def test_worked_examples(ex):
+    gop, gep, pgp = map(int, ex["penalties"].split())
+    lf, mf, sf = map(int, ex["factors"].split())
+    p = O.Params(gop=gop, gep=gep, pgp=pgp, lfactor_q16=lf, minfactor_q16=mf, sfactor_q16=sf,
+                 rounds=1, seed=int(ex["seed"]))
+    r = O.align_pair(O.encode(ex["query"]), O.encode(ex["target"]), int(ex["target_id"]), p,
+                     trace=True)
+    steps = [tuple(map(int, s.split())) for s in ex["steps"].split("|")]
+    assert r["trace"] == steps
+    assert O.decode(r["qrow"]) == ex["qrow"]
+    assert O.decode(r["trow"]) == ex["trow"]
+    assert r["score"] == int(ex["score"])
+
+
+# ----------------------------------------------------------------------------
+# P1: identity prefix -- closed form for any parameters, seed and rounds
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("case", range(60))
+def test_identity_prefix(case):
+    rng = np.random.default_rng(100 + case)
+    p = rand_params(rng)
+    n = int(rng.integers(1, 120))
+    x = int(rng.integers(0, 80))
+    a = rand_seq(rng, n)
+    tail = rand_seq(rng, x)
+    expect = int(sum(B[c, c] for c in a)) - p.pgp * x
+    # target = query + tail: the target is large
+    r = O.align_pair(a, np.concatenate([a, tail]), int(rng.integers(0, 10**6)), p)
+    assert r["score"] == expect
+    assert r["ops"] == ([n << 2 | O.OP_M] + ([x << 2 | O.OP_D] if x else []))
+    # query = target + tail: the query is large
+    r = O.align_pair(np.concatenate([a, tail]), a, int(rng.integers(0, 10**6)), p)
+    assert r["score"] == expect
+    assert r["ops"] == ([n << 2 | O.OP_M] + ([x << 2 | O.OP_I] if x else []))
+
+
+# ----------------------------------------------------------------------------
+# P2: one-letter small sequence with LF = 1: first best letter, closed form
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("case", range(40))
+def test_single_letter(case):
+    rng = np.random.default_rng(200 + case)
+    p = rand_params(rng)
+    p.lfactor_q16 = 65536
+    p.minfactor_q16 = 65536
+    L = rand_seq(rng, int(rng.integers(2, 60)))
+    s = rand_seq(rng, 1)
+    col = B[L, s[0]]
+    kbest = int(np.argmax(col))          # first maximum
+    expect = int(col.max()) - p.pgp * (len(L) - 1)
+    r = O.align_pair(s, L, 7, p)         # target large
+    assert r["score"] == expect
+    ops = ([kbest << 2 | O.OP_D] if kbest else []) + [4 | O.OP_M]
+    rest = len(L) - kbest - 1
+    ops += [rest << 2 | O.OP_D] if rest else []
+    assert r["ops"] == ops
+    r = O.align_pair(L, s, 8, p)         # query large
+    assert r["score"] == expect
+
+
+# ----------------------------------------------------------------------------
+# P3 + P4: every step re-derived by brute force, draws from numpy
+# ----------------------------------------------------------------------------
+def check_trace(q, t, tid, p, r):
+    target_large = len(t) >= len(q)
+    L, S = (t, q) if target_large else (q, t)
+    tr = r["trace"]
+    # round actually reported: recompute its factors from numpy draws
+    rnd = r["round"]
+    lf = max(p.minfactor_q16, numpy_draw(p.seed, tid, rnd, 0))
+    sf = max(p.minfactor_q16, numpy_draw(p.seed, tid, rnd, 1))
+    LF = (p.lfactor_q16 * lf) >> 16
+    SF = (p.sfactor_q16 * sf) >> 16
+    pL = pS = 0
+    total = 0
+    cols_q, cols_t = [], []
+    for step, (tpL, tpS, ls, ss, k, D) in enumerate(tr):
+        assert (tpL, tpS) == (pL, pS)
+        nL, nS = len(L) - pL, len(S) - pS
+        assert nL > 0 and nS > 0
+        u = numpy_draw(p.seed, tid, rnd, 2 + step)
+        assert ls == max(1, (nL * LF) >> 16)
+        assert ss == min(ls, max(1, (nS * SF * u) >> 32))
+        assert 1 <= ss <= ls <= nL and ss <= nS
+        Ds = [int(B[L[pL + kk:pL + kk + ss], S[pS:pS + ss]].sum()) for kk in range(ls - ss + 1)]
+        assert D == max(Ds) and k == Ds.index(max(Ds))
+        total += D
+        if step == 0:
+            total -= p.pgp * k
+        elif k > 0:
+            total -= p.gop + (k - 1) * p.gep
+        pL += k + ss
+        pS += ss
+    assert pL >= len(L) or pS >= len(S)
+    total -= p.pgp * ((len(L) - pL) + (len(S) - pS))
+    assert total == r["score"]
+
+
+@pytest.mark.parametrize("case", range(40))
+def test_steps_brute_force(case):
+    rng = np.random.default_rng(300 + case)
+    p = rand_params(rng)
+    q = rand_seq(rng, int(rng.integers(1, 90)), 24)
+    t = rand_seq(rng, int(rng.integers(1, 140)), 24)
+    tid = int(rng.integers(0, 2**40))
+    r = O.align_pair(q, t, tid, p, trace=True)
+    check_trace(q, t, tid, p, r)
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_steps_equal_length(case):
+    """Equal lengths: the target plays "large" (the paper leaves the choice
+    open); every gap column before the tail is then a target letter (D)."""
+    rng = np.random.default_rng(350 + case)
+    p = rand_params(rng)
+    n = int(rng.integers(2, 80))
+    q, t = rand_seq(rng, n), rand_seq(rng, n)
+    r = O.align_pair(q, t, case, p, trace=True)
+    check_trace(q, t, case, p, r)
+    assert all((o & 3) != O.OP_I for o in r["ops"][:-1])
+
+
+def test_steps_full_factors():
+    """LFactor = MinFactor = 1 makes ls exactly the rest of large."""
+    rng = np.random.default_rng(7)
+    for i in range(20):
+        p = O.Params(lfactor_q16=65536, minfactor_q16=65536, sfactor_q16=65536,
+                     seed=int(rng.integers(0, 2**62)))
+        q, t = rand_seq(rng, 40), rand_seq(rng, 70)
+        r = O.align_pair(q, t, i, p, trace=True)
+        for (pL, pS, ls, ss, k, D) in r["trace"]:
+            assert ls == len(t) - pL
+        check_trace(q, t, i, p, r)
+
+
+# ----------------------------------------------------------------------------
+# P5: independent rescoring and validity of every alignment
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("case", range(60))
+def test_rescore(case):
+    rng = np.random.default_rng(400 + case)
+    p = rand_params(rng)
+    q = rand_seq(rng, int(rng.integers(1, 200)), 24)
+    t = rand_seq(rng, int(rng.integers(1, 300)), 24)
+    r = O.align_pair(q, t, case, p)
+    qr, tr = O.decode(r["qrow"]), O.decode(r["trow"])
+    assert ungap(qr) == O.decode(q) and ungap(tr) == O.decode(t)
+    assert all(not (a == "-" and b == "-") for a, b in zip(qr, tr))
+    assert rescore(qr, tr, p.gop, p.gep, p.pgp) == r["score"]
+    # ops cover both sequences from position 0
+    nq = sum(o >> 2 for o in r["ops"] if (o & 3) in (O.OP_M, O.OP_I))
+    nt = sum(o >> 2 for o in r["ops"] if (o & 3) in (O.OP_M, O.OP_D))
+    assert (nq, nt) == (len(q), len(t))
+
+
+# ----------------------------------------------------------------------------
+# P6: no heuristic score exceeds the affine Smith-Waterman optimum
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("case", range(40))
+def test_below_smith_waterman(case):
+    rng = np.random.default_rng(500 + case)
+    p = rand_params(rng)
+    q = rand_seq(rng, int(rng.integers(1, 150)))
+    if case % 2:   # related pair: mutated copy with an insertion
+        t = q.copy()
+        t[rng.random(len(t)) < 0.3] = rng.integers(0, 20)
+        t = np.concatenate([rand_seq(rng, 5), t[: len(t) // 2], rand_seq(rng, 7), t[len(t) // 2:]])
+    else:
+        t = rand_seq(rng, int(rng.integers(1, 200)))
+    r = O.align_pair(q, t, case, p)
+    assert r["score"] <= O.sw_score(q, t, p.gop, p.gep)
+
+
+# ----------------------------------------------------------------------------
+# P9: more rounds never lower the score (round r's draws depend only on r)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("case", range(15))
+def test_rounds_monotone(case):
+    rng = np.random.default_rng(600 + case)
+    p = rand_params(rng)
+    q, t = rand_seq(rng, int(rng.integers(5, 100))), rand_seq(rng, int(rng.integers(5, 150)))
+    prev = None
+    for R in range(1, 7):
+        p.rounds = R
+        r = O.align_pair(q, t, case, p)
+        if prev is not None:
+            assert r["score"] >= prev[0]
+            if r["score"] == prev[0]:
+                assert r["round"] == prev[1]    # first round kept on ties
+        prev = (r["score"], r["round"])
+
+
+# ----------------------------------------------------------------------------
+# search: ranking rule and agreement with pairwise runs
+# ----------------------------------------------------------------------------
+def test_search_rank_and_planted():
+    import synth
+    q, res, off, planted = synth.tiny_db(seed=11, n_bg=300, qlen=40, n_hom=8)
+    codes = O.encode_db(res, off)
+    qc = O.encode(bytes(q))
+    out = O.search(codes, off, qc, O.Params(), k=60, n_aln=10)
+    sc = out["all_scores"]
+    ids = out["ids"]
+    keys = [(-int(sc[i]), int(i)) for i in ids]
+    assert keys == sorted(keys)
+    rest = np.setdiff1d(np.arange(len(sc)), ids)
+    assert (sc[rest] <= sc[ids[-1]]).all()
+    for i in (0, 5, 77):
+        a = O.align_pair(qc, codes[off[i]:off[i + 1]], i, O.Params())
+        assert a["score"] == sc[i]
