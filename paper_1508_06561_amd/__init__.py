@@ -1,0 +1,10 @@
+"""MI355X (gfx950) search library for the constant-auxiliary-space heuristic of
+Nag & Karforma (arXiv 1508.06561): one query, or a batch, against a protein
+database, ranked, with alignments for the best hits.  The work runs in the
+HIP kernels of libhs.so behind the C ABI of include/hs.h; this package is the
+Python binding of that ABI."""
+from .hs import (ALPHABET, HSError, Database, DeviceSearch, Params, Result, builtin_matrix,
+                 encode, lib, params_default)
+
+__all__ = ["ALPHABET", "HSError", "Database", "DeviceSearch", "Params", "Result", "builtin_matrix",
+           "encode", "lib", "params_default"]

@@ -1,0 +1,281 @@
+"""Python binding of the C ABI in include/hs.h (argument marshalling only).
+
+Every step of a search runs in the HIP kernels of ``libhs.so``; this module
+passes pointers and sizes through ctypes, takes device buffers from torch and
+the stream from ``torch.cuda.current_stream()``.  It fails loudly when the
+library is missing: there is no other path.
+"""
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhs.so")
+
+HS_OK, HS_EINVAL, HS_ENOMEM, HS_ENOSPC, HS_EDEVICE = 0, -1, -2, -3, -4
+OP_M, OP_I, OP_D = 0, 1, 2
+MAX_K = 4096
+MAX_QUERY = 6000
+ALPHABET = "ARNDCQEGHILKMFPSTWYVBZX*"
+
+
+class HSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hs error {code}: {msg}")
+        self.code = code
+
+
+class _CParams(ctypes.Structure):
+    _fields_ = [("gop", ctypes.c_int32), ("gep", ctypes.c_int32), ("pgp", ctypes.c_int32),
+                ("lfactor_q16", ctypes.c_int32), ("sfactor_q16", ctypes.c_int32),
+                ("minfactor_q16", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("min_score", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("matrix", ctypes.POINTER(ctypes.c_int8))]
+
+
+class Hit(ctypes.Structure):
+    _fields_ = [("target_id", ctypes.c_int64), ("score", ctypes.c_int32), ("round", ctypes.c_int32)]
+
+
+class Aln(ctypes.Structure):
+    _fields_ = [("target_id", ctypes.c_int64), ("score", ctypes.c_int32), ("n_ops", ctypes.c_int32),
+                ("ops_off", ctypes.c_int64)]
+
+
+HIT_DTYPE = np.dtype([("target_id", np.int64), ("score", np.int32), ("round", np.int32)])
+ALN_DTYPE = np.dtype([("target_id", np.int64), ("score", np.int32), ("n_ops", np.int32),
+                      ("ops_off", np.int64)])
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build())")
+        # torch brings its own HIP runtime (same soname); loading it first
+        # makes libhs.so bind to that one instead of a second runtime that
+        # would contend for the device.
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        L.hs_params_default.argtypes = [P(_CParams)]
+        L.hs_builtin_matrix.argtypes = [P(ctypes.c_int8)]
+        L.hs_encode.argtypes = [ctypes.c_char_p, ctypes.c_int64, P(ctypes.c_uint8)]
+        L.hs_db_load.argtypes = [vp, P(ctypes.c_int64), ctypes.c_int64, vp, P(vp)]
+        L.hs_db_free.argtypes = [vp]
+        L.hs_db_info.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
+        L.hs_workspace_bytes.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32]
+        L.hs_workspace_bytes.restype = ctypes.c_size_t
+        L.hs_search.argtypes = [vp, ctypes.c_char_p, ctypes.c_int32, P(_CParams), ctypes.c_int32,
+                                ctypes.c_int32, vp, vp, P(ctypes.c_int32), vp, P(ctypes.c_int32),
+                                vp, ctypes.c_int64, P(ctypes.c_int64)]
+        L.hs_search_dev.argtypes = [vp, vp, ctypes.c_int32, P(_CParams), ctypes.c_int32,
+                                    ctypes.c_int32, vp, vp, ctypes.c_size_t, vp, vp, vp, vp,
+                                    ctypes.c_int64]
+        L.hs_score_dev.argtypes = [vp, vp, ctypes.c_int32, P(_CParams), vp, vp, vp, vp]
+        L.hs_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != HS_OK:
+        raise HSError(rc, lib().hs_last_error().decode())
+    return rc
+
+
+@dataclasses.dataclass
+class Params:
+    """hs_params; defaults are the search setting of Section IV of the paper
+    (PGP 0, GOP 10, GEP 5, LFactor 0.5, SFactor 1, MinFactor 0.5, Rounds 1)."""
+    gop: int = 10
+    gep: int = 5
+    pgp: int = 0
+    lfactor_q16: int = 32768
+    sfactor_q16: int = 65536
+    minfactor_q16: int = 32768
+    rounds: int = 1
+    min_score: int = -(2**31)
+    seed: int = 0
+    matrix: np.ndarray = None
+
+    def c(self):
+        p = _CParams(self.gop, self.gep, self.pgp, self.lfactor_q16, self.sfactor_q16,
+                     self.minfactor_q16, self.rounds, self.min_score, self.seed & (2**64 - 1), None)
+        if self.matrix is not None:
+            self._m = np.ascontiguousarray(self.matrix, dtype=np.int8).reshape(24, 24)
+            p.matrix = self._m.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+        return p
+
+
+def params_default():
+    p = _CParams()
+    lib().hs_params_default(ctypes.byref(p))
+    return Params(p.gop, p.gep, p.pgp, p.lfactor_q16, p.sfactor_q16, p.minfactor_q16, p.rounds,
+                  p.min_score, p.seed)
+
+
+def builtin_matrix():
+    m = np.zeros((24, 24), dtype=np.int8)
+    lib().hs_builtin_matrix(m.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+    return m
+
+
+def encode(seq):
+    """ASCII -> alphabet codes (host)."""
+    b = seq.encode() if isinstance(seq, str) else bytes(seq)
+    out = np.empty(len(b), dtype=np.uint8)
+    _check(lib().hs_encode(b, len(b), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+    return out
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclasses.dataclass
+class Result:
+    hits: np.ndarray          # HIT_DTYPE, ranked
+    alns: np.ndarray          # ALN_DTYPE, alns[i] belongs to hits[i]
+    ops: np.ndarray           # uint32 run-length ops, alns index into it
+
+    def ops_of(self, i):
+        a = self.alns[i]
+        return self.ops[a["ops_off"]:a["ops_off"] + a["n_ops"]]
+
+
+class Database:
+    """A database loaded on the device (hs_db_load).  `residues` is a uint8
+    array of concatenated ASCII letters, `offsets` int64 with n + 1 bounds."""
+
+    def __init__(self, residues, offsets, stream=None):
+        res = np.ascontiguousarray(residues, dtype=np.uint8)
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        h = ctypes.c_void_p()
+        _check(lib().hs_db_load(res.ctypes.data_as(ctypes.c_void_p),
+                                off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                len(off) - 1, _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.n_targets = len(off) - 1
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hs_db_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().hs_db_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return dict(n_targets=a.value, n_residues=b.value, device_bytes=c.value)
+
+    def search(self, query, params=None, k=50, n_aln=50, stream=None):
+        """hs_search: host query in, host results out."""
+        p = (params or Params()).c()
+        q = query.encode() if isinstance(query, str) else bytes(query)
+        hits = np.zeros(k, dtype=HIT_DTYPE)
+        alns = np.zeros(max(n_aln, 1), dtype=ALN_DTYPE)
+        cap = max(1, n_aln * (2 * len(q) + 2))
+        ops = np.zeros(cap, dtype=np.uint32)
+        nh, na, used = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().hs_search(self._h, q, len(q), ctypes.byref(p), k, n_aln, _stream(stream),
+                               hits.ctypes.data, ctypes.byref(nh), alns.ctypes.data,
+                               ctypes.byref(na), ops.ctypes.data, cap, ctypes.byref(used)))
+        n_a = na.value if n_aln > 0 else 0
+        return Result(hits[:nh.value].copy(), alns[:n_a].copy(), ops[:used.value].copy())
+
+    # ---- device-resident form (hs_search_dev) ----
+    def workspace_bytes(self, nq, max_qlen, k, n_aln):
+        return int(lib().hs_workspace_bytes(self._h, nq, max_qlen, k, n_aln))
+
+    def search_dev(self, d_qcodes, qlen, params, k, n_aln, d_ws, d_hits, d_n_hits, d_alns, d_ops,
+                   ops_stride, stream=None):
+        """Queues one search; every buffer argument is a torch CUDA tensor."""
+        p = params.c()
+        _check(lib().hs_search_dev(self._h, d_qcodes.data_ptr(), qlen, ctypes.byref(p), k, n_aln,
+                                   _stream(stream), d_ws.data_ptr(), d_ws.numel() * d_ws.element_size(),
+                                   d_hits.data_ptr(), d_n_hits.data_ptr(),
+                                   d_alns.data_ptr() if d_alns is not None else None,
+                                   d_ops.data_ptr() if d_ops is not None else None, ops_stride))
+
+
+    def score_dev(self, d_qcodes, qlen, params, d_scores, d_rounds=None, d_cells=None,
+                  stream=None):
+        """Queues hs_score_dev: every target's pair score into d_scores (int32
+        torch CUDA tensor of n_targets), winning rounds into d_rounds, and
+        the scored residue pairs added to d_cells (one int64)."""
+        p = params.c()
+        _check(lib().hs_score_dev(self._h, d_qcodes.data_ptr(), qlen, ctypes.byref(p),
+                                  _stream(stream), d_scores.data_ptr(),
+                                  d_rounds.data_ptr() if d_rounds is not None else None,
+                                  d_cells.data_ptr() if d_cells is not None else None))
+
+    def scores(self, query, params=None):
+        """(scores, rounds, cells): every target's pair score and winning
+        round (host int32 arrays) and the total scored residue pairs."""
+        import torch
+        codes = torch.from_numpy(encode(query)).cuda()
+        out = torch.empty(max(self.n_targets, 1), dtype=torch.int32, device="cuda")
+        rounds = torch.empty(max(self.n_targets, 1), dtype=torch.int32, device="cuda")
+        cells = torch.zeros(1, dtype=torch.int64, device="cuda")
+        self.score_dev(codes, len(codes), params or Params(), out, rounds, cells)
+        return (out.cpu().numpy()[:self.n_targets], rounds.cpu().numpy()[:self.n_targets],
+                int(cells.cpu()[0]))
+
+
+class DeviceSearch:
+    """Preallocated torch device buffers for repeated hs_search_dev calls on
+    one database (benchmarks, serving)."""
+
+    def __init__(self, db, max_qlen, k, n_aln, device="cuda"):
+        import torch
+        self.db, self.k, self.n_aln = db, k, n_aln
+        self.stride = 2 * max_qlen + 2
+        ws = db.workspace_bytes(1, max_qlen, k, n_aln)
+        self.ws = torch.empty(ws, dtype=torch.uint8, device=device)
+        self.q = torch.empty(max_qlen, dtype=torch.uint8, device=device)
+        self.hits = torch.empty(k * HIT_DTYPE.itemsize, dtype=torch.uint8, device=device)
+        self.n_hits = torch.empty(1, dtype=torch.int32, device=device)
+        self.alns = torch.empty(max(n_aln, 1) * ALN_DTYPE.itemsize, dtype=torch.uint8, device=device)
+        self.ops = torch.empty(max(n_aln, 1) * self.stride, dtype=torch.int32, device=device)
+
+    def set_query(self, query):
+        import torch
+        codes = encode(query)
+        self.qlen = len(codes)
+        self.q[:self.qlen].copy_(torch.from_numpy(codes))
+
+    def run(self, params, stream=None):
+        self.db.search_dev(self.q, self.qlen, params, self.k, self.n_aln, self.ws, self.hits,
+                           self.n_hits, self.alns, self.ops, self.stride, stream)
+
+    def fetch(self):
+        """Copies the last results to the host (synchronises)."""
+        nh = int(self.n_hits.cpu()[0])
+        hits = np.frombuffer(self.hits.cpu().numpy().tobytes(), dtype=HIT_DTYPE)[:nh].copy()
+        na = min(self.n_aln, nh)
+        alns = np.frombuffer(self.alns.cpu().numpy().tobytes(), dtype=ALN_DTYPE)[:na].copy()
+        ops = self.ops.cpu().numpy().view(np.uint32)
+        chunks, off = [], 0
+        for i in range(na):
+            a = alns[i]
+            chunks.append(ops[a["ops_off"]:a["ops_off"] + a["n_ops"]])
+            alns[i]["ops_off"] = off
+            off += a["n_ops"]
+        return Result(hits, alns, np.concatenate(chunks) if chunks else np.zeros(0, np.uint32))
