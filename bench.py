@@ -126,12 +126,12 @@ def main():
     # dominant kernel alone (pair scoring), same stream, HIP events
     scores = torch.empty(w.n_targets, dtype=torch.int32, device="cuda")
     cells_t = torch.zeros(1, dtype=torch.int64, device="cuda")
-    db.score_dev(ds.q, ds.qlen, p, scores, None, cells_t)
+    db.score_dev(ds.q, ds.qlen, p, ds.ws, scores, None, cells_t)
     torch.cuda.synchronize()
     cells = int(cells_t.cpu()[0])
     ev0.record(stream)
     for _ in range(args.steps):
-        db.score_dev(ds.q, ds.qlen, p, scores)
+        db.score_dev(ds.q, ds.qlen, p, ds.ws, scores)
     ev1.record(stream)
     torch.cuda.synchronize()
     k_ms = ev0.elapsed_time(ev1) / args.steps

@@ -50,7 +50,7 @@ extern "C" {
 
 #define HS_MAX_K 4096          /* most ranked hits per query */
 #define HS_MAX_SEQ 1000000     /* longest target */
-#define HS_MAX_QUERY 6000      /* longest query: its score profile lives in LDS */
+#define HS_MAX_QUERY 5600      /* longest query: its score profile lives in LDS */
 #define HS_MAX_PENALTY 1000    /* largest GOP, GEP or PGP */
 
 /* Parameters of Section III.B.1.  Factors are Q16 fixed point (65536 = 1.0)
@@ -111,9 +111,9 @@ int hs_encode(const char* ascii, int64_t n, uint8_t* codes);
 /* Loads a database (Section III.B.5: a flat collection of protein
  * sequences).  `residues` (host) holds the targets' letters concatenated;
  * target i is residues[offsets[i] .. offsets[i+1]).  Target i's index in
- * every result is i.  The library validates and copies the letters, then
- * packs them on the device (5-bit codes, six per 32-bit word), binned by
- * length and interleaved 64 targets wide; the returned handle owns that
+ * every result is i.  The library copies the letters to the device and
+ * encodes them there (one alphabet code per byte, targets back to back, a
+ * length-sorted hand-out order alongside); the returned handle owns that
  * device image until hs_db_free.  Every target needs 1..HS_MAX_SEQ letters. */
 int hs_db_load(const char* residues, const int64_t* offsets, int64_t n_targets,
                void* stream, hs_db** out);
@@ -165,12 +165,14 @@ int hs_search_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const 
  * every target (Fig. 1 with Section III.B.3), written by target index into
  * d_scores (int32) and the winning round into d_rounds (int32; may be NULL),
  * both device arrays of n_targets entries.  No ranking, no alignments; the
- * caller may threshold or rank the scores itself.  If d_cells (one device
- * uint64) is not NULL, the number of residue pairs scored on diagonals --
- * the sum over all steps of (ls - ss + 1) * ss, the work measure of Section
- * III.B.4 -- is added to it.  Queued on `stream`. */
+ * caller may threshold or rank the scores itself.  d_ws is a device
+ * workspace of at least hs_workspace_bytes(db, 1, qlen, 1, 0) bytes.  If
+ * d_cells (one device uint64) is not NULL, the number of residue pairs scored
+ * on diagonals -- the sum over all steps of (ls - ss + 1) * ss, the work
+ * measure of Section III.B.4 -- is added to it.  Queued on `stream`. */
 int hs_score_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const hs_params* params,
-                 void* stream, int32_t* d_scores, int32_t* d_rounds, uint64_t* d_cells);
+                 void* stream, void* d_ws, size_t ws_bytes, int32_t* d_scores, int32_t* d_rounds,
+                 uint64_t* d_cells);
 
 /* Thread-local description of the last failing call on this thread. */
 const char* hs_last_error(void);

@@ -1,6 +1,6 @@
 // device_common.hpp -- shared device-side pieces of the search library:
 // the keyed random stream behind random() of Fig. 1, parameters in kernel
-// form, and the packed database view.
+// form, the database view and the window arithmetic of one step.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,8 +9,11 @@
 namespace hs {
 
 constexpr int kNsym = 24;         // BLOSUM62 alphabet ARNDCQEGHILKMFPSTWYVBZX*
-constexpr int kLanes = 64;        // wavefront width; also the interleave width
-constexpr int kResPerWord = 6;    // 5-bit residue codes per 32-bit word
+constexpr int kLanes = 64;        // wavefront width
+constexpr int kZeroRow = 24;      // profile row of zeros (no-op lookups)
+constexpr int kProfRows = 25;
+constexpr int kPad = 8;           // zero profile columns on each side of the query
+constexpr int kLetterPad = 64;    // readable bytes after the last target letter
 
 // Parameters of Section III.B.1 as the kernels use them.
 struct KParams {
@@ -26,18 +29,16 @@ struct KMatrix {
     int8_t m[kNsym * kNsym];
 };
 
-// Device image of a database.  Targets are sorted by length (longest first)
-// and dealt into groups of 64; group g occupies rows of 64 words starting at
-// words[group_base[g]], lane l of the group reading word w at
-// words[group_base[g] + w * 64 + l], so that a wavefront whose lanes walk
-// their targets in step reads 256 contiguous bytes.
+// Device image of a database: one byte (alphabet code) per residue, targets
+// concatenated in index order, followed by kLetterPad readable bytes.
+// `order` lists target indices longest first: the order in which pairs are
+// handed out, so that the longest pairs start early.
 struct DbView {
-    const uint32_t* words;
-    const int64_t* group_base;
-    const int32_t* slot_id;     // g * 64 + lane -> target index, -1 if empty
-    const int32_t* slot_len;    // g * 64 + lane -> length
-    const int32_t* loc;         // target index -> g * 64 + lane
-    int32_t n_groups;
+    const uint8_t* letters;
+    const int64_t* offsets;     // start of target i in letters
+    const int32_t* lens;
+    const int32_t* order;
+    int32_t n;
 };
 
 // ---------------------------------------------------------------------------
@@ -67,11 +68,17 @@ __device__ __forceinline__ void philox4x64_10(uint64_t& x0, uint64_t& x1, uint64
 // The random fractions of one (target, round): 16-bit values, sixteen per
 // Philox block.  Draw d lives in block d / 16 (counter = (target, round,
 // d / 16, 0), key = (seed, 0)), word (d / 4) % 4, bits 16 * (d % 4).
+__device__ __forceinline__ void philox_block(uint64_t seed, uint64_t target, uint32_t round,
+                                             uint32_t block, uint64_t w[4]) {
+    w[0] = target; w[1] = round; w[2] = block; w[3] = 0;
+    philox4x64_10(w[0], w[1], w[2], w[3], seed, 0);
+}
+
 struct DrawStream {
     uint64_t seed, target;
     uint32_t round;
     int32_t block;
-    uint64_t w0, w1, w2, w3;
+    uint64_t w[4];
 
     __device__ __forceinline__ void init(uint64_t s, uint64_t t, uint32_t r) {
         seed = s; target = t; round = r; block = -1;
@@ -80,14 +87,19 @@ struct DrawStream {
         const int32_t b = (int32_t)(d >> 4);
         if (b != block) {
             block = b;
-            w0 = target; w1 = round; w2 = (uint64_t)b; w3 = 0;
-            philox4x64_10(w0, w1, w2, w3, seed, 0);
+            philox_block(seed, target, round, (uint32_t)b, w);
         }
         const uint32_t wi = (d >> 2) & 3;
-        const uint64_t w = wi == 0 ? w0 : wi == 1 ? w1 : wi == 2 ? w2 : w3;
-        return (uint32_t)(w >> (16 * (d & 3))) & 0xFFFFu;
+        const uint64_t x = wi == 0 ? w[0] : wi == 1 ? w[1] : wi == 2 ? w[2] : w[3];
+        return (uint32_t)(x >> (16 * (d & 3))) & 0xFFFFu;
     }
 };
+
+// Per-round factors (Fig. 1, AlignSequences): lf = MAX(minFactor, random())
+// scaled by LFactor, likewise sf by SFactor (Q16).
+__device__ __forceinline__ uint32_t round_factor(uint32_t factor, uint32_t minf, uint32_t u) {
+    return (uint32_t)(((uint64_t)factor * (u < minf ? minf : u)) >> 16);
+}
 
 // Window sizes of one step (Fig. 1, PROCEDURE Align), Q16 fixed point.
 __device__ __forceinline__ int32_t window_large(int32_t rem_large, uint32_t LF) {
@@ -108,30 +120,14 @@ __device__ __forceinline__ int32_t shift_penalty(const KParams& p, int32_t t, in
     return k > 0 ? p.gop + (k - 1) * p.gep : 0;
 }
 
-// Sequential reader of one interleaved target: returns 5-bit codes from
-// position p onwards.  Reads one word ahead, so the word array carries one
-// spare row of padding after the last group.
-struct TargetStream {
-    const uint32_t* ptr;
-    uint32_t w;
-    int32_t ph;
-    __device__ __forceinline__ void seek(const uint32_t* lane_base, int32_t p) {
-        const int32_t q = p / kResPerWord;
-        ph = p - q * kResPerWord;
-        ptr = lane_base + (int64_t)q * kLanes;
-        w = *ptr >> (5 * ph);
-    }
-    __device__ __forceinline__ uint32_t next() {
-        const uint32_t r = w & 31u;
-        if (++ph == kResPerWord) {
-            ph = 0;
-            ptr += kLanes;
-            w = *ptr;
-        } else {
-            w >>= 5;
-        }
-        return r;
-    }
-};
+// Key of a placement for the first-best rule: larger score first, then the
+// smaller shift; comparing keys as unsigned integers picks the winner.
+__device__ __forceinline__ uint64_t shift_key(int32_t D, int32_t k) {
+    return ((uint64_t)((uint32_t)D ^ 0x80000000u) << 32) | (uint64_t)(~(uint32_t)k);
+}
+__device__ __forceinline__ int32_t key_score(uint64_t key) {
+    return (int32_t)((uint32_t)(key >> 32) ^ 0x80000000u);
+}
+__device__ __forceinline__ int32_t key_shift(uint64_t key) { return (int32_t)(~(uint32_t)key); }
 
 }  // namespace hs

@@ -95,58 +95,34 @@ __constant__ int8_t c_codes[256];
 struct hs_db {
     int64_t n_targets = 0;
     int64_t n_residues = 0;
-    int32_t n_groups = 0;
-    int64_t n_words = 0;
-    uint32_t* d_words = nullptr;
-    int64_t* d_group_base = nullptr;   // n_groups + 1
-    int32_t* d_slot_id = nullptr;
-    int32_t* d_slot_len = nullptr;
-    int32_t* d_loc = nullptr;
+    uint8_t* d_letters = nullptr;   // codes, index order, kLetterPad readable bytes after
+    int64_t* d_offsets = nullptr;
+    int32_t* d_lens = nullptr;
+    int32_t* d_order = nullptr;     // longest first
+    PairRec* d_recs = nullptr;      // (index, length, offset) in hand-out order
+    int64_t n_queue = 0;            // hand-out positions (targets plus padding)
     int64_t device_bytes = 0;
 
     DbView view() const {
         DbView v;
-        v.words = d_words;
-        v.group_base = d_group_base;
-        v.slot_id = d_slot_id;
-        v.slot_len = d_slot_len;
-        v.loc = d_loc;
-        v.n_groups = n_groups;
+        v.letters = d_letters;
+        v.offsets = d_offsets;
+        v.lens = d_lens;
+        v.order = d_order;
+        v.n = (int32_t)n_targets;
         return v;
     }
 };
 
-// One workgroup per group of 64 targets: encode letters and pack six 5-bit
-// codes per word, lane-interleaved.
-__global__ __launch_bounds__(256) void k_pack(const uint8_t* __restrict__ residues,
-                                              const int64_t* __restrict__ offsets,
-                                              const int32_t* __restrict__ slot_id,
-                                              const int32_t* __restrict__ slot_len,
-                                              const int64_t* __restrict__ group_base,
-                                              uint32_t* __restrict__ words, int32_t* err) {
-    const int32_t g = blockIdx.x;
-    const int64_t base = group_base[g];
-    const int64_t nw = group_base[g + 1] - base;
-    for (int64_t x = threadIdx.x; x < nw; x += blockDim.x) {
-        const int32_t lane = (int32_t)(x & (kLanes - 1));
-        const int64_t w = x >> 6;
-        const int32_t id = slot_id[g * kLanes + lane];
-        uint32_t word = 0;
-        if (id >= 0) {
-            const int64_t len = slot_len[g * kLanes + lane];
-            const uint8_t* src = residues + offsets[id];
-            for (int i = 0; i < kResPerWord; ++i) {
-                const int64_t p = w * kResPerWord + i;
-                if (p >= len) break;
-                int c = c_codes[src[p]];
-                if (c < 0) {
-                    atomicOr(err, 1);
-                    c = 0;
-                }
-                word |= (uint32_t)c << (5 * i);
-            }
-        }
-        words[base + x] = word;
+// Encodes ASCII letters to alphabet codes in place; flags bytes outside the
+// alphabet.
+__global__ __launch_bounds__(256) void k_encode(uint8_t* __restrict__ letters, int64_t n,
+                                                int32_t* err) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = c_codes[letters[i]];
+        if (c < 0) atomicOr(err, 1);
+        letters[i] = (uint8_t)(c < 0 ? 0 : c);
     }
 }
 
@@ -154,11 +130,11 @@ namespace {
 
 void free_db(hs_db* db) {
     if (!db) return;
-    (void)hipFree(db->d_words);
-    (void)hipFree(db->d_group_base);
-    (void)hipFree(db->d_slot_id);
-    (void)hipFree(db->d_slot_len);
-    (void)hipFree(db->d_loc);
+    (void)hipFree(db->d_letters);
+    (void)hipFree(db->d_offsets);
+    (void)hipFree(db->d_lens);
+    (void)hipFree(db->d_order);
+    (void)hipFree(db->d_recs);
     delete db;
 }
 
@@ -213,6 +189,13 @@ KMatrix kmatrix(const hs_params* p) {
     return m;
 }
 
+// Offset that makes every matrix entry a byte in 0..15.
+int32_t matrix_bias(const KMatrix& m) {
+    int mn = 127;
+    for (int i = 0; i < kNsym * kNsym; ++i) mn = std::min<int>(mn, m.m[i]);
+    return -mn;
+}
+
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -220,34 +203,41 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct QueryWs {
     int32_t* scores;
     int32_t* rounds;
+    uint64_t* draws;
+    uint32_t* queue;
     TopkState* topk;
     uint32_t* hist;
     uint64_t* keys;
 };
 
-size_t query_ws_bytes(int64_t n_targets, int32_t k) {
-    return 2 * align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(n_targets, 1)) +
+size_t query_ws_bytes(int64_t n_targets, int64_t n_queue, int32_t k) {
+    const size_t n = (size_t)std::max<int64_t>(n_targets, 1);
+    const size_t nq = (size_t)std::max<int64_t>(n_queue, 1);
+    return 2 * align_up(sizeof(int32_t) * n) + align_up(sizeof(uint64_t) * 8 * nq) + kAlign +
            align_up(sizeof(TopkState)) + align_up(sizeof(uint32_t) * kTopkBins) +
            align_up(sizeof(uint64_t) * (size_t)std::max(k, 1));
 }
 
-QueryWs carve(void* ws, int64_t n_targets, int32_t k) {
+QueryWs carve(void* ws, int64_t n_targets, int64_t n_queue) {
+    const size_t n = (size_t)std::max<int64_t>(n_targets, 1);
+    const size_t nq = (size_t)std::max<int64_t>(n_queue, 1);
     char* p = (char*)ws;
     QueryWs q;
     q.scores = (int32_t*)p;
-    p += align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(n_targets, 1));
+    p += align_up(sizeof(int32_t) * n);
     q.rounds = (int32_t*)p;
-    p += align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(n_targets, 1));
+    p += align_up(sizeof(int32_t) * n);
+    q.draws = (uint64_t*)p;
+    p += align_up(sizeof(uint64_t) * 8 * nq);
+    q.queue = (uint32_t*)p;
+    p += kAlign;
     q.topk = (TopkState*)p;
     p += align_up(sizeof(TopkState));
     q.hist = (uint32_t*)p;
     p += align_up(sizeof(uint32_t) * kTopkBins);
     q.keys = (uint64_t*)p;
-    (void)k;
     return q;
 }
-
-int32_t profile_stride(int32_t qlen) { return (qlen + 3) & ~3; }
 
 int check_search_args(const hs_db* db, int32_t qlen, const hs_params* p, int32_t k,
                       int32_t n_aln) {
@@ -264,41 +254,80 @@ int set_lds_limit(const void* fn, size_t bytes) {
     return HS_OK;
 }
 
-int launch_score(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_params* p,
-                 hipStream_t st, int32_t* d_scores, int32_t* d_rounds, uint64_t* d_cells) {
-    if (db->n_groups == 0) return HS_OK;
-    const int32_t ps = profile_stride(qlen);
-    const size_t lds = (size_t)kNsym * ps;
-    const int wg = (db->n_groups + 3) / 4;
-    if (d_cells) {
-        int rc = set_lds_limit((const void*)k_score_lanes<true>, lds);
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_score_lanes<true>, dim3(wg), dim3(256), lds, st, db->view(), d_q, qlen,
-                           ps, kparams(p), kmatrix(p), d_scores, d_rounds,
-                           (unsigned long long*)d_cells);
-    } else {
-        int rc = set_lds_limit((const void*)k_score_lanes<false>, lds);
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_score_lanes<false>, dim3(wg), dim3(256), lds, st, db->view(), d_q, qlen,
-                           ps, kparams(p), kmatrix(p), d_scores, d_rounds, nullptr);
+size_t device_lds_limit() {
+    static size_t lim = 0;
+    if (!lim) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            v > 0)
+            lim = (size_t)v;
+        else
+            lim = 64 * 1024;
     }
+    return lim;
+}
+
+int device_cus() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1)
+        return 256;
+    return v;
+}
+
+template <int kCopies, bool kCount>
+int launch_sched(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParams& kp,
+                 const KMatrix& km, int32_t bias, hipStream_t st, const QueryWs& w,
+                 int32_t* d_scores, int32_t* d_rounds, uint64_t* d_cells) {
+    const void* fn = (const void*)k_score_sched<kCopies, kCount>;
+    const size_t lds = sched_lds_bytes(qlen, kCopies);
+    int rc = set_lds_limit(fn, lds);
+    if (rc) return rc;
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds));
+    if (per_cu < 1) return fail(HS_ENOMEM, "scoring kernel does not fit on a compute unit");
+    // every workgroup should get at least a quarter of its slots filled
+    // every wavefront should get at least a quarter of its slots filled
+    const int64_t want = (db->n_targets + kThreads / 4 - 1) / (kThreads / 4);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * device_cus(), want));
+    hipLaunchKernelGGL((k_score_sched<kCopies, kCount>), dim3(grid), dim3(kThreads), lds, st,
+                       (const PairRec*)db->d_recs, (int32_t)db->n_queue, db->d_letters, d_q, qlen,
+                       kp, km, bias, (const uint64_t*)w.draws, w.queue, d_scores, d_rounds,
+                       (unsigned long long*)d_cells);
     HIP_TRY(hipGetLastError());
     return HS_OK;
+}
+
+int launch_score(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_params* p,
+                 hipStream_t st, const QueryWs& w, int32_t* d_scores, int32_t* d_rounds,
+                 uint64_t* d_cells) {
+    if (db->n_targets == 0) return HS_OK;
+    const KParams kp = kparams(p);
+    const KMatrix km = kmatrix(p);
+    const int32_t bias = matrix_bias(km);
+    const int32_t nq = (int32_t)db->n_queue;
+    hipLaunchKernelGGL(k_draws, dim3((nq + 255) / 256), dim3(256), 0, st, (const PairRec*)db->d_recs, nq,
+                       kp.seed, w.draws, w.queue);
+    HIP_TRY(hipGetLastError());
+    const bool four = sched_lds_bytes(qlen, 4) <= device_lds_limit();
+    if (!four && sched_lds_bytes(qlen, 1) > device_lds_limit())
+        return fail(HS_EINVAL, "query too long for the device's LDS");
+    if (d_cells)
+        return four ? launch_sched<4, true>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, d_cells)
+                    : launch_sched<1, true>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, d_cells);
+    return four ? launch_sched<4, false>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, nullptr)
+                : launch_sched<1, false>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, nullptr);
 }
 
 // Queues one search.  All pointers are device pointers.
 int launch_search(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_params* p, int32_t k,
                   int32_t n_aln, hipStream_t st, void* d_ws, DevHit* d_hits, int32_t* d_n_hits,
                   DevAln* d_alns, uint32_t* d_ops, int64_t ops_stride) {
-    const KParams kp = kparams(p);
-    const KMatrix km = kmatrix(p);
-    const int32_t ps = profile_stride(qlen);
-    const size_t lds = (size_t)kNsym * ps;
-    QueryWs w = carve(d_ws, db->n_targets, k);
+    QueryWs w = carve(d_ws, db->n_targets, db->n_queue);
     const int32_t n = (int32_t)db->n_targets;
-
-    int rc0 = launch_score(db, d_q, qlen, p, st, w.scores, w.rounds, nullptr);
-    if (rc0) return rc0;
+    int rc = launch_score(db, d_q, qlen, p, st, w, w.scores, w.rounds, nullptr);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_topk_init, dim3(1), dim3(256), 0, st, w.topk, w.hist, k);
     const int tb = std::max(1, std::min(1024, (n + 255) / 256));
     for (int pass = 0; pass < kTopkPasses; ++pass)
@@ -310,11 +339,13 @@ int launch_search(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_pa
                        d_hits, d_n_hits);
     HIP_TRY(hipGetLastError());
     if (n_aln > 0) {
-        int rc = set_lds_limit((const void*)k_traceback, lds);
+        const KParams kp = kparams(p);
+        const KMatrix km = kmatrix(p);
+        const size_t lds = (size_t)profile_copy_bytes(profile_stride(qlen));
+        rc = set_lds_limit((const void*)k_traceback, lds);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_traceback, dim3((n_aln + 63) / 64), dim3(64), lds, st, db->view(), d_q,
-                           qlen, ps, kp, km, d_hits, d_n_hits, n_aln, (int32_t)db->n_targets,
-                           d_alns, d_ops, ops_stride);
+        hipLaunchKernelGGL(k_traceback, dim3(n_aln), dim3(64), lds, st, db->view(), d_q, qlen, kp, km,
+                           matrix_bias(km), d_hits, d_n_hits, n_aln, d_alns, d_ops, ops_stride);
         HIP_TRY(hipGetLastError());
     }
     return HS_OK;
@@ -362,84 +393,83 @@ int hs_db_load(const char* residues, const int64_t* offsets, int64_t n_targets, 
     if (n_targets > 0 && (!offsets || !residues)) return fail(HS_EINVAL, "NULL residues or offsets");
     hipStream_t st = (hipStream_t)stream;
     std::vector<int32_t> len((size_t)n_targets);
+    std::vector<int64_t> rel((size_t)n_targets);
     for (int64_t i = 0; i < n_targets; ++i) {
         const int64_t L = offsets[i + 1] - offsets[i];
         if (L < 1 || L > HS_MAX_SEQ)
             return fail(HS_EINVAL, "target " + std::to_string(i) + " has length outside [1, HS_MAX_SEQ]");
         len[(size_t)i] = (int32_t)L;
+        rel[(size_t)i] = offsets[i] - offsets[0];
     }
     const int64_t total = n_targets ? offsets[n_targets] - offsets[0] : 0;
-
-    // length bins: longest first, ties by index; groups of 64
+    // hand-out order: longest first, ties by index
     std::vector<int32_t> order((size_t)n_targets);
     for (int64_t i = 0; i < n_targets; ++i) order[(size_t)i] = (int32_t)i;
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return len[(size_t)a] > len[(size_t)b]; });
-    const int32_t n_groups = (int32_t)((n_targets + kLanes - 1) / kLanes);
-    std::vector<int32_t> slot_id((size_t)n_groups * kLanes, -1), slot_len((size_t)n_groups * kLanes, 0);
-    std::vector<int32_t> loc((size_t)n_targets);
-    std::vector<int64_t> gbase((size_t)n_groups + 1, 0);
-    for (int64_t s = 0; s < n_targets; ++s) {
-        slot_id[(size_t)s] = order[(size_t)s];
-        slot_len[(size_t)s] = len[(size_t)order[(size_t)s]];
-        loc[(size_t)order[(size_t)s]] = (int32_t)s;
-    }
-    for (int32_t g = 0; g < n_groups; ++g) {
-        const int64_t maxlen = slot_len[(size_t)g * kLanes];
-        gbase[(size_t)g + 1] = gbase[(size_t)g] + (maxlen + kResPerWord - 1) / kResPerWord * kLanes;
-    }
-    const int64_t n_words = gbase[(size_t)n_groups] + kLanes;   // one spare row for read-ahead
 
     hs_db* db = new hs_db();
     db->n_targets = n_targets;
     db->n_residues = total;
-    db->n_groups = n_groups;
-    db->n_words = n_words;
     int rc = HS_OK;
-    uint8_t* d_res = nullptr;
-    int64_t* d_off = nullptr;
     int32_t* d_err = nullptr;
     auto cleanup = [&](int code) {
-        (void)hipFree(d_res);
-        (void)hipFree(d_off);
         (void)hipFree(d_err);
         if (code != HS_OK) free_db(db);
         return code;
     };
-    if ((rc = dev_alloc(&db->d_words, (size_t)n_words, &db->device_bytes)) ||
-        (rc = dev_alloc(&db->d_group_base, (size_t)n_groups + 1, &db->device_bytes)) ||
-        (rc = dev_alloc(&db->d_slot_id, slot_id.size(), &db->device_bytes)) ||
-        (rc = dev_alloc(&db->d_slot_len, slot_len.size(), &db->device_bytes)) ||
-        (rc = dev_alloc(&db->d_loc, loc.size(), &db->device_bytes)) ||
-        (rc = dev_alloc(&d_res, (size_t)total, nullptr)) ||
-        (rc = dev_alloc(&d_off, (size_t)n_targets + 1, nullptr)) ||
+    // Hand-out order: wavefronts take 64 consecutive positions at a time, so
+    // position 64 b + i holds the target of length rank i * nb + b: every
+    // batch of 64 gets one target of each length stratum, and the longest
+    // targets go out first, one per batch.  Unused positions hold id -1.
+    const int64_t nb = (n_targets + kGrabSize - 1) / kGrabSize;
+    db->n_queue = nb * kGrabSize;
+    std::vector<PairRec> recs((size_t)db->n_queue);
+    for (int64_t b = 0; b < nb; ++b)
+        for (int64_t i = 0; i < kGrabSize; ++i) {
+            const int64_t rank = i * nb + b;
+            PairRec& r = recs[(size_t)(b * kGrabSize + i)];
+            if (rank < n_targets) {
+                const int32_t id = order[(size_t)rank];
+                r.id = id;
+                r.len = len[(size_t)id];
+                r.offset = rel[(size_t)id];
+            } else {
+                r.id = -1;
+                r.len = 0;
+                r.offset = 0;
+            }
+        }
+    if ((rc = dev_alloc(&db->d_letters, (size_t)total + kLetterPad, &db->device_bytes)) ||
+        (rc = dev_alloc(&db->d_offsets, (size_t)n_targets, &db->device_bytes)) ||
+        (rc = dev_alloc(&db->d_lens, (size_t)n_targets, &db->device_bytes)) ||
+        (rc = dev_alloc(&db->d_order, (size_t)n_targets, &db->device_bytes)) ||
+        (rc = dev_alloc(&db->d_recs, recs.size(), &db->device_bytes)) ||
         (rc = dev_alloc(&d_err, 1, nullptr)))
         return cleanup(rc);
     auto h2d = [&](void* dst, const void* src, size_t bytes) {
         return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
     };
-    std::vector<int64_t> rel((size_t)n_targets + 1);
-    for (int64_t i = 0; i <= n_targets; ++i) rel[(size_t)i] = n_targets ? offsets[i] - offsets[0] : 0;
-    if (h2d(db->d_group_base, gbase.data(), gbase.size() * 8) != hipSuccess ||
-        h2d(db->d_slot_id, slot_id.data(), slot_id.size() * 4) != hipSuccess ||
-        h2d(db->d_slot_len, slot_len.data(), slot_len.size() * 4) != hipSuccess ||
-        h2d(db->d_loc, loc.data(), loc.size() * 4) != hipSuccess ||
-        h2d(d_res, residues + (n_targets ? offsets[0] : 0), (size_t)total) != hipSuccess ||
-        h2d(d_off, rel.data(), rel.size() * 8) != hipSuccess ||
+    if (h2d(db->d_letters, residues + (n_targets ? offsets[0] : 0), (size_t)total) != hipSuccess ||
+        h2d(db->d_offsets, rel.data(), rel.size() * 8) != hipSuccess ||
+        h2d(db->d_lens, len.data(), len.size() * 4) != hipSuccess ||
+        h2d(db->d_order, order.data(), order.size() * 4) != hipSuccess ||
+        h2d(db->d_recs, recs.data(), recs.size() * sizeof(PairRec)) != hipSuccess ||
         hipMemsetAsync(d_err, 0, sizeof(int32_t), st) != hipSuccess ||
-        hipMemsetAsync(db->d_words + gbase[(size_t)n_groups], 0, kLanes * 4, st) != hipSuccess ||
+        hipMemsetAsync(db->d_letters + total, kZeroRow, kLetterPad, st) != hipSuccess ||
         hipMemcpyToSymbolAsync(HIP_SYMBOL(c_codes), kCodes.t, 256, 0, hipMemcpyHostToDevice, st) !=
             hipSuccess)
         return cleanup(fail(HS_EDEVICE, "copy to device failed"));
-    if (n_groups > 0) {
-        hipLaunchKernelGGL(k_pack, dim3(n_groups), dim3(256), 0, st, d_res, d_off, db->d_slot_id,
-                           db->d_slot_len, db->d_group_base, db->d_words, d_err);
-        if (hipGetLastError() != hipSuccess) return cleanup(fail(HS_EDEVICE, "pack launch failed"));
+    if (total > 0) {
+        const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_encode, dim3((unsigned)blocks), dim3(256), 0, st, db->d_letters, total,
+                           d_err);
+        if (hipGetLastError() != hipSuccess) return cleanup(fail(HS_EDEVICE, "encode launch failed"));
     }
     int32_t err = 0;
     if (hipMemcpyAsync(&err, d_err, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
-        return cleanup(fail(HS_EDEVICE, "database packing failed"));
+        return cleanup(fail(HS_EDEVICE, "database upload failed"));
     if (err) return cleanup(fail(HS_EINVAL, "database holds a residue outside the alphabet"));
     *out = db;
     return cleanup(HS_OK);
@@ -462,7 +492,7 @@ size_t hs_workspace_bytes(const hs_db* db, int32_t nq, int32_t max_qlen, int32_t
     (void)max_qlen;
     (void)n_aln;
     if (!db || nq < 1) return 0;
-    return (size_t)nq * query_ws_bytes(db->n_targets, k);
+    return (size_t)nq * query_ws_bytes(db->n_targets, db->n_queue, k);
 }
 
 int hs_search_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const hs_params* params,
@@ -546,13 +576,16 @@ int hs_search(const hs_db* db, const char* query, int32_t qlen, const hs_params*
 }
 
 int hs_score_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const hs_params* params,
-                 void* stream, int32_t* d_scores, int32_t* d_rounds, uint64_t* d_cells) {
+                 void* stream, void* d_ws, size_t ws_bytes, int32_t* d_scores, int32_t* d_rounds,
+                 uint64_t* d_cells) {
     if (!db) return fail(HS_EINVAL, "db is NULL");
     if (qlen < 1 || qlen > HS_MAX_QUERY) return fail(HS_EINVAL, "qlen must lie in [1, HS_MAX_QUERY]");
     int rc = check_params(params);
     if (rc) return rc;
-    if (!d_qcodes || !d_scores) return fail(HS_EINVAL, "NULL device pointer");
-    return launch_score(db, d_qcodes, qlen, params, (hipStream_t)stream, d_scores, d_rounds,
+    if (!d_qcodes || !d_scores || !d_ws) return fail(HS_EINVAL, "NULL device pointer");
+    if (ws_bytes < hs_workspace_bytes(db, 1, qlen, 1, 0)) return fail(HS_ENOSPC, "workspace too small");
+    QueryWs w = carve(d_ws, db->n_targets, db->n_queue);
+    return launch_score(db, d_qcodes, qlen, params, (hipStream_t)stream, w, d_scores, d_rounds,
                         d_cells);
 }
 

@@ -1,130 +1,705 @@
 // score_kernels.hpp -- pair scoring: the search-mode heuristic of Fig. 1
-// (Section III.B.3: Rounds = 1 by default, contained shifts only) for every
-// (query, target) pair, one lane per target.
+// (Section III.B.3: contained shifts only) for every (query, target) pair.
+//
+// Work decomposition.  A pair is a chain of steps; step t slides an ss-letter
+// window of the small sequence over an ls-letter window of the large one and
+// keeps the first best of nk = ls - ss + 1 placements (diagonals).  Every
+// wavefront of a persistent workgroup runs on its own: it keeps 64 pairs in
+// flight (one slot per lane; pairs are pulled from a global queue, longest
+// first) and advances them in phases: every phase applies the previous step's
+// winner to each slot, draws the next windows, cuts each step into blocks of
+// 8 consecutive diagonals, counting-sorts the blocks by (orientation, ss) so
+// that the lanes get blocks of equal length, and lets every lane score blocks.
+// The workgroup's wavefronts share only the query profile, so one
+// wavefront's memory waits are covered by the others' arithmetic.
+//
+// Block kernel.  The query profile lives in LDS as biased bytes (B + bias in
+// 0..15), four copies shifted by one column so that every 8-column read is
+// dword aligned.  For a block, one 8-byte read of the profile row of a target
+// letter yields the 8 cells of that letter with 8 consecutive query columns,
+// which belong to the block's 8 diagonals; they are added with one 32-bit add
+// per 4 cells into byte-packed accumulators, widened to 16 bits every 16
+// letters.
+//   * target is small: iterate over the ss window letters of the target; the
+//     8 columns are the 8 diagonals' query letters; no masking.
+//   * target is large: iterate over the ss + 7 target letters the block
+//     touches; letter i meets query columns pS + i - 7 .. pS + i, so the
+//     first and last 7 letters carry cells outside the window: those bytes
+//     are masked with compile-time masks (entry and exit ramps).
 #pragma once
 
 #include "device_common.hpp"
 
 namespace hs {
 
-// Query profile in LDS: prof[r * ps + c] = B[r][query[c]] for target letter
-// r and query position c; columns qlen..ps-1 are zero padding.
-__device__ __forceinline__ void build_profile(int8_t* prof, int32_t ps, const uint8_t* qcodes,
-                                              int32_t qlen, const KMatrix& km) {
-    for (int32_t idx = threadIdx.x; idx < kNsym * ps; idx += blockDim.x) {
-        const int32_t r = idx / ps;
-        const int32_t c = idx - r * ps;
-        prof[idx] = c < qlen ? km.m[r * kNsym + qcodes[c]] : (int8_t)0;
+constexpr int kBlockDiags = 8;
+constexpr int kWaves = 8;            // wavefronts per workgroup
+constexpr int kThreads = kWaves * kLanes;
+constexpr int kItemCap = 512;        // blocks issued per wavefront and phase
+constexpr int kBins = 128;           // (orientation, ss bucket)
+
+// Profile layout: copy s (0..kCopies-1) holds column c of row r at byte
+// s * cpb + r * ps + (c + kPad - s).  With four copies, column c is read from
+// copy (c + kPad) & 3 at a 4-aligned offset; with one copy (queries too long
+// for four copies in LDS) reads are unaligned.  Columns outside [0, qlen) and
+// row kZeroRow are 0.
+__host__ __device__ inline int32_t profile_stride(int32_t qlen) {
+    return (qlen + 2 * kPad + 8 + 7) & ~7;
+}
+__host__ __device__ inline int32_t profile_copy_bytes(int32_t ps) { return kProfRows * ps; }
+
+template <int kCopies>
+__device__ __forceinline__ void build_profile(uint8_t* prof, int32_t ps, const uint8_t* qcodes,
+                                              int32_t qlen, const KMatrix& km, int32_t bias) {
+    const int32_t cpb = profile_copy_bytes(ps);
+    uint32_t* p32 = (uint32_t*)prof;
+    const int32_t nw = kCopies * cpb / 4;
+    for (int32_t w = threadIdx.x; w < nw; w += blockDim.x) {
+        const int32_t byte0 = w * 4;
+        const int32_t s = byte0 / cpb;
+        const int32_t rem = byte0 - s * cpb;
+        const int32_t r = rem / ps;
+        const int32_t x0 = rem - r * ps;
+        uint32_t v = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int32_t c = x0 + b + s - kPad;
+            uint32_t e = 0;
+            if (r < kNsym && c >= 0 && c < qlen) e = (uint32_t)(km.m[r * kNsym + qcodes[c]] + bias);
+            v |= e << (8 * b);
+        }
+        p32[w] = v;
     }
 }
 
-// Best contained shift (PROCEDURE getBestSubsequenceAlignment with
-// start = len(small) - 1, end = len(large) - 1): the ss-letter window of
-// small at every shift k in [0, ls - ss] of the ls-letter window of large;
-// each placement scores the sum of substitution scores over its ss pairs
-// (getVirtualAlignmentScore).  The first shift reaching the maximum wins.
-// The cell (k, j) pairs large[pL + k + j] with small[pS + j]; in the profile
-// the target letter picks the row and the query position the column.
-__device__ __forceinline__ void best_shift_lane(const int8_t* prof, int32_t ps,
-                                                const uint32_t* lane_base, bool target_large,
-                                                int32_t pL, int32_t pS, int32_t ls, int32_t ss,
-                                                int32_t& kbest, int32_t& dbest) {
-    const int32_t nk = ls - ss + 1;
-    dbest = INT32_MIN;
-    kbest = 0;
-    TargetStream ts;
-    for (int32_t k = 0; k < nk; ++k) {
-        int32_t D = 0;
-        const int8_t* col;
-        if (target_large) {
-            ts.seek(lane_base, pL + k);
-            col = prof + pS;
+// Byte-packed accumulators of 8 diagonals: b0 holds bytes 0..3, b1 bytes
+// 4..7 of each profile read; h0..h3 hold the widened 16-bit sums as pairs
+// (h0 = bytes 0 and 2, h1 = 1 and 3, h2 = 4 and 6, h3 = 5 and 7); w[] holds
+// 32-bit totals for windows longer than 4096 letters.
+struct Acc8 {
+    uint32_t b0, b1, h0, h1, h2, h3;
+    uint32_t w[8];
+    __device__ __forceinline__ void zero() {
+        b0 = b1 = h0 = h1 = h2 = h3 = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w[i] = 0;
+    }
+    __device__ __forceinline__ void flush() {
+        h0 += b0 & 0x00FF00FFu;
+        h1 += (b0 >> 8) & 0x00FF00FFu;
+        h2 += b1 & 0x00FF00FFu;
+        h3 += (b1 >> 8) & 0x00FF00FFu;
+        b0 = b1 = 0;
+    }
+    // 16-bit lanes stay below 65536 for 4096 letters (4096 * 15)
+    __device__ __forceinline__ void widen() {
+        w[0] += h0 & 0xFFFFu; w[2] += h0 >> 16;
+        w[1] += h1 & 0xFFFFu; w[3] += h1 >> 16;
+        w[4] += h2 & 0xFFFFu; w[6] += h2 >> 16;
+        w[5] += h3 & 0xFFFFu; w[7] += h3 >> 16;
+        h0 = h1 = h2 = h3 = 0;
+    }
+};
+
+// Per-block read bases: iteration i (0-based from a column e = c + kPad) reads
+// copy (e + i) & 3 at offset e + i - ((e + i) & 3); with i = 4m + v that is
+// base[v] + 4m, base[v] = ((e+v)&3) * cpb + e + v - ((e+v)&3).  With one copy
+// base[v] = e + v.
+template <int kCopies>
+struct Bases {
+    int32_t v0, v1, v2, v3;
+    __device__ __forceinline__ void set(int32_t e, int32_t cpb) {
+        if (kCopies == 4) {
+            const int32_t s0 = e & 3, s1 = (e + 1) & 3, s2 = (e + 2) & 3, s3 = (e + 3) & 3;
+            v0 = s0 * cpb + e - s0;
+            v1 = s1 * cpb + e + 1 - s1;
+            v2 = s2 * cpb + e + 2 - s2;
+            v3 = s3 * cpb + e + 3 - s3;
         } else {
-            ts.seek(lane_base, pS);
-            col = prof + pL + k;
+            v0 = e; v1 = e + 1; v2 = e + 2; v3 = e + 3;
         }
-        for (int32_t j = 0; j < ss; ++j) D += col[(int32_t)ts.next() * ps + j];
-        if (D > dbest) {
-            dbest = D;
-            kbest = k;
+    }
+    __device__ __forceinline__ void advance(int32_t d) { v0 += d; v1 += d; v2 += d; v3 += d; }
+};
+
+template <int kCopies>
+__device__ __forceinline__ uint2 lds8(const uint8_t* prof, int32_t addr) {
+    if (kCopies == 4) {
+        const uint32_t* p = (const uint32_t*)(prof + addr);
+        return make_uint2(p[0], p[1]);
+    }
+    uint2 x;
+    __builtin_memcpy(&x, prof + addr, 8);
+    return x;
+}
+
+__device__ __forceinline__ uint32_t load4(const uint8_t* p) {
+    uint32_t w;
+    __builtin_memcpy(&w, p, 4);
+    return w;
+}
+__device__ __forceinline__ uint4 load16(const uint8_t* p) {
+    uint4 w;
+    __builtin_memcpy(&w, p, 16);
+    return w;
+}
+
+__device__ __forceinline__ uint32_t letter_of(uint32_t w, int v) { return (w >> (8 * v)) & 0xFFu; }
+
+// One letter: the profile row of `r` at 8 columns, optionally masked.
+template <int kCopies, uint32_t kMaskLo = 0xFFFFFFFFu, uint32_t kMaskHi = 0xFFFFFFFFu>
+__device__ __forceinline__ void step_letter(const uint8_t* prof, int32_t ps, int32_t base,
+                                            uint32_t r, Acc8& a) {
+    // rows < 25 and strides < 2^15: a 24-bit multiply-add forms the address
+    const uint2 x = lds8<kCopies>(prof, (int32_t)(__umul24(r, (uint32_t)ps) + (uint32_t)base));
+    if (kMaskLo) a.b0 += x.x & kMaskLo;
+    if (kMaskHi) a.b1 += x.y & kMaskHi;
+}
+
+__device__ __forceinline__ uint32_t pick4(const uint4& w, int32_t i) {
+    return i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w;
+}
+
+// Unmasked run of `count` letters starting at T with read bases B.  Letters
+// come 16 at a time, fetched one chunk ahead; `first` holds letters 0..15 and
+// `tail` the 16 letters from count & ~15 on, both fetched by the caller.
+template <int kCopies>
+__device__ __forceinline__ void run_letters(const uint8_t* prof, int32_t ps, const uint8_t* T,
+                                            int32_t count, uint4 first, uint4 tail,
+                                            Bases<kCopies>& B, Acc8& a, int32_t& since_widen) {
+    const int32_t n16 = count >> 4;
+    uint4 wn = first;
+    for (int32_t q = 0; q < n16; ++q) {
+        const uint4 w = wn;
+        T += 16;
+        wn = load16(T);          // the letter array is padded, so this stays in range
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const uint32_t wm = pick4(w, m);
+            step_letter<kCopies>(prof, ps, B.v0 + 4 * m, letter_of(wm, 0), a);
+            step_letter<kCopies>(prof, ps, B.v1 + 4 * m, letter_of(wm, 1), a);
+            step_letter<kCopies>(prof, ps, B.v2 + 4 * m, letter_of(wm, 2), a);
+            step_letter<kCopies>(prof, ps, B.v3 + 4 * m, letter_of(wm, 3), a);
         }
+        B.advance(16);
+        a.flush();
+        if (++since_widen == 256) {
+            a.widen();
+            since_widen = 0;
+        }
+    }
+    const int32_t n4 = (count >> 2) & 3;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        if (u < n4) {
+            const uint32_t w = pick4(tail, u);
+            step_letter<kCopies>(prof, ps, B.v0, letter_of(w, 0), a);
+            step_letter<kCopies>(prof, ps, B.v1, letter_of(w, 1), a);
+            step_letter<kCopies>(prof, ps, B.v2, letter_of(w, 2), a);
+            step_letter<kCopies>(prof, ps, B.v3, letter_of(w, 3), a);
+            B.advance(4);
+        }
+    }
+    const int32_t rem = count & 3;
+    if (rem) {
+        const uint32_t w = pick4(tail, n4);
+        step_letter<kCopies>(prof, ps, B.v0, letter_of(w, 0), a);
+        step_letter<kCopies>(prof, ps, B.v1, rem > 1 ? letter_of(w, 1) : (uint32_t)kZeroRow, a);
+        step_letter<kCopies>(prof, ps, B.v2, rem > 2 ? letter_of(w, 2) : (uint32_t)kZeroRow, a);
+        B.advance(4);
+    }
+    a.flush();
+}
+
+// Diagonal sums (biased) of byte position b of the block's reads.
+__device__ __forceinline__ void acc_values(const Acc8& a, uint32_t v[8]) {
+    v[0] = a.w[0] + (a.h0 & 0xFFFFu);
+    v[2] = a.w[2] + (a.h0 >> 16);
+    v[1] = a.w[1] + (a.h1 & 0xFFFFu);
+    v[3] = a.w[3] + (a.h1 >> 16);
+    v[4] = a.w[4] + (a.h2 & 0xFFFFu);
+    v[6] = a.w[6] + (a.h2 >> 16);
+    v[5] = a.w[5] + (a.h3 & 0xFFFFu);
+    v[7] = a.w[7] + (a.h3 >> 16);
+}
+
+// Best placement of a block: byte b holds the biased sum of diagonal
+// k0 + b (kAscending) or k0 + 7 - b; only diagonals below nk are real.  The
+// largest sum wins, the smaller diagonal on ties.
+template <bool kAscending>
+__device__ __forceinline__ uint64_t block_best(const uint32_t v[8], int32_t k0, int32_t nk,
+                                               int32_t off) {
+    const int32_t nreal = nk - k0;          // >= 1
+    uint32_t m = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int32_t d = kAscending ? b : 7 - b;
+        const uint32_t x = d < nreal ? v[b] + 1 : 0u;   // +1: a real diagonal beats a padding one
+        m = x > m ? x : m;
+    }
+    int32_t dbest = 7;
+#pragma unroll
+    for (int b = 7; b >= 0; --b) {
+        const int32_t d = kAscending ? b : 7 - b;
+        const uint32_t x = d < nreal ? v[b] + 1 : 0u;
+        dbest = (x == m && d < dbest) ? d : dbest;
+    }
+    return shift_key((int32_t)(m - 1) - off, k0 + dbest);
+}
+
+// Letters of one block, fetched before it is scored: the run of letters that
+// needs no masking starts at `run` and has `count` letters (first 16 and
+// last count % 16 of them preloaded); blocks of a large target also preload
+// their entry and exit ramps.
+struct BlockFetch {
+    const uint8_t* run;
+    int32_t count;
+    uint4 first, tail, ramp_in, ramp_out;
+};
+
+// Target is small: cell (k, j) pairs target letter T[j] (row) with query
+// column pL + k + j.  Byte b of the read at letter j is diagonal k0 + b.
+template <int kCopies>
+__device__ __forceinline__ uint64_t block_target_small(const uint8_t* prof, int32_t ps,
+                                                       int32_t cpb, int32_t bias,
+                                                       const BlockFetch& f, int32_t pL, int32_t k0,
+                                                       int32_t ss, int32_t nk) {
+    Acc8 a;
+    a.zero();
+    Bases<kCopies> B;
+    B.set(pL + k0 + kPad, cpb);
+    int32_t sw = 0;
+    run_letters<kCopies>(prof, ps, f.run, ss, f.first, f.tail, B, a, sw);
+    uint32_t v[8];
+    acc_values(a, v);
+    return block_best<true>(v, k0, nk, bias * ss);
+}
+
+// Target is large: letter i (0 <= i < ss + 7) of the block is target letter
+// T[i], meeting query columns pS + i - 7 + b; byte b belongs to diagonal
+// k0 + 7 - b and is a real cell only if 0 <= i - (7 - b) < ss.
+template <int kCopies>
+__device__ __forceinline__ uint64_t block_target_large(const uint8_t* prof, int32_t ps,
+                                                       int32_t cpb, int32_t bias,
+                                                       const BlockFetch& f, const uint8_t* T,
+                                                       int32_t pS, int32_t k0, int32_t ss,
+                                                       int32_t nk) {
+    uint32_t v[8];
+    if (ss >= 7) {
+        Acc8 a;
+        a.zero();
+        Bases<kCopies> B;
+        const int32_t e = pS - 7 + kPad;
+        // entry ramp: letters 0..6, letter i keeps bytes >= 7 - i
+        {
+            B.set(e, cpb);
+            const uint32_t w0 = f.ramp_in.x, w1 = f.ramp_in.y;
+            step_letter<kCopies, 0u, 0xFF000000u>(prof, ps, B.v0, letter_of(w0, 0), a);
+            step_letter<kCopies, 0u, 0xFFFF0000u>(prof, ps, B.v1, letter_of(w0, 1), a);
+            step_letter<kCopies, 0u, 0xFFFFFF00u>(prof, ps, B.v2, letter_of(w0, 2), a);
+            step_letter<kCopies, 0u, 0xFFFFFFFFu>(prof, ps, B.v3, letter_of(w0, 3), a);
+            step_letter<kCopies, 0xFF000000u, 0xFFFFFFFFu>(prof, ps, B.v0 + 4, letter_of(w1, 0), a);
+            step_letter<kCopies, 0xFFFF0000u, 0xFFFFFFFFu>(prof, ps, B.v1 + 4, letter_of(w1, 1), a);
+            step_letter<kCopies, 0xFFFFFF00u, 0xFFFFFFFFu>(prof, ps, B.v2 + 4, letter_of(w1, 2), a);
+            a.flush();
+        }
+        // middle: letters 7 .. ss - 1, every byte real
+        int32_t sw = 0;
+        B.set(e + 7, cpb);
+        run_letters<kCopies>(prof, ps, f.run, f.count, f.first, f.tail, B, a, sw);
+        // exit ramp: letters ss .. ss + 6; letter ss + u keeps bytes < 7 - u
+        {
+            B.set(e + ss, cpb);
+            const uint32_t w0 = f.ramp_out.x, w1 = f.ramp_out.y;
+            step_letter<kCopies, 0xFFFFFFFFu, 0x00FFFFFFu>(prof, ps, B.v0, letter_of(w0, 0), a);
+            step_letter<kCopies, 0xFFFFFFFFu, 0x0000FFFFu>(prof, ps, B.v1, letter_of(w0, 1), a);
+            step_letter<kCopies, 0xFFFFFFFFu, 0x000000FFu>(prof, ps, B.v2, letter_of(w0, 2), a);
+            step_letter<kCopies, 0xFFFFFFFFu, 0u>(prof, ps, B.v3, letter_of(w0, 3), a);
+            step_letter<kCopies, 0x00FFFFFFu, 0u>(prof, ps, B.v0 + 4, letter_of(w1, 0), a);
+            step_letter<kCopies, 0x0000FFFFu, 0u>(prof, ps, B.v1 + 4, letter_of(w1, 1), a);
+            step_letter<kCopies, 0x000000FFu, 0u>(prof, ps, B.v2 + 4, letter_of(w1, 2), a);
+            a.flush();
+        }
+        acc_values(a, v);
+    } else {
+        // short windows: cell by cell from copy 0 (column c at c + kPad)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) v[b] = 0;
+        for (int32_t j = 0; j < ss; ++j) {
+            const uint8_t* col = prof + pS + j + kPad;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) v[7 - m] += col[(int32_t)T[m + j] * ps];
+        }
+    }
+    return block_best<false>(v, k0, nk, bias * ss);
+}
+
+// LDS slot record read by the block scorers.
+struct SlotInfo {
+    int32_t pL, pS;
+    int32_t ss_tl;      // ss | (target_large << 31)
+    int32_t nk;
+    int64_t tbase;      // offset of the target's first letter
+    uint64_t key;       // best placement of the current step so far
+};
+
+// Issues the letter loads of block k0 of slot `si`.
+__device__ __forceinline__ void fetch_block(const SlotInfo& si, int32_t k0,
+                                            const uint8_t* __restrict__ letters, BlockFetch& f) {
+    const int32_t ss = si.ss_tl & 0x7FFFFFFF;
+    if (si.ss_tl < 0) {
+        const uint8_t* T = letters + si.tbase + si.pL + k0;
+        f.run = T + 7;
+        f.count = ss - 7;
+        if (ss >= 7) {
+            f.ramp_in = load16(T);
+            f.ramp_out = load16(T + ss);
+            f.first = load16(f.run);
+            f.tail = load16(f.run + (f.count & ~15));
+        }
+    } else {
+        f.run = letters + si.tbase + si.pS;
+        f.count = ss;
+        f.first = load16(f.run);
+        f.tail = load16(f.run + (ss & ~15));
     }
 }
 
-// One (query, target) pair: AlignSequences over `rounds` rounds, each an
-// Align run whose score is accumulated on the fly: the sum of the chosen
-// placements' scores, minus the gap cost of each chosen shift, minus the
-// trailing periphery gaps left when one sequence runs out (SCORE).
-__device__ __forceinline__ void score_pair_lane(const KParams& kp, const int8_t* prof,
-                                                int32_t ps, int32_t qlen,
-                                                const uint32_t* lane_base, int32_t tlen,
-                                                uint64_t target_id, int32_t& best,
-                                                int32_t& best_round, uint64_t& cells) {
-    const bool target_large = tlen >= qlen;
-    const int32_t nl = target_large ? tlen : qlen;
-    const int32_t ns = target_large ? qlen : tlen;
-    best = INT32_MIN;
-    best_round = 0;
-    cells = 0;
-    DrawStream ds;
-    for (int32_t r = 0; r < kp.rounds; ++r) {
-        ds.init(kp.seed, target_id, (uint32_t)r);
-        uint32_t lf = ds.get(0), sf = ds.get(1);
-        lf = lf < kp.minfactor ? kp.minfactor : lf;
-        sf = sf < kp.minfactor ? kp.minfactor : sf;
-        const uint32_t LF = (uint32_t)(((uint64_t)kp.lfactor * lf) >> 16);
-        const uint32_t SF = (uint32_t)(((uint64_t)kp.sfactor * sf) >> 16);
-        int32_t pL = 0, pS = 0, t = 0, score = 0;
-        while (pL < nl && pS < ns) {
-            const int32_t ls = window_large(nl - pL, LF);
-            const int32_t ss = window_small(ns - pS, SF, ds.get(2u + (uint32_t)t), ls);
-            int32_t kb, db;
-            best_shift_lane(prof, ps, lane_base, target_large, pL, pS, ls, ss, kb, db);
-            cells += (uint64_t)(ls - ss + 1) * (uint64_t)ss;
-            score += db - shift_penalty(kp, t, kb);
-            pL += kb + ss;
-            pS += ss;
-            ++t;
-        }
-        score -= kp.pgp * ((nl - pL) + (ns - pS));
-        if (score > best) {
-            best = score;
-            best_round = r;
-        }
-    }
+template <int kCopies>
+__device__ __forceinline__ uint64_t score_block(const uint8_t* prof, int32_t ps, int32_t cpb,
+                                                int32_t bias, const SlotInfo& si, int32_t k0,
+                                                const BlockFetch& f) {
+    const int32_t ss = si.ss_tl & 0x7FFFFFFF;
+    if (si.ss_tl < 0)
+        return block_target_large<kCopies>(prof, ps, cpb, bias, f, f.run - 7, si.pS, k0, ss, si.nk);
+    return block_target_small<kCopies>(prof, ps, cpb, bias, f, si.pL, k0, ss, si.nk);
 }
 
-// One wavefront per group of 64 targets, four groups per workgroup sharing
-// one LDS profile.  Writes the pair score and winning round by target index;
-// with kCount it also adds the residue pairs scored on diagonals (the work
-// measure of Section III.B.4) to *cells_total.
+// A target as handed out by the queue (stored in hand-out order).
+struct PairRec {
+    int32_t id, len;
+    int64_t offset;
+};
+
+// One pair's progress, held in the registers of the slot's lane.
+struct PairState {
+    int32_t id;          // target index, -1 when the slot is empty
+    int32_t qi;          // hand-out position (indexes the precomputed draws)
+    int32_t nl, ns;
+    bool tl;             // target is the large sequence
+    int32_t round, t;
+    uint32_t LF, SF;
+    int32_t pL, pS, score, best, best_round;
+    int32_t ss, blk, nblk;
+    bool stepping;
+    int64_t tbase;
+    uint32_t dw_i, pf_i;  // indices of the cached and the prefetched draw word
+    uint64_t dw, pf;      // Philox words of round 0 (four draws each)
+};
+
+// random() draw d of the pair's current round: round 0's first 32 draws come
+// from the table filled before the search (staged in LDS when the pair is
+// handed out), the rest from Philox directly.
+__device__ __forceinline__ uint32_t pair_draw(PairState& s, const KParams& kp,
+                                              const uint64_t* __restrict__ draws, uint32_t d) {
+    if (s.round == 0 && d < 32) {
+        const uint32_t wi = d >> 2;
+        if (wi != s.dw_i) {
+            if (wi == s.pf_i) {
+                s.dw = s.pf;
+            } else {
+                s.dw = draws[(int64_t)s.qi * 8 + wi];
+            }
+            s.dw_i = wi;
+        }
+        return (uint32_t)(s.dw >> (16 * (d & 3))) & 0xFFFFu;
+    }
+    uint64_t w[4];
+    philox_block(kp.seed, (uint64_t)s.id, (uint32_t)s.round, d >> 4, w);
+    const uint32_t wi = (d >> 2) & 3;
+    const uint64_t x = wi == 0 ? w[0] : wi == 1 ? w[1] : wi == 2 ? w[2] : w[3];
+    return (uint32_t)(x >> (16 * (d & 3))) & 0xFFFFu;
+}
+
+__device__ __forceinline__ void start_round(PairState& s, const KParams& kp,
+                                            const uint64_t* __restrict__ draws) {
+    s.LF = round_factor(kp.lfactor, kp.minfactor, pair_draw(s, kp, draws, 0));
+    s.SF = round_factor(kp.sfactor, kp.minfactor, pair_draw(s, kp, draws, 1));
+    s.pL = s.pS = s.t = s.score = 0;
+}
+
+// Advances the pair until it has a step to score (or finishes).  Finished
+// pairs write their best round's score.
 template <bool kCount>
-__global__ __launch_bounds__(256) void k_score_lanes(DbView db, const uint8_t* __restrict__ qcodes,
-                                                    int32_t qlen, int32_t ps, KParams kp,
-                                                    KMatrix km, int32_t* __restrict__ scores,
-                                                    int32_t* __restrict__ rounds,
-                                                    unsigned long long* cells_total) {
-    extern __shared__ int8_t prof[];
-    build_profile(prof, ps, qcodes, qlen, km);
-    __syncthreads();
-    const int32_t g = blockIdx.x * (blockDim.x / kLanes) + threadIdx.x / kLanes;
+__device__ __forceinline__ void advance_pair(PairState& s, const KParams& kp,
+                                             const uint64_t* __restrict__ draws, SlotInfo* slot,
+                                             int32_t* scores, int32_t* rounds, uint64_t& cells) {
+    while (s.id >= 0 && !s.stepping) {
+        if (s.pL < s.nl && s.pS < s.ns) {
+            const int32_t ls = window_large(s.nl - s.pL, s.LF);
+            const int32_t ss =
+                window_small(s.ns - s.pS, s.SF, pair_draw(s, kp, draws, 2u + (uint32_t)s.t), ls);
+            const int32_t nk = ls - ss + 1;
+            s.ss = ss;
+            s.blk = 0;
+            s.nblk = (nk + kBlockDiags - 1) / kBlockDiags;
+            s.stepping = true;
+            // fetch the word of the next step's draw while this step is scored
+            const uint32_t wn = (3u + (uint32_t)s.t) >> 2;
+            if (s.round == 0 && wn < 8 && wn != s.dw_i && wn != s.pf_i) {
+                s.pf = draws[(int64_t)s.qi * 8 + wn];
+                s.pf_i = wn;
+            }
+            if (kCount) cells += (uint64_t)nk * (uint64_t)ss;
+            SlotInfo si;
+            si.pL = s.pL;
+            si.pS = s.pS;
+            si.ss_tl = ss | (s.tl ? (int32_t)0x80000000 : 0);
+            si.nk = nk;
+            si.tbase = s.tbase;
+            si.key = 0;
+            *slot = si;
+            return;
+        }
+        s.score -= kp.pgp * ((s.nl - s.pL) + (s.ns - s.pS));
+        if (s.score > s.best) {
+            s.best = s.score;
+            s.best_round = s.round;
+        }
+        if (++s.round < kp.rounds) {
+            start_round(s, kp, draws);
+            continue;
+        }
+        scores[s.id] = s.best;
+        if (rounds) rounds[s.id] = s.best_round;
+        s.id = -1;
+    }
+}
+
+// Wavefront-private LDS: slots, issued blocks, bin counters.
+struct WaveLds {
+    SlotInfo slots[kLanes];
+    uint32_t items[kItemCap];
+    uint32_t bins[kBins];
+};
+
+// Queue positions are taken from the global counter 64 at a time per
+// wavefront, so that the counter sees one atomic per 64 pairs.
+constexpr uint32_t kGrab = 64;
+constexpr int64_t kGrabSize = kGrab;
+
+// Bin of a step: orientation, then ss exactly below 32, in steps of 4 up to
+// 95 and of 16 up to 351, so that neighbouring blocks in the sorted order
+// have close ss.
+__device__ __forceinline__ int32_t ss_bin(bool tl, int32_t ss) {
+    int32_t b;
+    if (ss < 32) b = ss;
+    else if (ss < 96) b = 32 + ((ss - 32) >> 2);
+    else b = 48 + ((ss - 96) >> 4);
+    return (tl ? 64 : 0) + (b < 63 ? b : 63);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Inclusive prefix sum across the wavefront.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x, int32_t lane) {
+#pragma unroll
+    for (int o = 1; o < kLanes; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, kLanes);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// Dynamic LDS: [profile copies][kWaves x WaveLds].
+__host__ __device__ inline size_t sched_lds_bytes(int32_t qlen, int copies) {
+    const int32_t ps = profile_stride(qlen);
+    return (size_t)copies * profile_copy_bytes(ps) + sizeof(WaveLds) * kWaves;
+}
+
+template <int kCopies, bool kCount>
+__global__ __launch_bounds__(kThreads) void k_score_sched(
+    const PairRec* __restrict__ recs, int32_t n, const uint8_t* __restrict__ letters,
+    const uint8_t* __restrict__ qcodes, int32_t qlen, KParams kp, KMatrix km, int32_t bias,
+    const uint64_t* __restrict__ draws, uint32_t* queue, int32_t* __restrict__ scores,
+    int32_t* __restrict__ rounds, unsigned long long* cells_total) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const int32_t ps = profile_stride(qlen);
+    const int32_t cpb = profile_copy_bytes(ps);
+    uint8_t* prof = lds;
+    build_profile<kCopies>(prof, ps, qcodes, qlen, km, bias);
+    __syncthreads();   // the only workgroup barrier: wavefronts run independently from here
+
     const int32_t lane = threadIdx.x & (kLanes - 1);
-    if (g >= db.n_groups) return;
-    const int32_t slot = g * kLanes + lane;
-    const int32_t id = db.slot_id[slot];
+    WaveLds& W = ((WaveLds*)(lds + kCopies * cpb))[threadIdx.x / kLanes];
+    PairState s;
+    s.id = -1;
+    s.stepping = false;
+    bool exhausted = false;
+    uint32_t q_next = 0, q_end = 0;   // held range of queue positions (wavefront-uniform)
     uint64_t cells = 0;
-    if (id >= 0) {
-        const int32_t tlen = db.slot_len[slot];
-        const uint32_t* lane_base = db.words + db.group_base[g] + lane;
-        int32_t best, best_round;
-        score_pair_lane(kp, prof, ps, qlen, lane_base, tlen, (uint64_t)id, best, best_round, cells);
-        scores[id] = best;
-        if (rounds) rounds[id] = best_round;
+
+    for (;;) {
+        // ---- phase A: apply last step's winner, advance, refill ----
+        if (s.id >= 0 && s.stepping && s.blk >= s.nblk) {
+            const uint64_t key = W.slots[lane].key;
+            const int32_t kb = key_shift(key);
+            s.score += key_score(key) - shift_penalty(kp, s.t, kb);
+            s.pL += kb + s.ss;
+            s.pS += s.ss;
+            ++s.t;
+            s.stepping = false;
+        }
+        advance_pair<kCount>(s, kp, draws, &W.slots[lane], scores, rounds, cells);
+        {
+            const bool need = s.id < 0 && !exhausted;
+            const uint64_t mask = __ballot(need);
+            if (mask) {
+                const uint32_t cnt = (uint32_t)__popcll(mask);
+                const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1));
+                // from the range already held, then from one new range
+                const uint32_t take1 = cnt < q_end - q_next ? cnt : q_end - q_next;
+                uint32_t qi = q_next + rank;
+                q_next += take1;
+                if (take1 < cnt) {
+                    uint32_t base = 0;
+                    if (lane == 0) base = atomicAdd(queue, kGrab);
+                    base = __shfl(base, 0, kLanes);
+                    if (rank >= take1) qi = base + (rank - take1);
+                    q_next = base + (cnt - take1);
+                    q_end = base + kGrab;
+                }
+                if (need) {
+                    if (qi < (uint32_t)n && recs[qi].id >= 0) {
+                        const PairRec r = recs[qi];
+                        s.dw = draws[(int64_t)qi * 8];
+                        s.dw_i = 0;
+                        s.pf_i = 0xFFFFFFFFu;
+                        s.id = r.id;
+                        s.qi = (int32_t)qi;
+                        s.tl = r.len >= qlen;
+                        s.nl = s.tl ? r.len : qlen;
+                        s.ns = s.tl ? qlen : r.len;
+                        s.tbase = r.offset;
+                        s.round = 0;
+                        s.best = INT32_MIN;
+                        s.best_round = 0;
+                        s.stepping = false;
+                        start_round(s, kp, draws);
+                        advance_pair<kCount>(s, kp, draws, &W.slots[lane], scores, rounds, cells);
+                    } else if (qi >= (uint32_t)n) {
+                        exhausted = true;
+                    }
+                }
+            }
+        }
+        if (__ballot(s.id >= 0) == 0) break;
+
+        // ---- phase B: issue blocks, sorted by (orientation, ss) ----
+        W.bins[lane] = 0;
+        W.bins[lane + kLanes] = 0;
+        wave_sync();
+        const int32_t want = (s.id >= 0 && s.stepping) ? s.nblk - s.blk : 0;
+        const int32_t bkey = ss_bin(s.tl, s.ss);
+        uint32_t off = 0;
+        if (want > 0) off = atomicAdd(&W.bins[bkey], (uint32_t)want);
+        wave_sync();
+        {
+            // exclusive scan over the 128 bins: lane l owns bins 2l, 2l + 1
+            const uint32_t a0 = W.bins[2 * lane], a1 = W.bins[2 * lane + 1];
+            const uint32_t inc = wave_inclusive_scan(a0 + a1, lane);
+            const uint32_t before = inc - (a0 + a1);
+            wave_sync();
+            W.bins[2 * lane] = before;
+            W.bins[2 * lane + 1] = before + a0;
+        }
+        wave_sync();
+        if (want > 0) {
+            const int32_t start = (int32_t)(W.bins[bkey] + off);
+            int32_t issue = kItemCap - start;
+            issue = issue < 0 ? 0 : (issue > want ? want : issue);
+            for (int32_t b = 0; b < issue; ++b)
+                W.items[start + b] = ((uint32_t)lane << 24) | (uint32_t)(s.blk + b);
+            s.blk += issue;
+        }
+        // blocks issued = number of slots' wants, capped
+        uint32_t nw = (uint32_t)(want > 0 ? want : 0);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) nw += __shfl_xor(nw, o, kLanes);
+        const int32_t n_items = (int32_t)(nw < (uint32_t)kItemCap ? nw : (uint32_t)kItemCap);
+        wave_sync();
+
+        // ---- phase C: score the blocks; each lane fetches the letters of its
+        // next block before scoring the current one ----
+        {
+            int32_t i = lane;
+            bool have = i < n_items;
+            SlotInfo si;
+            int32_t sl = 0, k0 = 0;
+            BlockFetch f;
+            if (have) {
+                const uint32_t it = W.items[i];
+                sl = (int32_t)(it >> 24);
+                k0 = (int32_t)(it & 0xFFFFFFu) * kBlockDiags;
+                si = W.slots[sl];
+                fetch_block(si, k0, letters, f);
+            }
+            while (have) {
+                const int32_t in = i + kLanes;
+                const bool have_n = in < n_items;
+                SlotInfo si_n;
+                int32_t sl_n = 0, k0_n = 0;
+                BlockFetch f_n;
+                if (have_n) {
+                    const uint32_t it = W.items[in];
+                    sl_n = (int32_t)(it >> 24);
+                    k0_n = (int32_t)(it & 0xFFFFFFu) * kBlockDiags;
+                    si_n = W.slots[sl_n];
+                    fetch_block(si_n, k0_n, letters, f_n);
+                }
+                const uint64_t key = score_block<kCopies>(prof, ps, cpb, bias, si, k0, f);
+                atomicMax((unsigned long long*)&W.slots[sl].key, (unsigned long long)key);
+                si = si_n;
+                sl = sl_n;
+                k0 = k0_n;
+                f = f_n;
+                i = in;
+                have = have_n;
+            }
+        }
+        wave_sync();
     }
     if (kCount) {
-        for (int off = kLanes / 2; off > 0; off >>= 1) cells += __shfl_xor(cells, off, kLanes);
+        for (int o = kLanes / 2; o > 0; o >>= 1) cells += __shfl_xor(cells, o, kLanes);
         if (lane == 0) atomicAdd(cells_total, (unsigned long long)cells);
     }
+}
+
+// Random draws 0..31 of round 0 for every target in hand-out order (two
+// Philox blocks each), and the queue counter reset: run before the scoring
+// kernel.
+__global__ __launch_bounds__(256) void k_draws(const PairRec* __restrict__ recs, int32_t n,
+                                               uint64_t seed, uint64_t* __restrict__ out,
+                                               uint32_t* queue) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *queue = 0;
+    if (i >= n || recs[i].id < 0) return;
+    const uint64_t id = (uint64_t)recs[i].id;
+    uint64_t w[4];
+    philox_block(seed, id, 0, 0, w);
+    out[(int64_t)i * 8 + 0] = w[0];
+    out[(int64_t)i * 8 + 1] = w[1];
+    out[(int64_t)i * 8 + 2] = w[2];
+    out[(int64_t)i * 8 + 3] = w[3];
+    philox_block(seed, id, 0, 1, w);
+    out[(int64_t)i * 8 + 4] = w[0];
+    out[(int64_t)i * 8 + 5] = w[1];
+    out[(int64_t)i * 8 + 6] = w[2];
+    out[(int64_t)i * 8 + 7] = w[3];
 }
 
 }  // namespace hs

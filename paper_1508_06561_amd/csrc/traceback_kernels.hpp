@@ -42,70 +42,93 @@ struct OpWriter {
     }
 };
 
-// Replays the winning round of hit a (a < min(n_aln, n_hits)) and writes its
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
+    for (int o = kLanes / 2; o > 0; o >>= 1) {
+        const uint64_t y = __shfl_xor(x, o, kLanes);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// One wavefront per alignment a < min(n_aln, n_hits): replays the winning
+// round of the hit, lanes splitting each step's placements, and writes the
 // alignment as ops oriented (query, target).  Inside the chop-and-consume
-// loop only the small sequence receives gaps (Section III.B.3): the k* skipped
-// letters of large are target letters over gaps (D) when the target is large
-// and query letters over gaps (I) otherwise; after the loop the rest of
-// whichever sequence is left goes against gaps.
+// loop only the small sequence receives gaps (Section III.B.3): the k*
+// skipped letters of large are target letters over gaps (D) when the target
+// is large and query letters over gaps (I) otherwise; after the loop the rest
+// of whichever sequence is left goes against gaps.
 __global__ __launch_bounds__(64) void k_traceback(DbView db, const uint8_t* __restrict__ qcodes,
-                                                  int32_t qlen, int32_t ps, KParams kp, KMatrix km,
-                                                  const DevHit* __restrict__ hits,
+                                                  int32_t qlen, KParams kp, KMatrix km,
+                                                  int32_t bias, const DevHit* __restrict__ hits,
                                                   const int32_t* __restrict__ n_hits, int32_t n_aln,
-                                                  int32_t n_targets, DevAln* __restrict__ alns,
+                                                  DevAln* __restrict__ alns,
                                                   uint32_t* __restrict__ ops, int64_t ops_stride) {
-    extern __shared__ int8_t prof[];
-    build_profile(prof, ps, qcodes, qlen, km);
+    extern __shared__ __align__(16) uint8_t prof[];
+    const int32_t ps = profile_stride(qlen);
+    build_profile<1>(prof, ps, qcodes, qlen, km, bias);
     __syncthreads();
-    const int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t nh = *n_hits;
-    if (a >= n_aln || a >= nh) return;
+    const int32_t a = blockIdx.x;
+    const int32_t lane = threadIdx.x;
+    if (a >= n_aln || a >= *n_hits) return;
     const int32_t id = (int32_t)hits[a].target_id;
     const int32_t r = hits[a].round;
-    if (id < 0 || id >= n_targets || r < 0 || r >= kp.rounds) return;   // never for a valid hit
-    const int32_t slot = db.loc[id];
-    const int32_t g = slot / kLanes, lane = slot % kLanes;
-    const int32_t tlen = db.slot_len[slot];
-    const uint32_t* lane_base = db.words + db.group_base[g] + lane;
+    if (id < 0 || id >= db.n || r < 0 || r >= kp.rounds) return;   // never for a valid hit
+    const int32_t tlen = db.lens[id];
+    const uint8_t* T = db.letters + db.offsets[id];
 
-    const bool target_large = tlen >= qlen;
-    const int32_t nl = target_large ? tlen : qlen;
-    const int32_t ns = target_large ? qlen : tlen;
-    const uint32_t gap_in_small = target_large ? kOpD : kOpI;   // large letter over a gap
-    const uint32_t gap_in_large = target_large ? kOpI : kOpD;   // small letter over a gap
+    const bool tl = tlen >= qlen;
+    const int32_t nl = tl ? tlen : qlen;
+    const int32_t ns = tl ? qlen : tlen;
+    const uint32_t gap_in_small = tl ? kOpD : kOpI;   // large letter over a gap
+    const uint32_t gap_in_large = tl ? kOpI : kOpD;   // small letter over a gap
 
     DrawStream ds;
     ds.init(kp.seed, (uint64_t)id, (uint32_t)r);
-    uint32_t lf = ds.get(0), sf = ds.get(1);
-    lf = lf < kp.minfactor ? kp.minfactor : lf;
-    sf = sf < kp.minfactor ? kp.minfactor : sf;
-    const uint32_t LF = (uint32_t)(((uint64_t)kp.lfactor * lf) >> 16);
-    const uint32_t SF = (uint32_t)(((uint64_t)kp.sfactor * sf) >> 16);
+    const uint32_t LF = round_factor(kp.lfactor, kp.minfactor, ds.get(0));
+    const uint32_t SF = round_factor(kp.sfactor, kp.minfactor, ds.get(1));
     OpWriter w;
     w.init(ops + (int64_t)a * ops_stride);
     int32_t pL = 0, pS = 0, t = 0, score = 0;
     while (pL < nl && pS < ns) {
         const int32_t ls = window_large(nl - pL, LF);
         const int32_t ss = window_small(ns - pS, SF, ds.get(2u + (uint32_t)t), ls);
-        int32_t kb, db_;
-        best_shift_lane(prof, ps, lane_base, target_large, pL, pS, ls, ss, kb, db_);
-        score += db_ - shift_penalty(kp, t, kb);
-        w.emit(gap_in_small, kb);
-        w.emit(kOpM, ss);
+        const int32_t nk = ls - ss + 1;
+        uint64_t best = 0;
+        for (int32_t k = lane; k < nk; k += kLanes) {
+            int32_t D = 0;
+            if (tl) {
+                const uint8_t* col = prof + pS + kPad;
+                for (int32_t j = 0; j < ss; ++j) D += col[(int32_t)T[pL + k + j] * ps + j];
+            } else {
+                const uint8_t* col = prof + pL + k + kPad;
+                for (int32_t j = 0; j < ss; ++j) D += col[(int32_t)T[pS + j] * ps + j];
+            }
+            const uint64_t key = shift_key(D - bias * ss, k);
+            best = key > best ? key : best;
+        }
+        best = wave_max_u64(best);
+        const int32_t kb = key_shift(best);
+        score += key_score(best) - shift_penalty(kp, t, kb);
+        if (lane == 0) {
+            w.emit(gap_in_small, kb);
+            w.emit(kOpM, ss);
+        }
         pL += kb + ss;
         pS += ss;
         ++t;
     }
     score -= kp.pgp * ((nl - pL) + (ns - pS));
-    w.emit(gap_in_small, nl - pL);
-    w.emit(gap_in_large, ns - pS);
-    w.flush();
-    DevAln out;
-    out.target_id = id;
-    out.score = score;
-    out.n_ops = w.n;
-    out.ops_off = (int64_t)a * ops_stride;
-    alns[a] = out;
+    if (lane == 0) {
+        w.emit(gap_in_small, nl - pL);
+        w.emit(gap_in_large, ns - pS);
+        w.flush();
+        DevAln out;
+        out.target_id = id;
+        out.score = score;
+        out.n_ops = w.n;
+        out.ops_off = (int64_t)a * ops_stride;
+        alns[a] = out;
+    }
 }
 
 }  // namespace hs

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libhs.so")
 HS_OK, HS_EINVAL, HS_ENOMEM, HS_ENOSPC, HS_EDEVICE = 0, -1, -2, -3, -4
 OP_M, OP_I, OP_D = 0, 1, 2
 MAX_K = 4096
-MAX_QUERY = 6000
+MAX_QUERY = 5600
 ALPHABET = "ARNDCQEGHILKMFPSTWYVBZX*"
 
 
@@ -80,7 +80,8 @@ def lib():
         L.hs_search_dev.argtypes = [vp, vp, ctypes.c_int32, P(_CParams), ctypes.c_int32,
                                     ctypes.c_int32, vp, vp, ctypes.c_size_t, vp, vp, vp, vp,
                                     ctypes.c_int64]
-        L.hs_score_dev.argtypes = [vp, vp, ctypes.c_int32, P(_CParams), vp, vp, vp, vp]
+        L.hs_score_dev.argtypes = [vp, vp, ctypes.c_int32, P(_CParams), vp, vp, ctypes.c_size_t,
+                                   vp, vp, vp]
         L.hs_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -215,14 +216,15 @@ class Database:
                                    d_ops.data_ptr() if d_ops is not None else None, ops_stride))
 
 
-    def score_dev(self, d_qcodes, qlen, params, d_scores, d_rounds=None, d_cells=None,
+    def score_dev(self, d_qcodes, qlen, params, d_ws, d_scores, d_rounds=None, d_cells=None,
                   stream=None):
         """Queues hs_score_dev: every target's pair score into d_scores (int32
         torch CUDA tensor of n_targets), winning rounds into d_rounds, and
         the scored residue pairs added to d_cells (one int64)."""
         p = params.c()
         _check(lib().hs_score_dev(self._h, d_qcodes.data_ptr(), qlen, ctypes.byref(p),
-                                  _stream(stream), d_scores.data_ptr(),
+                                  _stream(stream), d_ws.data_ptr(),
+                                  d_ws.numel() * d_ws.element_size(), d_scores.data_ptr(),
                                   d_rounds.data_ptr() if d_rounds is not None else None,
                                   d_cells.data_ptr() if d_cells is not None else None))
 
@@ -234,7 +236,8 @@ class Database:
         out = torch.empty(max(self.n_targets, 1), dtype=torch.int32, device="cuda")
         rounds = torch.empty(max(self.n_targets, 1), dtype=torch.int32, device="cuda")
         cells = torch.zeros(1, dtype=torch.int64, device="cuda")
-        self.score_dev(codes, len(codes), params or Params(), out, rounds, cells)
+        ws = torch.empty(self.workspace_bytes(1, len(codes), 1, 0), dtype=torch.uint8, device="cuda")
+        self.score_dev(codes, len(codes), params or Params(), ws, out, rounds, cells)
         return (out.cpu().numpy()[:self.n_targets], rounds.cpu().numpy()[:self.n_targets],
                 int(cells.cpu()[0]))
 

@@ -67,19 +67,19 @@ def test_argument_errors_before_device_use():
     assert rc == H.hs.HS_EINVAL and b"db" in L.hs_last_error()
     bad = H.Params(gop=-1).c()
     rc = L.hs_score_dev(ctypes.c_void_p(1), ctypes.c_void_p(1), 3, ctypes.byref(bad), None,
-                        ctypes.c_void_p(1), None, None)
+                        ctypes.c_void_p(1), 1 << 30, ctypes.c_void_p(1), None, None)
     assert rc == H.hs.HS_EINVAL
     bad = H.Params(lfactor_q16=70000).c()
     rc = L.hs_score_dev(ctypes.c_void_p(1), ctypes.c_void_p(1), 3, ctypes.byref(bad), None,
-                        ctypes.c_void_p(1), None, None)
+                        ctypes.c_void_p(1), 1 << 30, ctypes.c_void_p(1), None, None)
     assert rc == H.hs.HS_EINVAL
     wide = np.zeros((24, 24), np.int8)
     wide[0, 0] = 20
     bad = H.Params(matrix=wide)
     rc = L.hs_score_dev(ctypes.c_void_p(1), ctypes.c_void_p(1), 3, ctypes.byref(bad.c()), None,
-                        ctypes.c_void_p(1), None, None)
+                        ctypes.c_void_p(1), 1 << 30, ctypes.c_void_p(1), None, None)
     assert rc == H.hs.HS_EINVAL
     rc = L.hs_score_dev(ctypes.c_void_p(1), ctypes.c_void_p(1), 0, ctypes.byref(p), None,
-                        ctypes.c_void_p(1), None, None)
+                        ctypes.c_void_p(1), 1 << 30, ctypes.c_void_p(1), None, None)
     assert rc == H.hs.HS_EINVAL
     assert L.hs_workspace_bytes(None, 1, 10, 10, 1) == 0

@@ -251,7 +251,7 @@ def test_errors():
         with pytest.raises(Hm.HSError):
             db.search(b"ACD", Hm.Params(), k=0, n_aln=0)
         with pytest.raises(Hm.HSError):
-            db.search(b"A" * 6001, Hm.Params(), k=3, n_aln=1)
+            db.search(b"A" * 5601, Hm.Params(), k=3, n_aln=1)
         # ops buffer too small: reported, nothing written
         import ctypes
         L = Hm.lib()
