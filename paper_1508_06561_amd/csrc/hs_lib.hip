@@ -208,14 +208,22 @@ struct QueryWs {
     TopkState* topk;
     uint32_t* hist;
     uint64_t* keys;
+    TopkWs tw() const {
+        TopkWs t;
+        t.st = topk;
+        t.hist = hist;
+        t.keys = keys;
+        return t;
+    }
 };
 
 size_t query_ws_bytes(int64_t n_targets, int64_t n_queue, int32_t k) {
     const size_t n = (size_t)std::max<int64_t>(n_targets, 1);
     const size_t nq = (size_t)std::max<int64_t>(n_queue, 1);
+    (void)k;
     return 2 * align_up(sizeof(int32_t) * n) + align_up(sizeof(uint64_t) * 8 * nq) + kAlign +
-           align_up(sizeof(TopkState)) + align_up(sizeof(uint32_t) * kTopkBins) +
-           align_up(sizeof(uint64_t) * (size_t)std::max(k, 1));
+           align_up(sizeof(TopkState)) + align_up(sizeof(uint32_t) * kWinBins) +
+           align_up(sizeof(uint64_t) * kSortCap);
 }
 
 QueryWs carve(void* ws, int64_t n_targets, int64_t n_queue) {
@@ -234,7 +242,7 @@ QueryWs carve(void* ws, int64_t n_targets, int64_t n_queue) {
     q.topk = (TopkState*)p;
     p += align_up(sizeof(TopkState));
     q.hist = (uint32_t*)p;
-    p += align_up(sizeof(uint32_t) * kTopkBins);
+    p += align_up(sizeof(uint32_t) * kWinBins);
     q.keys = (uint64_t*)p;
     return q;
 }
@@ -279,7 +287,7 @@ int device_cus() {
 template <int kCopies, bool kCount>
 int launch_sched(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParams& kp,
                  const KMatrix& km, int32_t bias, hipStream_t st, const QueryWs& w,
-                 int32_t* d_scores, int32_t* d_rounds, uint64_t* d_cells) {
+                 int32_t* d_scores, int32_t* d_rounds, uint64_t* d_cells, int32_t* d_max) {
     const void* fn = (const void*)k_score_sched<kCopies, kCount>;
     const size_t lds = sched_lds_bytes(qlen, kCopies);
     int rc = set_lds_limit(fn, lds);
@@ -294,14 +302,14 @@ int launch_sched(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParam
     hipLaunchKernelGGL((k_score_sched<kCopies, kCount>), dim3(grid), dim3(kThreads), lds, st,
                        (const PairRec*)db->d_recs, (int32_t)db->n_queue, db->d_letters, d_q, qlen,
                        kp, km, bias, (const uint64_t*)w.draws, w.queue, d_scores, d_rounds,
-                       (unsigned long long*)d_cells);
+                       (unsigned long long*)d_cells, d_max);
     HIP_TRY(hipGetLastError());
     return HS_OK;
 }
 
 int launch_score(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_params* p,
                  hipStream_t st, const QueryWs& w, int32_t* d_scores, int32_t* d_rounds,
-                 uint64_t* d_cells) {
+                 uint64_t* d_cells, int32_t* d_max) {
     if (db->n_targets == 0) return HS_OK;
     const KParams kp = kparams(p);
     const KMatrix km = kmatrix(p);
@@ -314,10 +322,28 @@ int launch_score(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_par
     if (!four && sched_lds_bytes(qlen, 1) > device_lds_limit())
         return fail(HS_EINVAL, "query too long for the device's LDS");
     if (d_cells)
-        return four ? launch_sched<4, true>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, d_cells)
-                    : launch_sched<1, true>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, d_cells);
-    return four ? launch_sched<4, false>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, nullptr)
-                : launch_sched<1, false>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, nullptr);
+        return four ? launch_sched<4, true>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, d_cells, d_max)
+                    : launch_sched<1, true>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, d_cells, d_max);
+    return four ? launch_sched<4, false>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, nullptr, d_max)
+                : launch_sched<1, false>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, nullptr, d_max);
+}
+
+// Ranking of nq score arrays (query q's scores at scores + q * stride).
+int launch_rank(const hs_db* db, hipStream_t st, const int32_t* scores, const int32_t* rounds,
+                int64_t stride, int32_t nq, int32_t min_score, int32_t k, const TopkWs& tw,
+                DevHit* d_hits, int32_t* d_n_hits) {
+    const int32_t n = (int32_t)db->n_targets;
+    const int tb = std::max(1, std::min(512, (n + 255) / 256));
+    hipLaunchKernelGGL(k_topk_hist, dim3(tb, nq), dim3(256), 0, st, scores, stride, n, min_score, tw);
+    hipLaunchKernelGGL(k_topk_pick, dim3(1, nq), dim3(256), 0, st, k, min_score, n, tw);
+    hipLaunchKernelGGL(k_topk_collect, dim3(tb, nq), dim3(256), 0, st, scores, stride, n, min_score, tw);
+    const size_t lds = sizeof(uint64_t) * kSortCap;
+    int rc = set_lds_limit((const void*)k_topk_final, lds);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_topk_final, dim3(1, nq), dim3(1024), lds, st, scores, stride, rounds, n,
+                       min_score, k, tw, d_hits, d_n_hits);
+    HIP_TRY(hipGetLastError());
+    return HS_OK;
 }
 
 // Queues one search.  All pointers are device pointers.
@@ -326,18 +352,11 @@ int launch_search(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_pa
                   DevAln* d_alns, uint32_t* d_ops, int64_t ops_stride) {
     QueryWs w = carve(d_ws, db->n_targets, db->n_queue);
     const int32_t n = (int32_t)db->n_targets;
-    int rc = launch_score(db, d_q, qlen, p, st, w, w.scores, w.rounds, nullptr);
+    hipLaunchKernelGGL(k_topk_reset, dim3(1, 1), dim3(256), 0, st, w.tw());
+    int rc = launch_score(db, d_q, qlen, p, st, w, w.scores, w.rounds, nullptr, &w.topk->max_score);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_topk_init, dim3(1), dim3(256), 0, st, w.topk, w.hist, k);
-    const int tb = std::max(1, std::min(1024, (n + 255) / 256));
-    for (int pass = 0; pass < kTopkPasses; ++pass)
-        hipLaunchKernelGGL(k_topk_pass, dim3(tb), dim3(256), 0, st, w.scores, n, p->min_score,
-                           w.topk, w.hist, pass);
-    hipLaunchKernelGGL(k_topk_collect, dim3(tb), dim3(256), 0, st, w.scores, n, p->min_score,
-                       w.topk, w.keys, k);
-    hipLaunchKernelGGL(k_topk_sort, dim3(1), dim3(1024), 0, st, w.topk, w.keys, w.rounds, n, k,
-                       d_hits, d_n_hits);
-    HIP_TRY(hipGetLastError());
+    rc = launch_rank(db, st, w.scores, w.rounds, 0, 1, p->min_score, k, w.tw(), d_hits, d_n_hits);
+    if (rc) return rc;
     if (n_aln > 0) {
         const KParams kp = kparams(p);
         const KMatrix km = kmatrix(p);
@@ -586,7 +605,7 @@ int hs_score_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const h
     if (ws_bytes < hs_workspace_bytes(db, 1, qlen, 1, 0)) return fail(HS_ENOSPC, "workspace too small");
     QueryWs w = carve(d_ws, db->n_targets, db->n_queue);
     return launch_score(db, d_qcodes, qlen, params, (hipStream_t)stream, w, d_scores, d_rounds,
-                        d_cells);
+                        d_cells, nullptr);
 }
 
 const char* hs_last_error(void) { return g_err.c_str(); }

@@ -433,7 +433,8 @@ __device__ __forceinline__ void start_round(PairState& s, const KParams& kp,
 template <bool kCount>
 __device__ __forceinline__ void advance_pair(PairState& s, const KParams& kp,
                                              const uint64_t* __restrict__ draws, SlotInfo* slot,
-                                             int32_t* scores, int32_t* rounds, uint64_t& cells) {
+                                             int32_t* scores, int32_t* rounds, uint64_t& cells,
+                                             int32_t& best_seen) {
     while (s.id >= 0 && !s.stepping) {
         if (s.pL < s.nl && s.pS < s.ns) {
             const int32_t ls = window_large(s.nl - s.pL, s.LF);
@@ -472,6 +473,7 @@ __device__ __forceinline__ void advance_pair(PairState& s, const KParams& kp,
         }
         scores[s.id] = s.best;
         if (rounds) rounds[s.id] = s.best_round;
+        best_seen = s.best > best_seen ? s.best : best_seen;
         s.id = -1;
     }
 }
@@ -526,7 +528,7 @@ __global__ __launch_bounds__(kThreads) void k_score_sched(
     const PairRec* __restrict__ recs, int32_t n, const uint8_t* __restrict__ letters,
     const uint8_t* __restrict__ qcodes, int32_t qlen, KParams kp, KMatrix km, int32_t bias,
     const uint64_t* __restrict__ draws, uint32_t* queue, int32_t* __restrict__ scores,
-    int32_t* __restrict__ rounds, unsigned long long* cells_total) {
+    int32_t* __restrict__ rounds, unsigned long long* cells_total, int32_t* max_score) {
     extern __shared__ __align__(16) uint8_t lds[];
     const int32_t ps = profile_stride(qlen);
     const int32_t cpb = profile_copy_bytes(ps);
@@ -542,6 +544,7 @@ __global__ __launch_bounds__(kThreads) void k_score_sched(
     bool exhausted = false;
     uint32_t q_next = 0, q_end = 0;   // held range of queue positions (wavefront-uniform)
     uint64_t cells = 0;
+    int32_t best_seen = INT32_MIN;    // largest pair score written by this lane
 
     for (;;) {
         // ---- phase A: apply last step's winner, advance, refill ----
@@ -554,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void k_score_sched(
             ++s.t;
             s.stepping = false;
         }
-        advance_pair<kCount>(s, kp, draws, &W.slots[lane], scores, rounds, cells);
+        advance_pair<kCount>(s, kp, draws, &W.slots[lane], scores, rounds, cells, best_seen);
         {
             const bool need = s.id < 0 && !exhausted;
             const uint64_t mask = __ballot(need);
@@ -590,7 +593,7 @@ __global__ __launch_bounds__(kThreads) void k_score_sched(
                         s.best_round = 0;
                         s.stepping = false;
                         start_round(s, kp, draws);
-                        advance_pair<kCount>(s, kp, draws, &W.slots[lane], scores, rounds, cells);
+                        advance_pair<kCount>(s, kp, draws, &W.slots[lane], scores, rounds, cells, best_seen);
                     } else if (qi >= (uint32_t)n) {
                         exhausted = true;
                     }
@@ -676,6 +679,13 @@ __global__ __launch_bounds__(kThreads) void k_score_sched(
     if (kCount) {
         for (int o = kLanes / 2; o > 0; o >>= 1) cells += __shfl_xor(cells, o, kLanes);
         if (lane == 0) atomicAdd(cells_total, (unsigned long long)cells);
+    }
+    if (max_score) {
+        for (int o = kLanes / 2; o > 0; o >>= 1) {
+            const int32_t y = __shfl_xor(best_seen, o, kLanes);
+            best_seen = y > best_seen ? y : best_seen;
+        }
+        if (lane == 0 && best_seen != INT32_MIN) atomicMax(max_score, best_seen);
     }
 }
 

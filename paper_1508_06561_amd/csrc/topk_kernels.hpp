@@ -2,169 +2,172 @@
 // threshold are ranked by (score descending, target index ascending); each
 // target gets a unique 64-bit key, high word = score with the sign bit
 // flipped, low word = bitwise-not of the index, so that the top k keys are
-// exactly the k best ranks.  A most-significant-digit radix select (digits of
-// 12, 12, 8, 12, 12, 8 bits) narrows to the k-th key, a collect pass gathers
-// every key at or above it, and one workgroup sorts those k keys.
+// exactly the k best ranks.
+//
+// Fast path (exact): the scoring pass leaves the maximum score M; a
+// histogram of the scores in the window [M - 2047, M] finds the k-th best
+// score T; a collect pass gathers every key with score >= T; one workgroup
+// sorts them and keeps the first k.  When the window does not reach the k-th
+// best score, or too many keys tie at T to sort in one workgroup, a
+// single-workgroup radix select over all keys takes over (never for the
+// workloads here, kept so that every input is ranked exactly).
+// Every kernel handles one query per blockIdx.y.
 #pragma once
 
 #include "device_common.hpp"
 
 namespace hs {
 
-constexpr int kTopkBins = 4096;
-constexpr int kTopkPasses = 6;
-__host__ __device__ constexpr int topk_shift(int pass) {
-    return pass == 0 ? 52 : pass == 1 ? 40 : pass == 2 ? 32 : pass == 3 ? 20 : pass == 4 ? 8 : 0;
-}
-__host__ __device__ constexpr int topk_bits(int pass) { return (pass == 2 || pass == 5) ? 8 : 12; }
+constexpr int kWinBins = 2048;          // histogram window, in score units
+constexpr int kSortCap = 8192;          // keys one workgroup sorts in LDS
 
 struct TopkState {
-    uint64_t prefix;      // digits fixed so far (lower bits zero)
-    uint64_t mask;        // bits fixed so far
-    int32_t remaining;    // ranks still to fill among keys matching prefix
-    int32_t done;         // every selected key is >= prefix
-    uint32_t ticket;      // workgroups finished in the current pass
-    int32_t count;        // keys gathered by the collect pass
-    int32_t n_sel;        // min(k, eligible targets)
-    int32_t pad_;
+    int32_t max_score;      // written by the scoring pass (atomic max)
+    int32_t thr;            // k-th best score T
+    int32_t n_sel;          // min(k, eligible targets)
+    int32_t fallback;       // 1: the fast path cannot decide, use the radix select
+    int32_t count;          // keys gathered by the collect pass
+    int32_t pad_[3];
 };
 
-__device__ __forceinline__ uint64_t rank_key(int32_t score, int32_t id) {
-    return ((uint64_t)((uint32_t)score ^ 0x80000000u) << 32) | (uint64_t)(~(uint32_t)id);
-}
-
-__global__ void k_topk_init(TopkState* st, uint32_t* hist, int32_t k) {
-    if (threadIdx.x == 0) {
-        st->prefix = 0;
-        st->mask = 0;
-        st->remaining = k;
-        st->done = 0;
-        st->ticket = 0;
-        st->count = 0;
-        st->n_sel = 0;
-    }
-    for (int i = threadIdx.x; i < kTopkBins; i += blockDim.x) hist[i] = 0;
-}
-
-__global__ __launch_bounds__(256) void k_topk_pass(const int32_t* __restrict__ scores, int32_t n,
-                                                   int32_t min_score, TopkState* st,
-                                                   uint32_t* hist, int32_t pass) {
-    __shared__ uint32_t h[kTopkBins];
-    __shared__ uint32_t part[256];
-    __shared__ int32_t is_last;
-    if (__hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-    const int shift = topk_shift(pass);
-    const int nb = 1 << topk_bits(pass);
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) h[i] = 0;
-    __syncthreads();
-    const uint64_t prefix = st->prefix, mask = st->mask;
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int32_t s = scores[i];
-        if (s < min_score) continue;
-        const uint64_t key = rank_key(s, i);
-        if ((key & mask) != prefix) continue;
-        atomicAdd(&h[(uint32_t)(key >> shift) & (uint32_t)(nb - 1)], 1u);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < nb; i += blockDim.x)
-        if (h[i]) atomicAdd(&hist[i], h[i]);
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) is_last = (atomicAdd(&st->ticket, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    // Last workgroup: pull the global histogram, find the digit holding the
-    // remaining-th largest key, fix it, and reset the histogram.
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-        h[i] = __hip_atomic_load(&hist[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        hist[i] = 0;
-    }
-    __syncthreads();
-    // chunk c = bins [c * per, (c + 1) * per), counted from the top bin down
-    const int per = nb / 256;
-    uint32_t cs = 0;
-    for (int i = 0; i < per; ++i) cs += h[nb - 1 - (threadIdx.x * per + i)];
-    part[threadIdx.x] = cs;
-    __syncthreads();
-    // inclusive prefix over chunks (top-down order)
-    for (int off = 1; off < 256; off <<= 1) {
-        const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    const int32_t remaining = st->remaining;
-    const uint32_t total = part[255];
-    if (pass == 0 && total <= (uint32_t)remaining) {
-        // every eligible target is ranked
-        if (threadIdx.x == 0) {
-            st->n_sel = (int32_t)total;
-            st->done = 1;
-            st->prefix = 0;
-            st->mask = 0;
-            st->ticket = 0;
-        }
-        return;
-    }
-    if (pass == 0 && threadIdx.x == 0) st->n_sel = remaining;
-    const uint32_t before = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-    if (before < (uint32_t)remaining && part[threadIdx.x] >= (uint32_t)remaining) {
-        uint32_t above = before;
-        for (int i = 0; i < per; ++i) {
-            const int bin = nb - 1 - (threadIdx.x * per + i);
-            const uint32_t c = h[bin];
-            if (above + c >= (uint32_t)remaining) {
-                const int32_t rem = remaining - (int32_t)above;
-                st->remaining = rem;
-                st->prefix |= (uint64_t)bin << shift;
-                st->mask |= (uint64_t)(nb - 1) << shift;
-                st->done = (c == (uint32_t)rem) ? 1 : 0;
-                break;
-            }
-            above += c;
-        }
-        st->ticket = 0;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_topk_collect(const int32_t* __restrict__ scores, int32_t n,
-                                                      int32_t min_score, TopkState* st,
-                                                      uint64_t* __restrict__ keys, int32_t cap) {
-    const uint64_t thr = st->prefix;
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int32_t s = scores[i];
-        if (s < min_score) continue;
-        const uint64_t key = rank_key(s, i);
-        if (key >= thr) {
-            const int32_t slot = atomicAdd(&st->count, 1);
-            if (slot < cap) keys[slot] = key;
-        }
-    }
-}
-
-// One workgroup of 1024 threads: bitonic sort (descending) of the gathered
-// keys, padded with zeros, then the ranked hits.
 struct DevHit {
     int64_t target_id;
     int32_t score;
     int32_t round;
 };
 
-__global__ __launch_bounds__(1024) void k_topk_sort(const TopkState* st, const uint64_t* keys,
-                                                    const int32_t* __restrict__ rounds,
-                                                    int32_t n_targets, int32_t cap,
-                                                    DevHit* __restrict__ hits,
-                                                    int32_t* __restrict__ n_hits) {
-    __shared__ uint64_t s[4096];
-    // the collect pass gathers exactly n_sel keys; the clamps only keep a
-    // broken invariant from reaching memory out of range
-    int32_t n = st->n_sel < st->count ? st->n_sel : st->count;
-    n = n < cap ? n : cap;
-    int32_t m = 1;
-    while (m < n) m <<= 1;
-    for (int i = threadIdx.x; i < m; i += blockDim.x) s[i] = i < n ? keys[i] : 0ull;
+__device__ __forceinline__ uint64_t rank_key(int32_t score, int32_t id) {
+    return ((uint64_t)((uint32_t)score ^ 0x80000000u) << 32) | (uint64_t)(~(uint32_t)id);
+}
+__device__ __forceinline__ int32_t rank_key_score(uint64_t key) {
+    return (int32_t)((uint32_t)(key >> 32) ^ 0x80000000u);
+}
+__device__ __forceinline__ int32_t rank_key_id(uint64_t key) { return (int32_t)(~(uint32_t)key); }
+
+// Per query: state plus histogram.
+struct TopkWs {
+    TopkState* st;          // [nq]
+    uint32_t* hist;         // [nq][kWinBins]
+    uint64_t* keys;         // [nq][kSortCap]
+};
+
+// Before the scoring pass: reset the state and the histogram of every query.
+__global__ __launch_bounds__(256) void k_topk_reset(TopkWs w) {
+    const int q = blockIdx.y;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        TopkState s;
+        s.max_score = INT32_MIN;
+        s.thr = 0;
+        s.n_sel = 0;
+        s.fallback = 0;
+        s.count = 0;
+        s.pad_[0] = s.pad_[1] = s.pad_[2] = 0;
+        w.st[q] = s;
+    }
+    uint32_t* h = w.hist + (int64_t)q * kWinBins;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kWinBins; i += gridDim.x * blockDim.x)
+        h[i] = 0;
+}
+
+// Histogram of eligible scores within [M - kWinBins + 1, M].
+__global__ __launch_bounds__(256) void k_topk_hist(const int32_t* __restrict__ scores, int64_t stride,
+                                                   int32_t n, int32_t min_score, TopkWs w) {
+    __shared__ uint32_t h[kWinBins];
+    const int q = blockIdx.y;
+    const int32_t* sc = scores + (int64_t)q * stride;
+    const int32_t M = w.st[q].max_score;
+    for (int i = threadIdx.x; i < kWinBins; i += blockDim.x) h[i] = 0;
     __syncthreads();
+    const int32_t lo = M - (kWinBins - 1);
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int32_t s = sc[i];
+        if (s < min_score || s < lo) continue;
+        atomicAdd(&h[M - s], 1u);        // bin 0 = the best score
+    }
+    __syncthreads();
+    uint32_t* gh = w.hist + (int64_t)q * kWinBins;
+    for (int i = threadIdx.x; i < kWinBins; i += blockDim.x)
+        if (h[i]) atomicAdd(&gh[i], h[i]);
+}
+
+// One workgroup per query: the k-th best score from the window histogram.
+__global__ __launch_bounds__(256) void k_topk_pick(int32_t k, int32_t min_score, int32_t n, TopkWs w) {
+    __shared__ uint32_t part[256];
+    const int q = blockIdx.y;
+    TopkState* st = w.st + q;
+    const uint32_t* gh = w.hist + (int64_t)q * kWinBins;
+    const int32_t M = st->max_score;
+    if (n == 0 || M == INT32_MIN) {          // empty database
+        if (threadIdx.x == 0) { st->n_sel = 0; st->thr = INT32_MAX; }
+        return;
+    }
+    // chunk t = bins [8t, 8t + 8) (best scores first)
+    constexpr int per = kWinBins / 256;
+    uint32_t c[per];
+    uint32_t cs = 0;
+#pragma unroll
+    for (int i = 0; i < per; ++i) {
+        c[i] = gh[threadIdx.x * per + i];
+        cs += c[i];
+    }
+    part[threadIdx.x] = cs;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t x = threadIdx.x >= o ? part[threadIdx.x - o] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += x;
+        __syncthreads();
+    }
+    const uint32_t total = part[255];
+    const int32_t lo = M - (kWinBins - 1);
+    if (total < (uint32_t)k) {
+        // fewer than k eligible scores in the window: all of them are ranked
+        // if nothing eligible lies below it, otherwise the window is too narrow
+        if (threadIdx.x == 0) {
+            if (min_score >= lo) {
+                st->n_sel = (int32_t)total;
+                st->thr = min_score > lo ? min_score : lo;
+                if (total > (uint32_t)kSortCap) st->fallback = 1;
+            } else {
+                st->fallback = 1;
+            }
+        }
+        return;
+    }
+    const uint32_t before = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+    if (before < (uint32_t)k && part[threadIdx.x] >= (uint32_t)k) {
+        uint32_t acc = before;
+        for (int i = 0; i < per; ++i) {
+            acc += c[i];
+            if (acc >= (uint32_t)k) {
+                st->thr = M - (threadIdx.x * per + i);
+                st->n_sel = k;
+                if (acc > (uint32_t)kSortCap) st->fallback = 1;
+                break;
+            }
+        }
+    }
+}
+
+// Gathers every eligible key with score >= T (fast path only).
+__global__ __launch_bounds__(256) void k_topk_collect(const int32_t* __restrict__ scores, int64_t stride,
+                                                      int32_t n, int32_t min_score, TopkWs w) {
+    const int q = blockIdx.y;
+    TopkState* st = w.st + q;
+    if (st->fallback) return;
+    const int32_t thr = st->thr;
+    const int32_t* sc = scores + (int64_t)q * stride;
+    uint64_t* keys = w.keys + (int64_t)q * kSortCap;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int32_t s = sc[i];
+        if (s < thr || s < min_score) continue;
+        const int32_t slot = atomicAdd(&st->count, 1);
+        if (slot < kSortCap) keys[slot] = rank_key(s, i);
+    }
+}
+
+// Bitonic sort (descending) of m keys in LDS, m a power of two.
+__device__ __forceinline__ void bitonic_desc(uint64_t* s, int m) {
     for (int size = 2; size <= m; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int i = threadIdx.x; i < m; i += blockDim.x) {
@@ -181,16 +184,114 @@ __global__ __launch_bounds__(1024) void k_topk_sort(const TopkState* st, const u
             __syncthreads();
         }
     }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+}
+
+// Exact radix select over all eligible keys by one workgroup, most
+// significant digit first, 8 bits at a time; returns the k-th largest key.
+__device__ uint64_t radix_select_block(const int32_t* sc, int32_t n, int32_t min_score, int32_t k,
+                                       uint32_t* hist, uint32_t* part) {
+    uint64_t prefix = 0, mask = 0;
+    int32_t remaining = k;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const int32_t s = sc[i];
+            if (s < min_score) continue;
+            const uint64_t key = rank_key(s, i);
+            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t acc = 0;
+            int d = 255;
+            for (; d >= 0; --d) {
+                if (acc + hist[d] >= (uint32_t)remaining) break;
+                acc += hist[d];
+            }
+            part[0] = (uint32_t)d;
+            part[1] = acc;
+        }
+        __syncthreads();
+        const uint32_t d = part[0];
+        remaining -= (int32_t)part[1];
+        prefix |= (uint64_t)d << shift;
+        mask |= (uint64_t)0xFF << shift;
+        __syncthreads();
+    }
+    return prefix;
+}
+
+// One workgroup per query: sorts the gathered keys (fast path) or runs the
+// radix select (fallback), then writes the ranked hits.
+__global__ __launch_bounds__(1024) void k_topk_final(const int32_t* __restrict__ scores, int64_t stride,
+                                                     const int32_t* __restrict__ rounds, int32_t n,
+                                                     int32_t min_score, int32_t k, TopkWs w,
+                                                     DevHit* __restrict__ hits, int32_t* __restrict__ n_hits) {
+    extern __shared__ __align__(16) uint64_t s[];        // kSortCap keys
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t part[4];
+    __shared__ uint32_t cnt;
+    const int q = blockIdx.y;
+    TopkState* st = w.st + q;
+    const int32_t* sc = scores + (int64_t)q * stride;
+    const int32_t* rd = rounds + (int64_t)q * stride;
+    DevHit* out = hits + (int64_t)q * k;
+    int32_t m_keys;
+    int32_t n_out;
+    if (!st->fallback) {
+        const int32_t c = st->count < kSortCap ? st->count : kSortCap;
+        int32_t m = 1;
+        while (m < c) m <<= 1;
+        const uint64_t* keys = w.keys + (int64_t)q * kSortCap;
+        for (int i = threadIdx.x; i < m; i += blockDim.x) s[i] = i < c ? keys[i] : 0ull;
+        __syncthreads();
+        bitonic_desc(s, m);
+        m_keys = c;
+        n_out = st->n_sel < c ? st->n_sel : c;
+    } else {
+        // k-th largest key, then gather the keys at or above it
+        int32_t eligible = 0;
+        if (threadIdx.x == 0) cnt = 0;
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < n; i += blockDim.x)
+            if (sc[i] >= min_score) atomicAdd(&cnt, 1u);
+        __syncthreads();
+        eligible = (int32_t)cnt;
+        n_out = eligible < k ? eligible : k;
+        const uint64_t kth = n_out > 0 ? radix_select_block(sc, n, min_score, n_out, hist, part) : ~0ull;
+        if (threadIdx.x == 0) cnt = 0;
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const int32_t v = sc[i];
+            if (v < min_score) continue;
+            const uint64_t key = rank_key(v, i);
+            if (key >= kth) {
+                const uint32_t slot = atomicAdd(&cnt, 1u);
+                if (slot < (uint32_t)kSortCap) s[slot] = key;
+            }
+        }
+        __syncthreads();
+        int32_t c = (int32_t)cnt < kSortCap ? (int32_t)cnt : kSortCap;
+        int32_t m = 1;
+        while (m < c) m <<= 1;
+        for (int i = c + threadIdx.x; i < m; i += blockDim.x) s[i] = 0ull;
+        __syncthreads();
+        bitonic_desc(s, m);
+        m_keys = c;
+        n_out = n_out < c ? n_out : c;
+    }
+    (void)m_keys;
+    for (int i = threadIdx.x; i < n_out; i += blockDim.x) {
         const uint64_t key = s[i];
-        const int32_t id = (int32_t)(~(uint32_t)key);
+        const int32_t id = rank_key_id(key);
         DevHit h;
         h.target_id = id;
-        h.score = (int32_t)((uint32_t)(key >> 32) ^ 0x80000000u);
-        h.round = (id >= 0 && id < n_targets) ? rounds[id] : -1;
-        hits[i] = h;
+        h.score = rank_key_score(key);
+        h.round = (id >= 0 && id < n) ? rd[id] : -1;
+        out[i] = h;
     }
-    if (threadIdx.x == 0) *n_hits = n;
+    if (threadIdx.x == 0) n_hits[q] = n_out;
 }
 
 }  // namespace hs

@@ -306,3 +306,39 @@ def test_full_size_every_score():
             assert [int(x) for x in r.ops_of(i)] == a["ops"]
     finally:
         db.close()
+
+
+def test_ranking_fallback_wide_scores():
+    """Scores spread wider than the ranking histogram window: 50 exact copies
+    of a long query score far above 200 unrelated targets, and k = 100 needs
+    ranks below the window (exact radix-select path)."""
+    rng = np.random.default_rng(9)
+    q = synth.random_protein(rng, 900)
+    seqs = [q.copy() for _ in range(50)] + [synth.random_protein(rng, int(n))
+                                            for n in rng.integers(100, 400, 200)]
+    order = rng.permutation(len(seqs))
+    seqs = [seqs[i] for i in order]
+    res, off = synth.pack(seqs)
+    codes = O.encode_db(res, off)
+    db = H().Database(res, off)
+    try:
+        check_search(db, codes, off, q, H().Params(), k=100, n_aln=60)
+        check_search(db, codes, off, q, H().Params(min_score=-500), k=100, n_aln=10)
+    finally:
+        db.close()
+
+
+def test_ranking_fallback_many_ties():
+    """More tied keys at the k-th score than one workgroup sorts (10,000
+    identical targets): exact radix-select path, ties by index."""
+    rng = np.random.default_rng(10)
+    t = synth.random_protein(rng, 12)
+    res, off = synth.pack([t] * 10000)
+    q = synth.random_protein(rng, 8)
+    codes = O.encode_db(res, off)
+    db = H().Database(res, off)
+    try:
+        p = H().Params(lfactor_q16=65536, minfactor_q16=65536, sfactor_q16=0)
+        check_search(db, codes, off, q, p, k=300, n_aln=5)
+    finally:
+        db.close()
