@@ -5,10 +5,14 @@ pair scoring, device ranking (top 500) and alignments of the top 50.
 Prints one JSON line.  `value` is query*database residues per second with the
 database and the query resident in device memory when timing starts.  The
 roofline object covers the dominant kernel (pair scoring): algorithmic integer
-ops (2 per scored residue pair: one substitution lookup, one add) per launch
-divided by its mean duration, timed with HIP events on its own stream, against
-the chip's int32 vector-ALU peak.  cpu_baseline times the single-threaded
-oracle on a bounded, deterministic sample of the same workload.
+ops (2 per scored residue pair -- one substitution-score fetch, one add) per
+launch divided by its mean duration, timed with HIP events on its own stream.
+The peak is the vector ALU's byte-operation rate, 256 CUs x 64 lanes x 4 bytes
+per 32-bit op x 2.4 GHz = 157.3 TOP/s: the kernel does its adds four bytes to a
+32-bit op, and the same figure in cells (78.6 T/s) is the rate at which LDS
+delivers one score byte per cell at 128 bytes per clock per CU.  cpu_baseline
+times the single-threaded oracle on a bounded, deterministic sample of the
+same workload.
 """
 import argparse
 import hashlib
@@ -20,8 +24,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes, 2.4 GHz -> int32 vector ops per second
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 4 byte lanes per 32-bit op, 2.4 GHz
+ALU_PEAK_TOPS = 256 * 64 * 4 * 2.4e9 / 1e12
 OPS_PER_CELL = 2
 
 
@@ -38,7 +42,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(n_launch_bytes_key="score"):
+def traffic_from_profile():
     """HBM bytes per launch of the scoring kernel from the committed
     rocprofv3 counter summary, or None when the kernel sources changed since
     the counters were taken."""
@@ -81,7 +85,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy this many bytes device-to-device (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the search shards by target range across GPUs "
               "by design, but this build measures the single-GPU kernel (use --gpus 1)",
@@ -158,10 +173,11 @@ def main():
                    "db_residues": w.db_residues, "k": w.k, "n_aln": w.n_aln,
                    "params": "PGP 0, GOP 10, GEP 5, LFactor 0.5, SFactor 1, MinFactor 0.5, "
                              "Rounds 1"},
-        "roofline": {"bound": "alu", "kernel": "k_score_lanes", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": "k_score_sched", "achieved": achieved,
                      "peak": ALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS,
-                     "traffic": traffic_from_profile(), "cells_per_launch": cells,
-                     "kernel_ms": k_ms},
+                     "traffic": traffic_from_profile(), "ops_per_cell": OPS_PER_CELL,
+                     "cells_per_launch": cells, "kernel_ms": k_ms,
+                     "cells_per_s": cells / (k_ms * 1e-3)},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, q, args.cpu_budget)
