@@ -52,6 +52,7 @@ extern "C" {
 #define HS_MAX_SEQ 1000000     /* longest target */
 #define HS_MAX_QUERY 5600      /* longest query: its score profile lives in LDS */
 #define HS_MAX_PENALTY 1000    /* largest GOP, GEP or PGP */
+#define HS_MAX_BATCH 4096      /* most queries in one batch */
 
 /* Parameters of Section III.B.1.  Factors are Q16 fixed point (65536 = 1.0)
  * and lie in [0, 65536]; penalties lie in [0, HS_MAX_PENALTY].
@@ -94,6 +95,7 @@ typedef struct hs_aln {
 } hs_aln;
 
 typedef struct hs_db hs_db;
+typedef struct hs_batch hs_batch;
 
 /* Fills *p with the search setting of Section IV of the paper: PGP 0,
  * GOP 10, GEP 5, LFactor 0.5, SFactor 1, MinFactor 0.5, Rounds 1 (Section
@@ -173,6 +175,105 @@ int hs_search_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const 
 int hs_score_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const hs_params* params,
                  void* stream, void* d_ws, size_t ws_bytes, int32_t* d_scores, int32_t* d_rounds,
                  uint64_t* d_cells);
+
+/* ---------------------------------------------------------------------------
+ * Batches.  The query-against-database comparison of Section II, done for
+ * many queries at once: every (query, target) pair is scored by the same
+ * search-mode heuristic (Fig. 1 with Section III.B.3) and every query is
+ * ranked and aligned exactly as hs_search would, so the results of a batch
+ * are identical, bit for bit, to separate hs_search calls with the same
+ * parameters -- whatever the batch size, query order or schedule.  Scoring
+ * runs as one persistent launch over (query, range of targets) work items,
+ * longest queries first; a workgroup builds one query's score profile in
+ * LDS per item.
+ *
+ * A batch handle (hs_batch) owns one device allocation sized at creation and
+ * reuses it for every batch of queries set on it; it borrows the database,
+ * which must outlive it.  One handle runs one search at a time.
+ * ------------------------------------------------------------------------- */
+
+/* Creates a batch handle for up to max_nq (1..HS_MAX_BATCH) queries of at
+ * most max_qlen (1..HS_MAX_QUERY) letters and max_residues letters in all,
+ * returning k (1..HS_MAX_K) ranks and n_aln (0..k) alignments per query.
+ * Device memory: about max_nq * n_targets * 8 bytes of scores plus
+ * max_nq * n_aln * (2 * max_qlen + 2) * 8 bytes of alignment ops. */
+int hs_batch_create(const hs_db* db, int32_t max_nq, int32_t max_qlen, int64_t max_residues,
+                    int32_t k, int32_t n_aln, hs_batch** out);
+
+/* Releases a batch handle and its device memory.  NULL is allowed. */
+int hs_batch_free(hs_batch* b);
+
+/* Sets the queries of the next searches: query q is the host ASCII letters
+ * residues[offsets[q] .. offsets[q+1]) and uses params[q] (n_params == nq)
+ * or params[0] (n_params == 1).  Encodes and uploads the queries on `stream`
+ * and returns when the upload is complete; the host inputs may be reused
+ * afterwards.  Also lays out the work items under the current schedule. */
+int hs_batch_set(hs_batch* b, int32_t nq, const char* residues, const int64_t* offsets,
+                 const hs_params* params, int32_t n_params, void* stream);
+
+/* Fixes the schedule of the scoring launch (results do not depend on it):
+ *   copies   score-profile copies in LDS, 1 or 4 (4: aligned reads; needs
+ *            more LDS), 0 = 4 whenever it fits
+ *   cap      pairs in flight per wavefront, 1..64, 0 = 64
+ *   chunk    target positions per work item, a multiple of 64, 0 = sized
+ *            so that every workgroup gets about four items
+ * Applies to the current queries at once and to every later hs_batch_set. */
+int hs_batch_schedule(hs_batch* b, int32_t copies, int32_t cap, int32_t chunk, void* stream);
+
+/* The schedule in use, the workgroup count and the number of work items
+ * (any pointer may be NULL). */
+int hs_batch_get_schedule(const hs_batch* b, int32_t* copies, int32_t* cap, int32_t* chunk,
+                          int32_t* grid, int32_t* n_items);
+
+/* Autotuner: times the scoring pass of the current queries under every
+ * candidate schedule (copies x cap in {16, 32, 64} x chunk halvings), `reps`
+ * timed passes each on `stream`, keeps the fastest as the fixed schedule and
+ * reports its mean time in *best_ms (may be NULL).  Synchronizes `stream`. */
+int hs_batch_tune(hs_batch* b, void* stream, int32_t reps, float* best_ms);
+
+/* Queues the whole search of the current queries on `stream` (scoring,
+ * ranking, alignments) and returns.  Only kernel launches are queued, so the
+ * call may be captured into a graph.  hs_batch_run_graph does the same
+ * through a graph captured on its first use after hs_batch_set or
+ * hs_batch_schedule and replayed on `stream` afterwards. */
+int hs_batch_run(hs_batch* b, void* stream);
+int hs_batch_run_graph(hs_batch* b, void* stream);
+
+/* Queues the scoring pass alone (no ranking, no alignments); if d_cells (one
+ * device uint64) is not NULL, the residue pairs scored on diagonals are
+ * added to it, as in hs_score_dev. */
+int hs_batch_score(hs_batch* b, void* stream, uint64_t* d_cells);
+
+/* Results of the last run on the host, after the work queued on `stream`:
+ *   hits    nq * k entries, query q's ranks at hits[q * k], n_hits[q] filled
+ *   alns    nq * n_aln entries, query q's at alns[q * n_aln], n_alns[q]
+ *           filled; ops_off indexes the caller's ops buffer, which receives
+ *           every alignment's ops back to back (HS_ENOSPC if ops_cap is too
+ *           small, with *ops_used set to the size needed; the results stay
+ *           on the device and the call may be repeated)
+ * Synchronizes `stream`. */
+int hs_batch_results(hs_batch* b, void* stream, hs_hit* hits, int32_t* n_hits, hs_aln* alns,
+                     int32_t* n_alns, uint32_t* ops, int64_t ops_cap, int64_t* ops_used);
+
+/* Pair scores of the last run on the host: scores[q * n_targets + i] and,
+ * if rounds is not NULL, the winning rounds likewise.  Synchronizes `stream`. */
+int hs_batch_scores(hs_batch* b, void* stream, int32_t* scores, int32_t* rounds);
+
+/* Device addresses of the batch's outputs, for callers that keep results on
+ * the device: hits [max_nq][k], n_hits [max_nq], alns [max_nq][n_aln] (ops_off
+ * indexes d_ops), d_ops with alignment (q, a) at (q * n_aln + a) * ops_stride,
+ * scores and rounds [max_nq][n_targets].  Any pointer may be NULL.  Valid until
+ * hs_batch_free. */
+int hs_batch_outputs(const hs_batch* b, hs_hit** d_hits, int32_t** d_n_hits, hs_aln** d_alns,
+                     uint32_t** d_ops, int64_t* ops_stride, int32_t** d_scores,
+                     int32_t** d_rounds);
+
+/* One-shot batch search: create, set, run, results, free.  Arguments as in
+ * hs_batch_set and hs_batch_results; query lengths 1..HS_MAX_QUERY. */
+int hs_search_batch(const hs_db* db, int32_t nq, const char* residues, const int64_t* offsets,
+                    const hs_params* params, int32_t n_params, int32_t k, int32_t n_aln,
+                    void* stream, hs_hit* hits, int32_t* n_hits, hs_aln* alns, int32_t* n_alns,
+                    uint32_t* ops, int64_t ops_cap, int64_t* ops_used);
 
 /* Thread-local description of the last failing call on this thread. */
 const char* hs_last_error(void);

@@ -29,6 +29,24 @@ struct KMatrix {
     int8_t m[kNsym * kNsym];
 };
 
+// One query of a batch as the batch kernels read it from device memory.
+struct BatchQuery {
+    KParams kp;
+    int64_t qoff;       // first code of the query in the batch's code array
+    int32_t qlen;
+    int32_t bias;       // makes every entry of the query's matrix a byte in 0..15
+    int32_t table;      // 1: the round-0 draw table was filled with kp.seed
+    int32_t pad_;
+};
+
+// Work item of the batch scoring kernel: hand-out positions [lo, hi) of the
+// database for query q.
+struct BatchItem {
+    int32_t q;
+    uint32_t lo, hi;
+    int32_t pad_;
+};
+
 // Device image of a database: one byte (alphabet code) per residue, targets
 // concatenated in index order, followed by kLetterPad readable bytes.
 // `order` lists target indices longest first: the order in which pairs are

@@ -328,20 +328,22 @@ int launch_score(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_par
                 : launch_sched<1, false>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, nullptr, d_max);
 }
 
-// Ranking of nq score arrays (query q's scores at scores + q * stride).
+// Ranking of nq score arrays (query q's scores at scores + q * stride); the
+// threshold of each query is in its TopkState.
 int launch_rank(const hs_db* db, hipStream_t st, const int32_t* scores, const int32_t* rounds,
-                int64_t stride, int32_t nq, int32_t min_score, int32_t k, const TopkWs& tw,
-                DevHit* d_hits, int32_t* d_n_hits) {
+                int64_t stride, int32_t nq, int32_t k, const TopkWs& tw, DevHit* d_hits,
+                int32_t* d_n_hits) {
     const int32_t n = (int32_t)db->n_targets;
-    const int tb = std::max(1, std::min(512, (n + 255) / 256));
-    hipLaunchKernelGGL(k_topk_hist, dim3(tb, nq), dim3(256), 0, st, scores, stride, n, min_score, tw);
-    hipLaunchKernelGGL(k_topk_pick, dim3(1, nq), dim3(256), 0, st, k, min_score, n, tw);
-    hipLaunchKernelGGL(k_topk_collect, dim3(tb, nq), dim3(256), 0, st, scores, stride, n, min_score, tw);
+    // about 512 workgroups over all queries
+    const int tb = std::max(1, std::min(std::max(1, 512 / nq), (n + 255) / 256));
+    hipLaunchKernelGGL(k_topk_hist, dim3(tb, nq), dim3(256), 0, st, scores, stride, n, tw);
+    hipLaunchKernelGGL(k_topk_pick, dim3(1, nq), dim3(256), 0, st, k, n, tw);
+    hipLaunchKernelGGL(k_topk_collect, dim3(tb, nq), dim3(256), 0, st, scores, stride, n, tw);
     const size_t lds = sizeof(uint64_t) * kSortCap;
     int rc = set_lds_limit((const void*)k_topk_final, lds);
     if (rc) return rc;
     hipLaunchKernelGGL(k_topk_final, dim3(1, nq), dim3(1024), lds, st, scores, stride, rounds, n,
-                       min_score, k, tw, d_hits, d_n_hits);
+                       k, tw, d_hits, d_n_hits);
     HIP_TRY(hipGetLastError());
     return HS_OK;
 }
@@ -351,11 +353,11 @@ int launch_search(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_pa
                   int32_t n_aln, hipStream_t st, void* d_ws, DevHit* d_hits, int32_t* d_n_hits,
                   DevAln* d_alns, uint32_t* d_ops, int64_t ops_stride) {
     QueryWs w = carve(d_ws, db->n_targets, db->n_queue);
-    const int32_t n = (int32_t)db->n_targets;
-    hipLaunchKernelGGL(k_topk_reset, dim3(1, 1), dim3(256), 0, st, w.tw());
+    hipLaunchKernelGGL(k_topk_reset, dim3(1, 1), dim3(256), 0, st, w.tw(), p->min_score,
+                       (const BatchQuery*)nullptr, (uint32_t*)nullptr);
     int rc = launch_score(db, d_q, qlen, p, st, w, w.scores, w.rounds, nullptr, &w.topk->max_score);
     if (rc) return rc;
-    rc = launch_rank(db, st, w.scores, w.rounds, 0, 1, p->min_score, k, w.tw(), d_hits, d_n_hits);
+    rc = launch_rank(db, st, w.scores, w.rounds, 0, 1, k, w.tw(), d_hits, d_n_hits);
     if (rc) return rc;
     if (n_aln > 0) {
         const KParams kp = kparams(p);
@@ -367,6 +369,223 @@ int launch_search(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_pa
                            matrix_bias(km), d_hits, d_n_hits, n_aln, d_alns, d_ops, ops_stride);
         HIP_TRY(hipGetLastError());
     }
+    return HS_OK;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// batches: many queries in one persistent scoring launch
+// --------------------------------------------------------------------------
+struct hs_batch {
+    const hs_db* db = nullptr;
+    int32_t max_nq = 0, max_qlen = 0, k = 0, n_aln = 0;
+    int64_t max_res = 0, ops_stride = 0, max_items = 0;
+    char* d_mem = nullptr;
+    uint8_t* d_qcodes = nullptr;
+    BatchQuery* d_qs = nullptr;
+    KMatrix* d_mats = nullptr;
+    BatchItem* d_items = nullptr;
+    uint32_t* d_ctr = nullptr;
+    int32_t* d_scores = nullptr;        // [max_nq][n_targets]
+    int32_t* d_rounds = nullptr;
+    uint64_t* d_draws = nullptr;        // round-0 draws, 8 words per hand-out position
+    TopkState* d_st = nullptr;
+    uint32_t* d_hist = nullptr;
+    uint64_t* d_keys = nullptr;
+    DevHit* d_hits = nullptr;           // [max_nq][k]
+    int32_t* d_n_hits = nullptr;
+    DevAln* d_alns = nullptr;           // [max_nq][n_aln]
+    uint32_t* d_ops = nullptr;          // [max_nq * n_aln][ops_stride]
+    int64_t* d_pos = nullptr;           // packing offsets, max_nq * n_aln + 1
+    uint32_t* d_packed = nullptr;
+    // queries of the current batch
+    int32_t nq = 0, cur_max_qlen = 0;
+    std::vector<int32_t> qlens;
+    bool table_valid = false;
+    uint64_t table_seed = 0;
+    // schedule: profile copies, pairs in flight per wavefront, positions per item
+    int32_t copies = 0, cap = 0, chunk = 0;
+    int32_t fix_copies = 0, fix_cap = 0, fix_chunk = 0;   // 0: chosen automatically
+    int32_t grid = 0, n_items = 0;
+    // graph of one whole search
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    TopkWs tw() const {
+        TopkWs t;
+        t.st = d_st;
+        t.hist = d_hist;
+        t.keys = d_keys;
+        return t;
+    }
+};
+
+namespace {
+
+constexpr int32_t kMaxChunksPerQuery = 64;
+
+void drop_graph(hs_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+}
+
+void free_batch(hs_batch* b) {
+    if (!b) return;
+    drop_graph(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    (void)hipFree(b->d_mem);
+    delete b;
+}
+
+int64_t round64(int64_t x) { return (x + 63) / 64 * 64; }
+
+// Smallest item size that keeps a query within kMaxChunksPerQuery items.
+int32_t min_chunk(const hs_db* db) {
+    return (int32_t)std::max<int64_t>(64, round64((db->n_queue + kMaxChunksPerQuery - 1) / kMaxChunksPerQuery));
+}
+
+size_t batch_prof_bytes(int32_t qlen, int copies) {
+    return align_up((size_t)copies * profile_copy_bytes(profile_stride(qlen)));
+}
+
+// The batch kernel's LDS for queries up to qlen: profile region, wavefront
+// records and two counters.
+bool copies_fit(int32_t qlen, int copies) {
+    return batch_prof_bytes(qlen, copies) + sizeof(WaveLds) * kWaves + 16 <= device_lds_limit();
+}
+
+template <int kCopies, bool kCount>
+const void* batch_fn() {
+    return (const void*)k_score_batch<kCopies, kCount>;
+}
+
+const void* batch_kernel(int copies, bool count) {
+    if (copies == 4) return count ? batch_fn<4, true>() : batch_fn<4, false>();
+    return count ? batch_fn<1, true>() : batch_fn<1, false>();
+}
+
+size_t batch_lds(const hs_batch* b, int copies) {
+    return batch_prof_bytes(b->cur_max_qlen, copies) + sizeof(WaveLds) * kWaves;
+}
+
+// Work items for the current queries: longest queries first, each cut into
+// ranges of `chunk` hand-out positions.
+int upload_items(hs_batch* b, hipStream_t st) {
+    std::vector<int32_t> order((size_t)b->nq);
+    for (int32_t q = 0; q < b->nq; ++q) order[(size_t)q] = q;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return b->qlens[(size_t)x] > b->qlens[(size_t)y]; });
+    std::vector<BatchItem> items;
+    const int64_t nqueue = b->db->n_queue;
+    for (int32_t q : order)
+        for (int64_t lo = 0; lo < nqueue; lo += b->chunk) {
+            BatchItem it;
+            it.q = q;
+            it.lo = (uint32_t)lo;
+            it.hi = (uint32_t)std::min<int64_t>(lo + b->chunk, nqueue);
+            it.pad_ = 0;
+            items.push_back(it);
+        }
+    if ((int64_t)items.size() > b->max_items) return fail(HS_EINVAL, "too many work items");
+    b->n_items = (int32_t)items.size();
+    if (!items.empty()) {
+        HIP_TRY(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(BatchItem),
+                               hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    const void* fn = batch_kernel(b->copies, false);
+    const size_t lds = batch_lds(b, b->copies);
+    int rc = set_lds_limit(fn, lds);
+    if (!rc) rc = set_lds_limit(batch_kernel(b->copies, true), lds);
+    if (rc) return rc;
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds));
+    if (per_cu < 1) return fail(HS_ENOMEM, "batch scoring kernel does not fit on a compute unit");
+    b->grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * device_cus(), b->n_items));
+    drop_graph(b);
+    return HS_OK;
+}
+
+// Picks the schedule fields not fixed by the caller: four profile copies when
+// they fit, 64 pairs in flight per wavefront, and items small enough that
+// every workgroup gets about four.
+int choose_schedule(hs_batch* b, hipStream_t st) {
+    b->copies = b->fix_copies ? b->fix_copies : (copies_fit(b->cur_max_qlen, 4) ? 4 : 1);
+    if (!copies_fit(b->cur_max_qlen, b->copies))
+        return fail(HS_EINVAL, "profile copies do not fit in LDS for the longest query");
+    b->cap = b->fix_cap ? b->fix_cap : kLanes;
+    if (b->fix_chunk) {
+        b->chunk = std::max(b->fix_chunk, min_chunk(b->db));
+    } else {
+        int per_cu = 0;
+        const void* fn = batch_kernel(b->copies, false);
+        const size_t lds = batch_lds(b, b->copies);
+        int rc = set_lds_limit(fn, lds);
+        if (rc) return rc;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds));
+        const int64_t wgs = (int64_t)std::max(per_cu, 1) * device_cus();
+        const int64_t want = (int64_t)b->nq * b->db->n_queue / (4 * wgs);
+        b->chunk = (int32_t)std::min<int64_t>(round64(std::max<int64_t>(b->db->n_queue, 64)),
+                                              std::max<int64_t>(round64(want), min_chunk(b->db)));
+    }
+    return upload_items(b, st);
+}
+
+template <int kCopies, bool kCount>
+void launch_batch_kernel(const hs_batch* b, hipStream_t st, uint64_t* d_cells) {
+    const hs_db* db = b->db;
+    hipLaunchKernelGGL((k_score_batch<kCopies, kCount>), dim3(b->grid), dim3(kThreads),
+                       batch_lds(b, kCopies), st, (const BatchQuery*)b->d_qs,
+                       (const KMatrix*)b->d_mats, (const uint8_t*)b->d_qcodes,
+                       (const BatchItem*)b->d_items, b->n_items, b->d_ctr,
+                       (int32_t)batch_prof_bytes(b->cur_max_qlen, kCopies), b->cap,
+                       (const PairRec*)db->d_recs, (const uint8_t*)db->d_letters,
+                       (const uint64_t*)b->d_draws, b->d_scores, b->d_rounds,
+                       (int64_t)db->n_targets, &b->d_st->max_score,
+                       (int32_t)(sizeof(TopkState) / sizeof(int32_t)), (unsigned long long*)d_cells);
+}
+
+// Scoring of the current batch: state reset, then the persistent kernel.
+int enqueue_batch_score(const hs_batch* b, hipStream_t st, uint64_t* d_cells) {
+    hipLaunchKernelGGL(k_topk_reset, dim3(8, b->nq), dim3(256), 0, st, b->tw(), 0,
+                       (const BatchQuery*)b->d_qs, b->d_ctr);
+    HIP_TRY(hipGetLastError());
+    if (b->db->n_targets == 0 || b->n_items == 0) return HS_OK;
+    if (b->copies == 4) {
+        if (d_cells) launch_batch_kernel<4, true>(b, st, d_cells);
+        else launch_batch_kernel<4, false>(b, st, nullptr);
+    } else {
+        if (d_cells) launch_batch_kernel<1, true>(b, st, d_cells);
+        else launch_batch_kernel<1, false>(b, st, nullptr);
+    }
+    HIP_TRY(hipGetLastError());
+    return HS_OK;
+}
+
+// The whole search of the current batch: scoring, ranking, alignments.
+// Kernel launches only (no allocation, copy or fill), so it can be captured.
+int enqueue_batch(const hs_batch* b, hipStream_t st) {
+    int rc = enqueue_batch_score(b, st, nullptr);
+    if (rc) return rc;
+    rc = launch_rank(b->db, st, b->d_scores, b->d_rounds, b->db->n_targets, b->nq, b->k, b->tw(),
+                     b->d_hits, b->d_n_hits);
+    if (rc) return rc;
+    if (b->n_aln > 0) {
+        const size_t lds = (size_t)profile_copy_bytes(profile_stride(b->cur_max_qlen));
+        hipLaunchKernelGGL(k_traceback_batch, dim3(b->n_aln, b->nq), dim3(64), lds, st,
+                           b->db->view(), (const BatchQuery*)b->d_qs, (const KMatrix*)b->d_mats,
+                           (const uint8_t*)b->d_qcodes, b->nq, b->k, (const DevHit*)b->d_hits,
+                           (const int32_t*)b->d_n_hits, b->n_aln, b->d_alns, b->d_ops,
+                           b->ops_stride);
+        HIP_TRY(hipGetLastError());
+    }
+    return HS_OK;
+}
+
+int check_batch_ready(const hs_batch* b) {
+    if (!b) return fail(HS_EINVAL, "batch is NULL");
+    if (b->nq < 1) return fail(HS_EINVAL, "no queries set on the batch");
     return HS_OK;
 }
 
@@ -606,6 +825,394 @@ int hs_score_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const h
     QueryWs w = carve(d_ws, db->n_targets, db->n_queue);
     return launch_score(db, d_qcodes, qlen, params, (hipStream_t)stream, w, d_scores, d_rounds,
                         d_cells, nullptr);
+}
+
+int hs_batch_create(const hs_db* db, int32_t max_nq, int32_t max_qlen, int64_t max_residues,
+                    int32_t k, int32_t n_aln, hs_batch** out) {
+    if (!out) return fail(HS_EINVAL, "out is NULL");
+    if (!db) return fail(HS_EINVAL, "db is NULL");
+    if (max_nq < 1 || max_nq > HS_MAX_BATCH) return fail(HS_EINVAL, "max_nq must lie in [1, HS_MAX_BATCH]");
+    if (max_qlen < 1 || max_qlen > HS_MAX_QUERY)
+        return fail(HS_EINVAL, "max_qlen must lie in [1, HS_MAX_QUERY]");
+    if (max_residues < 1 || max_residues > (int64_t)max_nq * max_qlen)
+        return fail(HS_EINVAL, "max_residues must lie in [1, max_nq * max_qlen]");
+    if (k < 1 || k > HS_MAX_K) return fail(HS_EINVAL, "k must lie in [1, HS_MAX_K]");
+    if (n_aln < 0 || n_aln > k) return fail(HS_EINVAL, "n_aln must lie in [0, k]");
+    if (!copies_fit(max_qlen, 1)) return fail(HS_EINVAL, "max_qlen too long for the device's LDS");
+    hs_batch* b = new hs_batch();
+    b->db = db;
+    b->max_nq = max_nq;
+    b->max_qlen = max_qlen;
+    b->max_res = max_residues;
+    b->k = k;
+    b->n_aln = n_aln;
+    b->ops_stride = 2 * (int64_t)max_qlen + 2;
+    const int64_t chunks = (db->n_queue + min_chunk(db) - 1) / min_chunk(db);
+    b->max_items = (int64_t)max_nq * std::max<int64_t>(chunks, 1);
+    const size_t nt = (size_t)std::max<int64_t>(db->n_targets, 1);
+    const size_t nal = (size_t)max_nq * (size_t)std::max(n_aln, 1);
+    // one device allocation, carved below
+    size_t sz[16];
+    int ns = 0;
+    sz[ns++] = align_up((size_t)max_residues);                                // codes
+    sz[ns++] = align_up(sizeof(BatchQuery) * max_nq);
+    sz[ns++] = align_up(sizeof(KMatrix) * max_nq);
+    sz[ns++] = align_up(sizeof(BatchItem) * (size_t)b->max_items);
+    sz[ns++] = kAlign;                                                        // counter
+    sz[ns++] = align_up(sizeof(int32_t) * nt * max_nq);                       // scores
+    sz[ns++] = align_up(sizeof(int32_t) * nt * max_nq);                       // rounds
+    sz[ns++] = align_up(sizeof(uint64_t) * 8 * (size_t)std::max<int64_t>(db->n_queue, 1));
+    sz[ns++] = align_up(sizeof(TopkState) * max_nq);
+    sz[ns++] = align_up(sizeof(uint32_t) * kWinBins * max_nq);
+    sz[ns++] = align_up(sizeof(uint64_t) * kSortCap * max_nq);
+    sz[ns++] = align_up(sizeof(DevHit) * (size_t)k * max_nq);
+    sz[ns++] = align_up(sizeof(int32_t) * max_nq);
+    sz[ns++] = align_up(sizeof(DevAln) * nal);
+    sz[ns++] = align_up(sizeof(uint32_t) * nal * (size_t)b->ops_stride);      // ops
+    sz[ns++] = align_up(sizeof(int64_t) * (nal + 1)) + align_up(sizeof(uint32_t) * nal * (size_t)b->ops_stride);
+    size_t total = 0;
+    for (int i = 0; i < ns; ++i) total += sz[i];
+    if (hipMalloc((void**)&b->d_mem, total) != hipSuccess) {
+        b->d_mem = nullptr;
+        free_batch(b);
+        return fail(HS_ENOMEM, "device allocation of " + std::to_string(total) + " bytes for the batch failed");
+    }
+    char* p = b->d_mem;
+    int i = 0;
+    b->d_qcodes = (uint8_t*)p; p += sz[i++];
+    b->d_qs = (BatchQuery*)p; p += sz[i++];
+    b->d_mats = (KMatrix*)p; p += sz[i++];
+    b->d_items = (BatchItem*)p; p += sz[i++];
+    b->d_ctr = (uint32_t*)p; p += sz[i++];
+    b->d_scores = (int32_t*)p; p += sz[i++];
+    b->d_rounds = (int32_t*)p; p += sz[i++];
+    b->d_draws = (uint64_t*)p; p += sz[i++];
+    b->d_st = (TopkState*)p; p += sz[i++];
+    b->d_hist = (uint32_t*)p; p += sz[i++];
+    b->d_keys = (uint64_t*)p; p += sz[i++];
+    b->d_hits = (DevHit*)p; p += sz[i++];
+    b->d_n_hits = (int32_t*)p; p += sz[i++];
+    b->d_alns = (DevAln*)p; p += sz[i++];
+    b->d_ops = (uint32_t*)p; p += sz[i++];
+    b->d_pos = (int64_t*)p;
+    b->d_packed = (uint32_t*)(p + align_up(sizeof(int64_t) * (nal + 1)));
+    int rc = set_lds_limit((const void*)k_traceback_batch,
+                           (size_t)profile_copy_bytes(profile_stride(max_qlen)));
+    if (rc) {
+        free_batch(b);
+        return rc;
+    }
+    *out = b;
+    return HS_OK;
+}
+
+int hs_batch_free(hs_batch* b) {
+    free_batch(b);
+    return HS_OK;
+}
+
+int hs_batch_set(hs_batch* b, int32_t nq, const char* residues, const int64_t* offsets,
+                 const hs_params* params, int32_t n_params, void* stream) {
+    if (!b) return fail(HS_EINVAL, "batch is NULL");
+    if (nq < 1 || nq > b->max_nq) return fail(HS_EINVAL, "nq must lie in [1, max_nq]");
+    if (!residues || !offsets || !params) return fail(HS_EINVAL, "NULL residues, offsets or params");
+    if (n_params != 1 && n_params != nq) return fail(HS_EINVAL, "n_params must be 1 or nq");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t total = offsets[nq] - offsets[0];
+    if (total < 1 || total > b->max_res) return fail(HS_EINVAL, "total query length must lie in [1, max_residues]");
+    std::vector<int32_t> qlens((size_t)nq);
+    int32_t mx = 0;
+    for (int32_t q = 0; q < nq; ++q) {
+        const int64_t L = offsets[q + 1] - offsets[q];
+        if (L < 1 || L > b->max_qlen)
+            return fail(HS_EINVAL, "query " + std::to_string(q) + " has length outside [1, max_qlen]");
+        qlens[(size_t)q] = (int32_t)L;
+        mx = std::max(mx, (int32_t)L);
+    }
+    for (int32_t i = 0; i < n_params; ++i) {
+        int rc = check_params(params + i);
+        if (rc) return rc;
+    }
+    std::vector<uint8_t> codes((size_t)total);
+    {
+        int rc = hs_encode(residues + offsets[0], total, codes.data());
+        if (rc) return rc;
+    }
+    const uint64_t seed0 = params[0].seed;
+    const bool new_table = !b->table_valid || b->table_seed != seed0;
+    std::vector<BatchQuery> qs((size_t)nq);
+    std::vector<KMatrix> mats((size_t)nq);
+    for (int32_t q = 0; q < nq; ++q) {
+        const hs_params* p = params + (n_params == 1 ? 0 : q);
+        BatchQuery& Q = qs[(size_t)q];
+        Q.kp = kparams(p);
+        Q.qoff = offsets[q] - offsets[0];
+        Q.qlen = qlens[(size_t)q];
+        mats[(size_t)q] = kmatrix(p);
+        Q.bias = matrix_bias(mats[(size_t)q]);
+        Q.table = p->seed == seed0 ? 1 : 0;
+        Q.pad_ = 0;
+    }
+    b->nq = 0;      // not usable until the upload below completes
+    drop_graph(b);
+    HIP_TRY(hipMemcpyAsync(b->d_qcodes, codes.data(), codes.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b->d_qs, qs.data(), qs.size() * sizeof(BatchQuery), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b->d_mats, mats.data(), mats.size() * sizeof(KMatrix), hipMemcpyHostToDevice, st));
+    if (new_table && b->db->n_queue > 0) {
+        const int32_t nqueue = (int32_t)b->db->n_queue;
+        hipLaunchKernelGGL(k_draws, dim3((nqueue + 255) / 256), dim3(256), 0, st,
+                           (const PairRec*)b->db->d_recs, nqueue, seed0, b->d_draws, b->d_ctr);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    b->table_valid = true;
+    b->table_seed = seed0;
+    b->nq = nq;
+    b->qlens = qlens;
+    b->cur_max_qlen = mx;
+    int rc = choose_schedule(b, st);
+    if (rc) b->nq = 0;
+    return rc;
+}
+
+int hs_batch_schedule(hs_batch* b, int32_t copies, int32_t cap, int32_t chunk, void* stream) {
+    if (!b) return fail(HS_EINVAL, "batch is NULL");
+    if (copies != 0 && copies != 1 && copies != 4) return fail(HS_EINVAL, "copies must be 0, 1 or 4");
+    if (cap < 0 || cap > kLanes) return fail(HS_EINVAL, "cap must lie in [0, 64]");
+    if (chunk < 0 || chunk % 64 != 0) return fail(HS_EINVAL, "chunk must be 0 or a positive multiple of 64");
+    if (copies == 4 && b->nq > 0 && !copies_fit(b->cur_max_qlen, 4))
+        return fail(HS_EINVAL, "four profile copies do not fit in LDS for the longest query");
+    b->fix_copies = copies;
+    b->fix_cap = cap;
+    b->fix_chunk = chunk;
+    if (b->nq < 1) return HS_OK;
+    return choose_schedule(b, (hipStream_t)stream);
+}
+
+int hs_batch_get_schedule(const hs_batch* b, int32_t* copies, int32_t* cap, int32_t* chunk,
+                          int32_t* grid, int32_t* n_items) {
+    if (!b) return fail(HS_EINVAL, "batch is NULL");
+    if (copies) *copies = b->copies;
+    if (cap) *cap = b->cap;
+    if (chunk) *chunk = b->chunk;
+    if (grid) *grid = b->grid;
+    if (n_items) *n_items = b->n_items;
+    return HS_OK;
+}
+
+int hs_batch_tune(hs_batch* b, void* stream, int32_t reps, float* best_ms) {
+    int rc = check_batch_ready(b);
+    if (rc) return rc;
+    if (reps < 1) reps = 1;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int32_t> copies_c = {1};
+    if (copies_fit(b->cur_max_qlen, 4)) copies_c.push_back(4);
+    const int32_t full = (int32_t)round64(std::max<int64_t>(b->db->n_queue, 64));
+    std::vector<int32_t> chunk_c;
+    for (int32_t c = full; c >= min_chunk(b->db); c /= 2) {
+        const int32_t r = (int32_t)round64(c);
+        if (chunk_c.empty() || chunk_c.back() != r) chunk_c.push_back(r);
+        if (c <= 64) break;
+    }
+    const int32_t cap_c[] = {16, 32, 64};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(HS_EDEVICE, "event creation failed");
+    }
+    float best = 1e30f;
+    int32_t bc = 0, bk = 0, bch = 0;
+    // mean time of `reps` scoring passes under one schedule, after a warm-up
+    auto time_one = [&](int32_t cp, int32_t ca, int32_t ch, float* ms) -> int {
+        b->fix_copies = cp;
+        b->fix_cap = ca;
+        b->fix_chunk = ch;
+        int r = choose_schedule(b, st);
+        if (!r) r = enqueue_batch_score(b, st, nullptr);
+        if (r) return r;
+        if (hipEventRecord(e0, st) != hipSuccess) return fail(HS_EDEVICE, "event record failed");
+        for (int32_t i = 0; i < reps && !r; ++i) r = enqueue_batch_score(b, st, nullptr);
+        if (r) return r;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+            return fail(HS_EDEVICE, "timing failed");
+        *ms /= (float)reps;
+        return HS_OK;
+    };
+    for (int32_t cp : copies_c) {
+        for (int32_t ca : cap_c) {
+            for (int32_t ch : chunk_c) {
+                float ms = 0;
+                if ((rc = time_one(cp, ca, ch, &ms))) break;
+                if (ms < best) {
+                    best = ms;
+                    bc = cp;
+                    bk = ca;
+                    bch = ch;
+                }
+            }
+            if (rc) break;
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        b->fix_copies = b->fix_cap = b->fix_chunk = 0;
+        (void)choose_schedule(b, st);
+        return rc;
+    }
+    b->fix_copies = bc;
+    b->fix_cap = bk;
+    b->fix_chunk = bch;
+    if ((rc = choose_schedule(b, st))) return rc;
+    if (best_ms) *best_ms = best;
+    return HS_OK;
+}
+
+int hs_batch_score(hs_batch* b, void* stream, uint64_t* d_cells) {
+    int rc = check_batch_ready(b);
+    if (rc) return rc;
+    return enqueue_batch_score(b, (hipStream_t)stream, d_cells);
+}
+
+int hs_batch_run(hs_batch* b, void* stream) {
+    int rc = check_batch_ready(b);
+    if (rc) return rc;
+    return enqueue_batch(b, (hipStream_t)stream);
+}
+
+int hs_batch_run_graph(hs_batch* b, void* stream) {
+    int rc = check_batch_ready(b);
+    if (rc) return rc;
+    if (!b->exec) {
+        if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_batch(b, b->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+        if (rc || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc ? rc : fail(HS_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
+        }
+        const hipError_t ei = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            b->exec = nullptr;
+            return fail(HS_EDEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(ei));
+        }
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
+    return HS_OK;
+}
+
+int hs_batch_outputs(const hs_batch* b, hs_hit** d_hits, int32_t** d_n_hits, hs_aln** d_alns,
+                     uint32_t** d_ops, int64_t* ops_stride, int32_t** d_scores, int32_t** d_rounds) {
+    if (!b) return fail(HS_EINVAL, "batch is NULL");
+    if (d_hits) *d_hits = (hs_hit*)b->d_hits;
+    if (d_n_hits) *d_n_hits = b->d_n_hits;
+    if (d_alns) *d_alns = (hs_aln*)b->d_alns;
+    if (d_ops) *d_ops = b->d_ops;
+    if (ops_stride) *ops_stride = b->ops_stride;
+    if (d_scores) *d_scores = b->d_scores;
+    if (d_rounds) *d_rounds = b->d_rounds;
+    return HS_OK;
+}
+
+int hs_batch_results(hs_batch* b, void* stream, hs_hit* hits, int32_t* n_hits, hs_aln* alns,
+                     int32_t* n_alns, uint32_t* ops, int64_t ops_cap, int64_t* ops_used) {
+    int rc = check_batch_ready(b);
+    if (rc) return rc;
+    if (!hits || !n_hits || (b->n_aln > 0 && (!alns || !n_alns || !ops_used)))
+        return fail(HS_EINVAL, "NULL output pointer");
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t nq = b->nq, k = b->k, na = b->n_aln;
+    std::vector<DevHit> h_hits((size_t)nq * k);
+    std::vector<int32_t> h_nh((size_t)nq);
+    std::vector<DevAln> h_alns((size_t)nq * std::max(na, 1));
+    std::vector<int64_t> h_pos((size_t)nq * std::max(na, 1) + 1, 0);
+    if (na > 0) {
+        hipLaunchKernelGGL(k_ops_scan, dim3(1), dim3(1024), 0, st, (const DevAln*)b->d_alns,
+                           (const int32_t*)b->d_n_hits, nq, na, b->d_pos);
+        hipLaunchKernelGGL(k_ops_gather, dim3(na, nq), dim3(64), 0, st, (const DevAln*)b->d_alns,
+                           (const int32_t*)b->d_n_hits, na, (const uint32_t*)b->d_ops,
+                           (const int64_t*)b->d_pos, b->d_packed);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipMemcpyAsync(h_hits.data(), b->d_hits, sizeof(DevHit) * h_hits.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(h_nh.data(), b->d_n_hits, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
+    if (na > 0) {
+        HIP_TRY(hipMemcpyAsync(h_alns.data(), b->d_alns, sizeof(DevAln) * (size_t)nq * na,
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(h_pos.data(), b->d_pos, sizeof(int64_t) * ((size_t)nq * na + 1),
+                               hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    if (na > 0) {
+        const int64_t need = h_pos[(size_t)nq * na];
+        *ops_used = need;
+        if (need > ops_cap) return fail(HS_ENOSPC, "ops buffer too small");
+        if (need > 0) {
+            HIP_TRY(hipMemcpyAsync(ops, b->d_packed, sizeof(uint32_t) * need, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+    }
+    for (int32_t q = 0; q < nq; ++q) {
+        const int32_t nh = h_nh[(size_t)q];
+        std::memcpy(hits + (size_t)q * k, h_hits.data() + (size_t)q * k, sizeof(DevHit) * (size_t)nh);
+        n_hits[q] = nh;
+        if (na > 0) {
+            const int32_t m = std::min(na, nh);
+            for (int32_t a = 0; a < m; ++a) {
+                const size_t i = (size_t)q * na + a;
+                alns[i].target_id = h_alns[i].target_id;
+                alns[i].score = h_alns[i].score;
+                alns[i].n_ops = h_alns[i].n_ops;
+                alns[i].ops_off = h_pos[i];
+            }
+            n_alns[q] = m;
+        }
+    }
+    return HS_OK;
+}
+
+int hs_batch_scores(hs_batch* b, void* stream, int32_t* scores, int32_t* rounds) {
+    int rc = check_batch_ready(b);
+    if (rc) return rc;
+    if (!scores) return fail(HS_EINVAL, "scores is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t n = (size_t)b->nq * (size_t)b->db->n_targets;
+    if (n) {
+        HIP_TRY(hipMemcpyAsync(scores, b->d_scores, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+        if (rounds)
+            HIP_TRY(hipMemcpyAsync(rounds, b->d_rounds, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return HS_OK;
+}
+
+int hs_search_batch(const hs_db* db, int32_t nq, const char* residues, const int64_t* offsets,
+                    const hs_params* params, int32_t n_params, int32_t k, int32_t n_aln,
+                    void* stream, hs_hit* hits, int32_t* n_hits, hs_aln* alns, int32_t* n_alns,
+                    uint32_t* ops, int64_t ops_cap, int64_t* ops_used) {
+    if (!db) return fail(HS_EINVAL, "db is NULL");
+    if (nq < 1 || nq > HS_MAX_BATCH) return fail(HS_EINVAL, "nq must lie in [1, HS_MAX_BATCH]");
+    if (!offsets || !residues) return fail(HS_EINVAL, "NULL residues or offsets");
+    int32_t mx = 1;
+    for (int32_t q = 0; q < nq; ++q) {
+        const int64_t L = offsets[q + 1] - offsets[q];
+        if (L < 1 || L > HS_MAX_QUERY)
+            return fail(HS_EINVAL, "query " + std::to_string(q) + " has length outside [1, HS_MAX_QUERY]");
+        mx = std::max(mx, (int32_t)L);
+    }
+    hs_batch* b = nullptr;
+    int rc = hs_batch_create(db, nq, mx, offsets[nq] - offsets[0], k, n_aln, &b);
+    if (rc) return rc;
+    rc = hs_batch_set(b, nq, residues, offsets, params, n_params, stream);
+    if (!rc) rc = hs_batch_run(b, stream);
+    if (!rc) rc = hs_batch_results(b, stream, hits, n_hits, alns, n_alns, ops, ops_cap, ops_used);
+    free_batch(b);
+    return rc;
 }
 
 const char* hs_last_error(void) { return g_err.c_str(); }

@@ -398,11 +398,13 @@ struct PairState {
 };
 
 // random() draw d of the pair's current round: round 0's first 32 draws come
-// from the table filled before the search (staged in LDS when the pair is
-// handed out), the rest from Philox directly.
+// from the table filled before the search, the rest from Philox directly.
+// With kOptTable the table may be absent (NULL: a query whose seed differs
+// from the table's), and every draw comes from Philox.
+template <bool kOptTable>
 __device__ __forceinline__ uint32_t pair_draw(PairState& s, const KParams& kp,
                                               const uint64_t* __restrict__ draws, uint32_t d) {
-    if (s.round == 0 && d < 32) {
+    if ((!kOptTable || draws != nullptr) && s.round == 0 && d < 32) {
         const uint32_t wi = d >> 2;
         if (wi != s.dw_i) {
             if (wi == s.pf_i) {
@@ -421,16 +423,17 @@ __device__ __forceinline__ uint32_t pair_draw(PairState& s, const KParams& kp,
     return (uint32_t)(x >> (16 * (d & 3))) & 0xFFFFu;
 }
 
+template <bool kOptTable>
 __device__ __forceinline__ void start_round(PairState& s, const KParams& kp,
                                             const uint64_t* __restrict__ draws) {
-    s.LF = round_factor(kp.lfactor, kp.minfactor, pair_draw(s, kp, draws, 0));
-    s.SF = round_factor(kp.sfactor, kp.minfactor, pair_draw(s, kp, draws, 1));
+    s.LF = round_factor(kp.lfactor, kp.minfactor, pair_draw<kOptTable>(s, kp, draws, 0));
+    s.SF = round_factor(kp.sfactor, kp.minfactor, pair_draw<kOptTable>(s, kp, draws, 1));
     s.pL = s.pS = s.t = s.score = 0;
 }
 
 // Advances the pair until it has a step to score (or finishes).  Finished
 // pairs write their best round's score.
-template <bool kCount>
+template <bool kCount, bool kOptTable>
 __device__ __forceinline__ void advance_pair(PairState& s, const KParams& kp,
                                              const uint64_t* __restrict__ draws, SlotInfo* slot,
                                              int32_t* scores, int32_t* rounds, uint64_t& cells,
@@ -439,7 +442,7 @@ __device__ __forceinline__ void advance_pair(PairState& s, const KParams& kp,
         if (s.pL < s.nl && s.pS < s.ns) {
             const int32_t ls = window_large(s.nl - s.pL, s.LF);
             const int32_t ss =
-                window_small(s.ns - s.pS, s.SF, pair_draw(s, kp, draws, 2u + (uint32_t)s.t), ls);
+                window_small(s.ns - s.pS, s.SF, pair_draw<kOptTable>(s, kp, draws, 2u + (uint32_t)s.t), ls);
             const int32_t nk = ls - ss + 1;
             s.ss = ss;
             s.blk = 0;
@@ -447,7 +450,8 @@ __device__ __forceinline__ void advance_pair(PairState& s, const KParams& kp,
             s.stepping = true;
             // fetch the word of the next step's draw while this step is scored
             const uint32_t wn = (3u + (uint32_t)s.t) >> 2;
-            if (s.round == 0 && wn < 8 && wn != s.dw_i && wn != s.pf_i) {
+            if ((!kOptTable || draws != nullptr) && s.round == 0 && wn < 8 && wn != s.dw_i &&
+                wn != s.pf_i) {
                 s.pf = draws[(int64_t)s.qi * 8 + wn];
                 s.pf_i = wn;
             }
@@ -468,7 +472,7 @@ __device__ __forceinline__ void advance_pair(PairState& s, const KParams& kp,
             s.best_round = s.round;
         }
         if (++s.round < kp.rounds) {
-            start_round(s, kp, draws);
+            start_round<kOptTable>(s, kp, draws);
             continue;
         }
         scores[s.id] = s.best;
@@ -517,34 +521,28 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x, int32_t lane
     return x;
 }
 
-// Dynamic LDS: [profile copies][kWaves x WaveLds].
-__host__ __device__ inline size_t sched_lds_bytes(int32_t qlen, int copies) {
-    const int32_t ps = profile_stride(qlen);
-    return (size_t)copies * profile_copy_bytes(ps) + sizeof(WaveLds) * kWaves;
-}
-
-template <int kCopies, bool kCount>
-__global__ __launch_bounds__(kThreads) void k_score_sched(
-    const PairRec* __restrict__ recs, int32_t n, const uint8_t* __restrict__ letters,
-    const uint8_t* __restrict__ qcodes, int32_t qlen, KParams kp, KMatrix km, int32_t bias,
-    const uint64_t* __restrict__ draws, uint32_t* queue, int32_t* __restrict__ scores,
-    int32_t* __restrict__ rounds, unsigned long long* cells_total, int32_t* max_score) {
-    extern __shared__ __align__(16) uint8_t lds[];
-    const int32_t ps = profile_stride(qlen);
-    const int32_t cpb = profile_copy_bytes(ps);
-    uint8_t* prof = lds;
-    build_profile<kCopies>(prof, ps, qcodes, qlen, km, bias);
-    __syncthreads();   // the only workgroup barrier: wavefronts run independently from here
-
-    const int32_t lane = threadIdx.x & (kLanes - 1);
-    WaveLds& W = ((WaveLds*)(lds + kCopies * cpb))[threadIdx.x / kLanes];
+// One wavefront's share of the pairs of one query: hand-out positions below
+// `hi`, taken from the counter `ctr` -- kGrab at a time from a global
+// counter, or (kExact) exactly as many as the wavefront needs from a
+// workgroup counter in LDS -- with at most `cap` pairs in flight (lanes
+// 0..cap-1 hold them).  Returns when no pair is left; scores go to
+// scores[target], the best round to rounds[target].  kExact also allows a
+// missing draw table (see pair_draw).
+template <int kCopies, bool kCount, bool kExact>
+__device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap,
+                                           const uint8_t* prof, int32_t ps, int32_t cpb,
+                                           int32_t bias, int32_t qlen, const KParams& kp,
+                                           const PairRec* __restrict__ recs, uint32_t hi,
+                                           const uint8_t* __restrict__ letters,
+                                           const uint64_t* __restrict__ draws, uint32_t* ctr,
+                                           int32_t* __restrict__ scores,
+                                           int32_t* __restrict__ rounds, uint64_t& cells,
+                                           int32_t& best_seen) {
     PairState s;
     s.id = -1;
     s.stepping = false;
     bool exhausted = false;
     uint32_t q_next = 0, q_end = 0;   // held range of queue positions (wavefront-uniform)
-    uint64_t cells = 0;
-    int32_t best_seen = INT32_MIN;    // largest pair score written by this lane
 
     for (;;) {
         // ---- phase A: apply last step's winner, advance, refill ----
@@ -557,48 +555,54 @@ __global__ __launch_bounds__(kThreads) void k_score_sched(
             ++s.t;
             s.stepping = false;
         }
-        advance_pair<kCount>(s, kp, draws, &W.slots[lane], scores, rounds, cells, best_seen);
-        {
-            const bool need = s.id < 0 && !exhausted;
+        advance_pair<kCount, kExact>(s, kp, draws, &W.slots[lane], scores, rounds, cells, best_seen);
+        // Refill empty slots.  A position may hold padding (id -1): its lane
+        // stays empty and asks again; the refill repeats while no lane holds
+        // a pair, so the wavefront leaves only once every lane that may take
+        // pairs has seen the end of the range.
+        for (;;) {
+            const bool need = s.id < 0 && !exhausted && lane < cap;
             const uint64_t mask = __ballot(need);
-            if (mask) {
-                const uint32_t cnt = (uint32_t)__popcll(mask);
-                const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1));
-                // from the range already held, then from one new range
-                const uint32_t take1 = cnt < q_end - q_next ? cnt : q_end - q_next;
-                uint32_t qi = q_next + rank;
-                q_next += take1;
-                if (take1 < cnt) {
-                    uint32_t base = 0;
-                    if (lane == 0) base = atomicAdd(queue, kGrab);
-                    base = __shfl(base, 0, kLanes);
-                    if (rank >= take1) qi = base + (rank - take1);
-                    q_next = base + (cnt - take1);
-                    q_end = base + kGrab;
-                }
-                if (need) {
-                    if (qi < (uint32_t)n && recs[qi].id >= 0) {
-                        const PairRec r = recs[qi];
-                        s.dw = draws[(int64_t)qi * 8];
-                        s.dw_i = 0;
-                        s.pf_i = 0xFFFFFFFFu;
-                        s.id = r.id;
-                        s.qi = (int32_t)qi;
-                        s.tl = r.len >= qlen;
-                        s.nl = s.tl ? r.len : qlen;
-                        s.ns = s.tl ? qlen : r.len;
-                        s.tbase = r.offset;
-                        s.round = 0;
-                        s.best = INT32_MIN;
-                        s.best_round = 0;
-                        s.stepping = false;
-                        start_round(s, kp, draws);
-                        advance_pair<kCount>(s, kp, draws, &W.slots[lane], scores, rounds, cells, best_seen);
-                    } else if (qi >= (uint32_t)n) {
-                        exhausted = true;
-                    }
+            if (!mask) break;
+            const uint32_t cnt = (uint32_t)__popcll(mask);
+            const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1));
+            // from the range already held, then from one new range
+            const uint32_t take1 = cnt < q_end - q_next ? cnt : q_end - q_next;
+            uint32_t qi = q_next + rank;
+            q_next += take1;
+            if (take1 < cnt) {
+                const uint32_t g = kExact ? cnt - take1 : kGrab;
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(ctr, g);
+                base = __shfl(base, 0, kLanes);
+                if (rank >= take1) qi = base + (rank - take1);
+                q_next = base + (cnt - take1);
+                q_end = base + g;
+            }
+            if (need) {
+                if (qi < hi && recs[qi].id >= 0) {
+                    const PairRec r = recs[qi];
+                    s.dw = (!kExact || draws != nullptr) ? draws[(int64_t)qi * 8] : 0ull;
+                    s.dw_i = 0;
+                    s.pf_i = 0xFFFFFFFFu;
+                    s.id = r.id;
+                    s.qi = (int32_t)qi;
+                    s.tl = r.len >= qlen;
+                    s.nl = s.tl ? r.len : qlen;
+                    s.ns = s.tl ? qlen : r.len;
+                    s.tbase = r.offset;
+                    s.round = 0;
+                    s.best = INT32_MIN;
+                    s.best_round = 0;
+                    s.stepping = false;
+                    start_round<kExact>(s, kp, draws);
+                    advance_pair<kCount, kExact>(s, kp, draws, &W.slots[lane], scores, rounds,
+                                                 cells, best_seen);
+                } else if (qi >= hi) {
+                    exhausted = true;
                 }
             }
+            if (__ballot(s.id >= 0) != 0) break;
         }
         if (__ballot(s.id >= 0) == 0) break;
 
@@ -676,16 +680,102 @@ __global__ __launch_bounds__(kThreads) void k_score_sched(
         }
         wave_sync();
     }
+}
+
+__device__ __forceinline__ int32_t wave_max_i32(int32_t x) {
+    for (int o = kLanes / 2; o > 0; o >>= 1) {
+        const int32_t y = __shfl_xor(x, o, kLanes);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// Dynamic LDS: [profile copies][kWaves x WaveLds].
+__host__ __device__ inline size_t sched_lds_bytes(int32_t qlen, int copies) {
+    const int32_t ps = profile_stride(qlen);
+    return (size_t)copies * profile_copy_bytes(ps) + sizeof(WaveLds) * kWaves;
+}
+
+// One query against the whole database: every workgroup holds the query
+// profile, every wavefront pulls pairs from the global queue.
+template <int kCopies, bool kCount>
+__global__ __launch_bounds__(kThreads) void k_score_sched(
+    const PairRec* __restrict__ recs, int32_t n, const uint8_t* __restrict__ letters,
+    const uint8_t* __restrict__ qcodes, int32_t qlen, KParams kp, KMatrix km, int32_t bias,
+    const uint64_t* __restrict__ draws, uint32_t* queue, int32_t* __restrict__ scores,
+    int32_t* __restrict__ rounds, unsigned long long* cells_total, int32_t* max_score) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const int32_t ps = profile_stride(qlen);
+    const int32_t cpb = profile_copy_bytes(ps);
+    uint8_t* prof = lds;
+    build_profile<kCopies>(prof, ps, qcodes, qlen, km, bias);
+    __syncthreads();   // the only workgroup barrier: wavefronts run independently from here
+
+    const int32_t lane = threadIdx.x & (kLanes - 1);
+    WaveLds& W = ((WaveLds*)(lds + kCopies * cpb))[threadIdx.x / kLanes];
+    uint64_t cells = 0;
+    int32_t best_seen = INT32_MIN;    // largest pair score written by this lane
+    wave_pairs<kCopies, kCount, false>(W, lane, kLanes, prof, ps, cpb, bias, qlen, kp, recs,
+                                       (uint32_t)n, letters, draws, queue, scores, rounds, cells,
+                                       best_seen);
     if (kCount) {
         for (int o = kLanes / 2; o > 0; o >>= 1) cells += __shfl_xor(cells, o, kLanes);
         if (lane == 0) atomicAdd(cells_total, (unsigned long long)cells);
     }
     if (max_score) {
-        for (int o = kLanes / 2; o > 0; o >>= 1) {
-            const int32_t y = __shfl_xor(best_seen, o, kLanes);
-            best_seen = y > best_seen ? y : best_seen;
-        }
+        best_seen = wave_max_i32(best_seen);
         if (lane == 0 && best_seen != INT32_MIN) atomicMax(max_score, best_seen);
+    }
+}
+
+// Many queries against the whole database in one persistent launch.  A
+// workgroup takes work items (query, range of hand-out positions) from a
+// global counter, longest queries first; for each it builds that query's
+// profile, then its wavefronts pull the item's pairs from a counter in LDS,
+// at most `cap` in flight per wavefront.  Query q's scores go to
+// scores[q * stride + target], its maximum score to max_score[q * ms_stride].
+template <int kCopies, bool kCount>
+__global__ __launch_bounds__(kThreads) void k_score_batch(
+    const BatchQuery* __restrict__ qs, const KMatrix* __restrict__ mats,
+    const uint8_t* __restrict__ qcodes, const BatchItem* __restrict__ items, int32_t n_items,
+    uint32_t* item_ctr, int32_t prof_bytes, int32_t cap, const PairRec* __restrict__ recs,
+    const uint8_t* __restrict__ letters, const uint64_t* __restrict__ draws,
+    int32_t* __restrict__ scores, int32_t* __restrict__ rounds, int64_t stride,
+    int32_t* max_score, int32_t ms_stride, unsigned long long* cells_total) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ uint32_t s_item, s_ctr;
+    const int32_t lane = threadIdx.x & (kLanes - 1);
+    WaveLds& W = ((WaveLds*)(lds + prof_bytes))[threadIdx.x / kLanes];
+    uint64_t cells = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint32_t it = atomicAdd(item_ctr, 1u);
+            s_item = it;
+            if (it < (uint32_t)n_items) s_ctr = items[it].lo;
+        }
+        __syncthreads();
+        const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it >= (uint32_t)n_items) break;
+        const BatchItem item = items[it];
+        const int32_t q = item.q;
+        const BatchQuery Q = qs[q];
+        const int32_t ps = profile_stride(Q.qlen);
+        const int32_t cpb = profile_copy_bytes(ps);
+        build_profile<kCopies>(lds, ps, qcodes + Q.qoff, Q.qlen, mats[q], Q.bias);
+        __syncthreads();
+        int32_t best_seen = INT32_MIN;
+        wave_pairs<kCopies, kCount, true>(W, lane, cap, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, recs,
+                                          item.hi, letters, Q.table ? draws : nullptr, &s_ctr,
+                                          scores + (int64_t)q * stride,
+                                          rounds ? rounds + (int64_t)q * stride : nullptr, cells,
+                                          best_seen);
+        best_seen = wave_max_i32(best_seen);
+        if (lane == 0 && best_seen != INT32_MIN) atomicMax(max_score + (int64_t)q * ms_stride, best_seen);
+        __syncthreads();   // the profile and the counter are rewritten for the next item
+    }
+    if (kCount) {
+        for (int o = kLanes / 2; o > 0; o >>= 1) cells += __shfl_xor(cells, o, kLanes);
+        if (lane == 0) atomicAdd(cells_total, (unsigned long long)cells);
     }
 }
 

@@ -27,7 +27,8 @@ struct TopkState {
     int32_t n_sel;          // min(k, eligible targets)
     int32_t fallback;       // 1: the fast path cannot decide, use the radix select
     int32_t count;          // keys gathered by the collect pass
-    int32_t pad_[3];
+    int32_t min_score;      // eligibility threshold of the query
+    int32_t pad_[2];
 };
 
 struct DevHit {
@@ -51,8 +52,12 @@ struct TopkWs {
     uint64_t* keys;         // [nq][kSortCap]
 };
 
-// Before the scoring pass: reset the state and the histogram of every query.
-__global__ __launch_bounds__(256) void k_topk_reset(TopkWs w) {
+// Before the scoring pass: reset the state and the histogram of every query
+// and, if given, a work counter.  The threshold is qs[q].kp.min_score for a
+// batch, min_score otherwise.
+__global__ __launch_bounds__(256) void k_topk_reset(TopkWs w, int32_t min_score,
+                                                    const BatchQuery* __restrict__ qs,
+                                                    uint32_t* ctr) {
     const int q = blockIdx.y;
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         TopkState s;
@@ -61,8 +66,10 @@ __global__ __launch_bounds__(256) void k_topk_reset(TopkWs w) {
         s.n_sel = 0;
         s.fallback = 0;
         s.count = 0;
-        s.pad_[0] = s.pad_[1] = s.pad_[2] = 0;
+        s.min_score = qs ? qs[q].kp.min_score : min_score;
+        s.pad_[0] = s.pad_[1] = 0;
         w.st[q] = s;
+        if (ctr && q == 0) *ctr = 0;
     }
     uint32_t* h = w.hist + (int64_t)q * kWinBins;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kWinBins; i += gridDim.x * blockDim.x)
@@ -71,11 +78,12 @@ __global__ __launch_bounds__(256) void k_topk_reset(TopkWs w) {
 
 // Histogram of eligible scores within [M - kWinBins + 1, M].
 __global__ __launch_bounds__(256) void k_topk_hist(const int32_t* __restrict__ scores, int64_t stride,
-                                                   int32_t n, int32_t min_score, TopkWs w) {
+                                                   int32_t n, TopkWs w) {
     __shared__ uint32_t h[kWinBins];
     const int q = blockIdx.y;
     const int32_t* sc = scores + (int64_t)q * stride;
     const int32_t M = w.st[q].max_score;
+    const int32_t min_score = w.st[q].min_score;
     for (int i = threadIdx.x; i < kWinBins; i += blockDim.x) h[i] = 0;
     __syncthreads();
     const int32_t lo = M - (kWinBins - 1);
@@ -91,12 +99,13 @@ __global__ __launch_bounds__(256) void k_topk_hist(const int32_t* __restrict__ s
 }
 
 // One workgroup per query: the k-th best score from the window histogram.
-__global__ __launch_bounds__(256) void k_topk_pick(int32_t k, int32_t min_score, int32_t n, TopkWs w) {
+__global__ __launch_bounds__(256) void k_topk_pick(int32_t k, int32_t n, TopkWs w) {
     __shared__ uint32_t part[256];
     const int q = blockIdx.y;
     TopkState* st = w.st + q;
     const uint32_t* gh = w.hist + (int64_t)q * kWinBins;
     const int32_t M = st->max_score;
+    const int32_t min_score = st->min_score;
     if (n == 0 || M == INT32_MIN) {          // empty database
         if (threadIdx.x == 0) { st->n_sel = 0; st->thr = INT32_MAX; }
         return;
@@ -151,11 +160,12 @@ __global__ __launch_bounds__(256) void k_topk_pick(int32_t k, int32_t min_score,
 
 // Gathers every eligible key with score >= T (fast path only).
 __global__ __launch_bounds__(256) void k_topk_collect(const int32_t* __restrict__ scores, int64_t stride,
-                                                      int32_t n, int32_t min_score, TopkWs w) {
+                                                      int32_t n, TopkWs w) {
     const int q = blockIdx.y;
     TopkState* st = w.st + q;
     if (st->fallback) return;
     const int32_t thr = st->thr;
+    const int32_t min_score = st->min_score;
     const int32_t* sc = scores + (int64_t)q * stride;
     uint64_t* keys = w.keys + (int64_t)q * kSortCap;
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -226,7 +236,7 @@ __device__ uint64_t radix_select_block(const int32_t* sc, int32_t n, int32_t min
 // radix select (fallback), then writes the ranked hits.
 __global__ __launch_bounds__(1024) void k_topk_final(const int32_t* __restrict__ scores, int64_t stride,
                                                      const int32_t* __restrict__ rounds, int32_t n,
-                                                     int32_t min_score, int32_t k, TopkWs w,
+                                                     int32_t k, TopkWs w,
                                                      DevHit* __restrict__ hits, int32_t* __restrict__ n_hits) {
     extern __shared__ __align__(16) uint64_t s[];        // kSortCap keys
     __shared__ uint32_t hist[256];
@@ -234,6 +244,7 @@ __global__ __launch_bounds__(1024) void k_topk_final(const int32_t* __restrict__
     __shared__ uint32_t cnt;
     const int q = blockIdx.y;
     TopkState* st = w.st + q;
+    const int32_t min_score = st->min_score;
     const int32_t* sc = scores + (int64_t)q * stride;
     const int32_t* rd = rounds + (int64_t)q * stride;
     DevHit* out = hits + (int64_t)q * k;

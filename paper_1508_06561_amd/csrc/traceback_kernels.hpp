@@ -50,28 +50,20 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
     return x;
 }
 
-// One wavefront per alignment a < min(n_aln, n_hits): replays the winning
-// round of the hit, lanes splitting each step's placements, and writes the
-// alignment as ops oriented (query, target).  Inside the chop-and-consume
-// loop only the small sequence receives gaps (Section III.B.3): the k*
-// skipped letters of large are target letters over gaps (D) when the target
-// is large and query letters over gaps (I) otherwise; after the loop the rest
-// of whichever sequence is left goes against gaps.
-__global__ __launch_bounds__(64) void k_traceback(DbView db, const uint8_t* __restrict__ qcodes,
-                                                  int32_t qlen, KParams kp, KMatrix km,
-                                                  int32_t bias, const DevHit* __restrict__ hits,
-                                                  const int32_t* __restrict__ n_hits, int32_t n_aln,
-                                                  DevAln* __restrict__ alns,
-                                                  uint32_t* __restrict__ ops, int64_t ops_stride) {
-    extern __shared__ __align__(16) uint8_t prof[];
-    const int32_t ps = profile_stride(qlen);
-    build_profile<1>(prof, ps, qcodes, qlen, km, bias);
-    __syncthreads();
-    const int32_t a = blockIdx.x;
+// Replays the winning round of one hit with the query profile (one copy) in
+// LDS, lanes splitting each step's placements, and writes the alignment as
+// ops oriented (query, target).  Inside the chop-and-consume loop only the
+// small sequence receives gaps (Section III.B.3): the k* skipped letters of
+// large are target letters over gaps (D) when the target is large and query
+// letters over gaps (I) otherwise; after the loop the rest of whichever
+// sequence is left goes against gaps.
+__device__ __forceinline__ void traceback_one(const DbView& db, const uint8_t* prof, int32_t ps,
+                                              int32_t qlen, const KParams& kp, int32_t bias,
+                                              const DevHit& hit, DevAln* out_aln, uint32_t* ops,
+                                              int64_t ops_off) {
     const int32_t lane = threadIdx.x;
-    if (a >= n_aln || a >= *n_hits) return;
-    const int32_t id = (int32_t)hits[a].target_id;
-    const int32_t r = hits[a].round;
+    const int32_t id = (int32_t)hit.target_id;
+    const int32_t r = hit.round;
     if (id < 0 || id >= db.n || r < 0 || r >= kp.rounds) return;   // never for a valid hit
     const int32_t tlen = db.lens[id];
     const uint8_t* T = db.letters + db.offsets[id];
@@ -87,7 +79,7 @@ __global__ __launch_bounds__(64) void k_traceback(DbView db, const uint8_t* __re
     const uint32_t LF = round_factor(kp.lfactor, kp.minfactor, ds.get(0));
     const uint32_t SF = round_factor(kp.sfactor, kp.minfactor, ds.get(1));
     OpWriter w;
-    w.init(ops + (int64_t)a * ops_stride);
+    w.init(ops + ops_off);
     int32_t pL = 0, pS = 0, t = 0, score = 0;
     while (pL < nl && pS < ns) {
         const int32_t ls = window_large(nl - pL, LF);
@@ -126,9 +118,91 @@ __global__ __launch_bounds__(64) void k_traceback(DbView db, const uint8_t* __re
         out.target_id = id;
         out.score = score;
         out.n_ops = w.n;
-        out.ops_off = (int64_t)a * ops_stride;
-        alns[a] = out;
+        out.ops_off = ops_off;
+        *out_aln = out;
     }
+}
+
+// One wavefront per alignment a < min(n_aln, n_hits) of one query.
+__global__ __launch_bounds__(64) void k_traceback(DbView db, const uint8_t* __restrict__ qcodes,
+                                                  int32_t qlen, KParams kp, KMatrix km,
+                                                  int32_t bias, const DevHit* __restrict__ hits,
+                                                  const int32_t* __restrict__ n_hits, int32_t n_aln,
+                                                  DevAln* __restrict__ alns,
+                                                  uint32_t* __restrict__ ops, int64_t ops_stride) {
+    extern __shared__ __align__(16) uint8_t prof[];
+    const int32_t ps = profile_stride(qlen);
+    build_profile<1>(prof, ps, qcodes, qlen, km, bias);
+    __syncthreads();
+    const int32_t a = blockIdx.x;
+    if (a >= n_aln || a >= *n_hits) return;
+    traceback_one(db, prof, ps, qlen, kp, bias, hits[a], alns + a, ops, (int64_t)a * ops_stride);
+}
+
+// Batch form: alignment a = blockIdx.x of query q = blockIdx.y; query q's
+// hits start at hits[q * k], its alignments at alns[q * n_aln], and the ops
+// of alignment (q, a) at ops[(q * n_aln + a) * ops_stride].
+__global__ __launch_bounds__(64) void k_traceback_batch(
+    DbView db, const BatchQuery* __restrict__ qs, const KMatrix* __restrict__ mats,
+    const uint8_t* __restrict__ qcodes, int32_t nq, int32_t k, const DevHit* __restrict__ hits,
+    const int32_t* __restrict__ n_hits, int32_t n_aln, DevAln* __restrict__ alns,
+    uint32_t* __restrict__ ops, int64_t ops_stride) {
+    extern __shared__ __align__(16) uint8_t prof[];
+    const int32_t a = blockIdx.x, q = blockIdx.y;
+    if (q >= nq || a >= n_aln || a >= n_hits[q]) return;
+    const BatchQuery Q = qs[q];
+    const int32_t ps = profile_stride(Q.qlen);
+    build_profile<1>(prof, ps, qcodes + Q.qoff, Q.qlen, mats[q], Q.bias);
+    __syncthreads();
+    const int64_t slot = (int64_t)q * n_aln + a;
+    traceback_one(db, prof, ps, Q.qlen, Q.kp, Q.bias, hits[(int64_t)q * k + a], alns + slot, ops,
+                  slot * ops_stride);
+}
+
+// Packing of a batch's alignments: pos[i] = where alignment slot
+// i = q * n_aln + a starts in a packed ops buffer (slots past the query's
+// hit count hold no ops), pos[nq * n_aln] = the total.  One workgroup.
+__global__ __launch_bounds__(1024) void k_ops_scan(const DevAln* __restrict__ alns,
+                                                   const int32_t* __restrict__ n_hits, int32_t nq,
+                                                   int32_t n_aln, int64_t* __restrict__ pos) {
+    __shared__ int64_t part[1024];
+    const int32_t total = nq * n_aln;
+    const int32_t tid = threadIdx.x;
+    int64_t carry = 0;
+    for (int32_t base = 0; base < total; base += 1024) {
+        const int32_t i = base + tid;
+        int64_t v = 0;
+        if (i < total) {
+            const int32_t q = i / n_aln, a = i - q * n_aln;
+            if (a < n_hits[q]) v = alns[i].n_ops;
+        }
+        part[tid] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int64_t y = tid >= o ? part[tid - o] : 0;
+            __syncthreads();
+            part[tid] += y;
+            __syncthreads();
+        }
+        if (i < total) pos[i] = carry + part[tid] - v;
+        carry += part[1023];
+        __syncthreads();
+    }
+    if (tid == 0) pos[total] = carry;
+}
+
+// Copies the ops of alignment (q = blockIdx.y, a = blockIdx.x) to the packed
+// buffer at pos[q * n_aln + a].
+__global__ __launch_bounds__(64) void k_ops_gather(const DevAln* __restrict__ alns,
+                                                   const int32_t* __restrict__ n_hits,
+                                                   int32_t n_aln, const uint32_t* __restrict__ ops,
+                                                   const int64_t* __restrict__ pos,
+                                                   uint32_t* __restrict__ packed) {
+    const int32_t a = blockIdx.x, q = blockIdx.y;
+    if (a >= n_hits[q]) return;
+    const int64_t i = (int64_t)q * n_aln + a;
+    const DevAln al = alns[i];
+    for (int32_t j = threadIdx.x; j < al.n_ops; j += blockDim.x) packed[pos[i] + j] = ops[al.ops_off + j];
 }
 
 }  // namespace hs

@@ -18,6 +18,7 @@ HS_OK, HS_EINVAL, HS_ENOMEM, HS_ENOSPC, HS_EDEVICE = 0, -1, -2, -3, -4
 OP_M, OP_I, OP_D = 0, 1, 2
 MAX_K = 4096
 MAX_QUERY = 5600
+MAX_BATCH = 4096
 ALPHABET = "ARNDCQEGHILKMFPSTWYVBZX*"
 
 
@@ -82,6 +83,22 @@ def lib():
                                     ctypes.c_int64]
         L.hs_score_dev.argtypes = [vp, vp, ctypes.c_int32, P(_CParams), vp, vp, ctypes.c_size_t,
                                    vp, vp, vp]
+        i32, i64, pi32 = ctypes.c_int32, ctypes.c_int64, P(ctypes.c_int32)
+        L.hs_batch_create.argtypes = [vp, i32, i32, i64, i32, i32, P(vp)]
+        L.hs_batch_free.argtypes = [vp]
+        L.hs_batch_set.argtypes = [vp, i32, vp, P(ctypes.c_int64), P(_CParams), i32, vp]
+        L.hs_batch_schedule.argtypes = [vp, i32, i32, i32, vp]
+        L.hs_batch_get_schedule.argtypes = [vp, pi32, pi32, pi32, pi32, pi32]
+        L.hs_batch_tune.argtypes = [vp, vp, i32, P(ctypes.c_float)]
+        L.hs_batch_run.argtypes = [vp, vp]
+        L.hs_batch_run_graph.argtypes = [vp, vp]
+        L.hs_batch_score.argtypes = [vp, vp, vp]
+        L.hs_batch_results.argtypes = [vp, vp, vp, pi32, vp, pi32, vp, i64, P(ctypes.c_int64)]
+        L.hs_batch_scores.argtypes = [vp, vp, vp, vp]
+        L.hs_batch_outputs.argtypes = [vp, P(vp), P(vp), P(vp), P(vp), P(ctypes.c_int64), P(vp),
+                                       P(vp)]
+        L.hs_search_batch.argtypes = [vp, i32, vp, P(ctypes.c_int64), P(_CParams), i32, i32, i32,
+                                      vp, vp, pi32, vp, pi32, vp, i64, P(ctypes.c_int64)]
         L.hs_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -282,3 +299,140 @@ class DeviceSearch:
             alns[i]["ops_off"] = off
             off += a["n_ops"]
         return Result(hits, alns, np.concatenate(chunks) if chunks else np.zeros(0, np.uint32))
+
+
+def _pack_queries(queries):
+    """(concatenated ASCII bytes as uint8, int64 offsets) of a list of queries."""
+    bs = [q.encode() if isinstance(q, str) else bytes(q) for q in queries]
+    off = np.zeros(len(bs) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(b) for b in bs])
+    res = np.frombuffer(b"".join(bs), dtype=np.uint8).copy()
+    return res, off
+
+
+def _params_array(params, nq):
+    """ctypes array of hs_params: one shared entry or one per query."""
+    if params is None or isinstance(params, Params):
+        plist = [params or Params()]
+    else:
+        plist = list(params)
+        if len(plist) not in (1, nq):
+            raise ValueError("params must be one Params or one per query")
+    arr = (_CParams * len(plist))(*[p.c() for p in plist])
+    return arr, len(plist), plist
+
+
+def _split_batch(nq, k, n_aln, hits, n_hits, alns, n_alns, ops):
+    out = []
+    for q in range(nq):
+        h = hits[q * k:q * k + n_hits[q]].copy()
+        if n_aln > 0:
+            a = alns[q * n_aln:q * n_aln + n_alns[q]].copy()
+            o0 = int(a["ops_off"][0]) if len(a) else 0
+            o1 = int(a["ops_off"][-1] + a["n_ops"][-1]) if len(a) else 0
+            a["ops_off"] -= o0
+            out.append(Result(h, a, ops[o0:o1].copy()))
+        else:
+            out.append(Result(h, np.zeros(0, ALN_DTYPE), np.zeros(0, np.uint32)))
+    return out
+
+
+class Batch:
+    """A batch handle (hs_batch_*): many queries scored in one persistent
+    launch, ranked and aligned per query; results equal separate searches."""
+
+    def __init__(self, db, max_nq, max_qlen, max_residues=None, k=50, n_aln=50):
+        self.db, self.k, self.n_aln = db, k, n_aln
+        self.max_nq, self.max_qlen = max_nq, max_qlen
+        h = ctypes.c_void_p()
+        _check(lib().hs_batch_create(db._h, max_nq, max_qlen,
+                                     max_residues or max_nq * max_qlen, k, n_aln, ctypes.byref(h)))
+        self._h = h
+        self.nq = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hs_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set(self, queries, params=None, stream=None):
+        res, off = _pack_queries(queries)
+        arr, n_p, _ = _params_array(params, len(queries))
+        _check(lib().hs_batch_set(self._h, len(queries), res.ctypes.data_as(ctypes.c_void_p),
+                                  off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), arr, n_p,
+                                  _stream(stream)))
+        self.nq = len(queries)
+        self.qlens = np.diff(off)
+
+    def schedule(self, copies=0, cap=0, chunk=0, stream=None):
+        _check(lib().hs_batch_schedule(self._h, copies, cap, chunk, _stream(stream)))
+
+    def get_schedule(self):
+        v = [ctypes.c_int32() for _ in range(5)]
+        _check(lib().hs_batch_get_schedule(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("copies", "cap", "chunk", "grid", "n_items"), [x.value for x in v]))
+
+    def tune(self, reps=2, stream=None):
+        ms = ctypes.c_float()
+        _check(lib().hs_batch_tune(self._h, _stream(stream), reps, ctypes.byref(ms)))
+        return ms.value
+
+    def run(self, stream=None, graph=False):
+        fn = lib().hs_batch_run_graph if graph else lib().hs_batch_run
+        _check(fn(self._h, _stream(stream)))
+
+    def score(self, d_cells=None, stream=None):
+        _check(lib().hs_batch_score(self._h, _stream(stream),
+                                    d_cells.data_ptr() if d_cells is not None else None))
+
+    def results(self, stream=None):
+        """Per-query Result list of the last run (synchronises)."""
+        nq, k, na = self.nq, self.k, self.n_aln
+        hits = np.zeros(nq * k, dtype=HIT_DTYPE)
+        n_hits = np.zeros(nq, dtype=np.int32)
+        alns = np.zeros(max(nq * na, 1), dtype=ALN_DTYPE)
+        n_alns = np.zeros(nq, dtype=np.int32)
+        cap = max(1, int(sum(na * (2 * int(L) + 2) for L in self.qlens)))
+        ops = np.zeros(cap, dtype=np.uint32)
+        used = ctypes.c_int64()
+        P = ctypes.POINTER(ctypes.c_int32)
+        _check(lib().hs_batch_results(self._h, _stream(stream), hits.ctypes.data,
+                                      n_hits.ctypes.data_as(P), alns.ctypes.data,
+                                      n_alns.ctypes.data_as(P), ops.ctypes.data, cap,
+                                      ctypes.byref(used)))
+        return _split_batch(nq, k, na, hits, n_hits, alns, n_alns, ops)
+
+    def scores(self, stream=None):
+        """(scores, rounds): host int32 arrays of shape (nq, n_targets)."""
+        n = self.db.n_targets
+        sc = np.zeros((self.nq, max(n, 1)), dtype=np.int32)
+        rd = np.zeros((self.nq, max(n, 1)), dtype=np.int32)
+        _check(lib().hs_batch_scores(self._h, _stream(stream), sc.ctypes.data, rd.ctypes.data))
+        return sc[:, :n], rd[:, :n]
+
+
+def search_batch(db, queries, params=None, k=50, n_aln=50, stream=None):
+    """hs_search_batch: one-shot batch search, per-query Result list."""
+    nq = len(queries)
+    res, off = _pack_queries(queries)
+    arr, n_p, _ = _params_array(params, nq)
+    hits = np.zeros(nq * k, dtype=HIT_DTYPE)
+    n_hits = np.zeros(nq, dtype=np.int32)
+    alns = np.zeros(max(nq * n_aln, 1), dtype=ALN_DTYPE)
+    n_alns = np.zeros(nq, dtype=np.int32)
+    cap = max(1, int(n_aln * (2 * np.diff(off) + 2).sum()))
+    ops = np.zeros(cap, dtype=np.uint32)
+    used = ctypes.c_int64()
+    P = ctypes.POINTER(ctypes.c_int32)
+    _check(lib().hs_search_batch(db._h, nq, res.ctypes.data_as(ctypes.c_void_p),
+                                 off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), arr, n_p, k,
+                                 n_aln, _stream(stream), hits.ctypes.data, n_hits.ctypes.data_as(P),
+                                 alns.ctypes.data, n_alns.ctypes.data_as(P), ops.ctypes.data, cap,
+                                 ctypes.byref(used)))
+    return _split_batch(nq, k, n_aln, hits, n_hits, alns, n_alns, ops)

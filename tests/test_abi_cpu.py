@@ -22,7 +22,9 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ["hs_params_default", "hs_db_load", "hs_db_free", "hs_search", "hs_search_dev",
-              "hs_score_dev", "hs_last_error", "hs_encode", "hs_workspace_bytes"]:
+              "hs_score_dev", "hs_last_error", "hs_encode", "hs_workspace_bytes",
+              "hs_search_batch", "hs_batch_create", "hs_batch_set", "hs_batch_run",
+              "hs_batch_run_graph", "hs_batch_tune", "hs_batch_results", "hs_batch_free"]:
         assert n in names
 
 
@@ -83,3 +85,33 @@ def test_argument_errors_before_device_use():
                         ctypes.c_void_p(1), 1 << 30, ctypes.c_void_p(1), None, None)
     assert rc == H.hs.HS_EINVAL
     assert L.hs_workspace_bytes(None, 1, 10, 10, 1) == 0
+
+
+def test_batch_argument_errors_before_device_use():
+    import paper_1508_06561_amd as H
+    L = H.lib()
+    E = H.hs.HS_EINVAL
+    h = ctypes.c_void_p()
+    assert L.hs_batch_create(None, 4, 100, 400, 10, 5, ctypes.byref(h)) == E
+    assert b"db" in L.hs_last_error()
+    fake = ctypes.c_void_p(1)
+    # sizes are checked before the database is touched
+    assert L.hs_batch_create(fake, 0, 100, 400, 10, 5, ctypes.byref(h)) == E
+    assert L.hs_batch_create(fake, H.hs.MAX_BATCH + 1, 100, 400, 10, 5, ctypes.byref(h)) == E
+    assert L.hs_batch_create(fake, 4, 0, 400, 10, 5, ctypes.byref(h)) == E
+    assert L.hs_batch_create(fake, 4, H.hs.MAX_QUERY + 1, 400, 10, 5, ctypes.byref(h)) == E
+    assert L.hs_batch_create(fake, 4, 100, 401, 10, 5, ctypes.byref(h)) == E
+    assert L.hs_batch_create(fake, 4, 100, 400, 0, 0, ctypes.byref(h)) == E
+    assert L.hs_batch_create(fake, 4, 100, 400, 10, 11, ctypes.byref(h)) == E
+    assert L.hs_batch_create(fake, 4, 100, 400, 10, 5, None) == E
+    for fn in (L.hs_batch_run, L.hs_batch_run_graph):
+        assert fn(None, None) == E
+    assert L.hs_batch_score(None, None, None) == E
+    assert L.hs_batch_set(None, 1, None, None, None, 1, None) == E
+    assert L.hs_batch_schedule(None, 0, 0, 0, None) == E
+    assert L.hs_batch_free(None) == 0
+    p = H.Params().c()
+    off = np.array([0, 3], np.int64)
+    assert L.hs_search_batch(None, 1, b"ACD", off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                             ctypes.byref(p), 1, 4, 0, None, None, None, None, None, None, 0,
+                             None) == E
