@@ -92,27 +92,6 @@ __device__ __forceinline__ void philox_block(uint64_t seed, uint64_t target, uin
     philox4x64_10(w[0], w[1], w[2], w[3], seed, 0);
 }
 
-struct DrawStream {
-    uint64_t seed, target;
-    uint32_t round;
-    int32_t block;
-    uint64_t w[4];
-
-    __device__ __forceinline__ void init(uint64_t s, uint64_t t, uint32_t r) {
-        seed = s; target = t; round = r; block = -1;
-    }
-    __device__ __forceinline__ uint32_t get(uint32_t d) {
-        const int32_t b = (int32_t)(d >> 4);
-        if (b != block) {
-            block = b;
-            philox_block(seed, target, round, (uint32_t)b, w);
-        }
-        const uint32_t wi = (d >> 2) & 3;
-        const uint64_t x = wi == 0 ? w[0] : wi == 1 ? w[1] : wi == 2 ? w[2] : w[3];
-        return (uint32_t)(x >> (16 * (d & 3))) & 0xFFFFu;
-    }
-};
-
 // Per-round factors (Fig. 1, AlignSequences): lf = MAX(minFactor, random())
 // scaled by LFactor, likewise sf by SFactor (Q16).
 __device__ __forceinline__ uint32_t round_factor(uint32_t factor, uint32_t minf, uint32_t u) {

@@ -348,6 +348,23 @@ int launch_rank(const hs_db* db, hipStream_t st, const int32_t* scores, const in
     return HS_OK;
 }
 
+// Alignments of one query's first n_aln hits: one hit per wavefront, eight
+// per workgroup, so that every alignment is recovered at once.
+template <int kCopies>
+int launch_trace(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParams& kp,
+                 const KMatrix& km, hipStream_t st, const DevHit* d_hits, const int32_t* d_n_hits,
+                 int32_t n_aln, DevAln* d_alns, uint32_t* d_ops, int64_t ops_stride) {
+    constexpr int32_t per_wg = kWaves;
+    const size_t lds = sched_lds_bytes(qlen, kCopies);
+    int rc = set_lds_limit((const void*)k_trace_sched<kCopies>, lds);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_trace_sched<kCopies>), dim3((n_aln + per_wg - 1) / per_wg), dim3(kThreads),
+                       lds, st, db->view(), d_q, qlen, kp, km, matrix_bias(km), d_hits, d_n_hits,
+                       n_aln, per_wg, 1, d_alns, d_ops, ops_stride);
+    HIP_TRY(hipGetLastError());
+    return HS_OK;
+}
+
 // Queues one search.  All pointers are device pointers.
 int launch_search(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_params* p, int32_t k,
                   int32_t n_aln, hipStream_t st, void* d_ws, DevHit* d_hits, int32_t* d_n_hits,
@@ -362,12 +379,12 @@ int launch_search(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_pa
     if (n_aln > 0) {
         const KParams kp = kparams(p);
         const KMatrix km = kmatrix(p);
-        const size_t lds = (size_t)profile_copy_bytes(profile_stride(qlen));
-        rc = set_lds_limit((const void*)k_traceback, lds);
+        rc = sched_lds_bytes(qlen, 4) <= device_lds_limit()
+                 ? launch_trace<4>(db, d_q, qlen, kp, km, st, d_hits, d_n_hits, n_aln, d_alns, d_ops,
+                                   ops_stride)
+                 : launch_trace<1>(db, d_q, qlen, kp, km, st, d_hits, d_n_hits, n_aln, d_alns, d_ops,
+                                   ops_stride);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_traceback, dim3(n_aln), dim3(64), lds, st, db->view(), d_q, qlen, kp, km,
-                           matrix_bias(km), d_hits, d_n_hits, n_aln, d_alns, d_ops, ops_stride);
-        HIP_TRY(hipGetLastError());
     }
     return HS_OK;
 }
@@ -380,13 +397,14 @@ int launch_search(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_pa
 struct hs_batch {
     const hs_db* db = nullptr;
     int32_t max_nq = 0, max_qlen = 0, k = 0, n_aln = 0;
-    int64_t max_res = 0, ops_stride = 0, max_items = 0;
+    int64_t max_res = 0, ops_stride = 0, max_items = 0, max_titems = 0;
     char* d_mem = nullptr;
     uint8_t* d_qcodes = nullptr;
     BatchQuery* d_qs = nullptr;
     KMatrix* d_mats = nullptr;
     BatchItem* d_items = nullptr;
-    uint32_t* d_ctr = nullptr;
+    BatchItem* d_titems = nullptr;      // alignment work items
+    uint32_t* d_ctr = nullptr;          // [0]: scoring items, [1]: alignment items
     int32_t* d_scores = nullptr;        // [max_nq][n_targets]
     int32_t* d_rounds = nullptr;
     uint64_t* d_draws = nullptr;        // round-0 draws, 8 words per hand-out position
@@ -408,6 +426,8 @@ struct hs_batch {
     int32_t copies = 0, cap = 0, chunk = 0;
     int32_t fix_copies = 0, fix_cap = 0, fix_chunk = 0;   // 0: chosen automatically
     int32_t grid = 0, n_items = 0;
+    // alignment pass: hits per work item, in flight per wavefront, workgroups
+    int32_t tchunk = 0, tcap = 0, tgrid = 0, n_titems = 0;
     // graph of one whole search
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -489,11 +509,28 @@ int upload_items(hs_batch* b, hipStream_t st) {
         }
     if ((int64_t)items.size() > b->max_items) return fail(HS_EINVAL, "too many work items");
     b->n_items = (int32_t)items.size();
-    if (!items.empty()) {
+    // alignment items: each query's first n_aln ranks, in ranges of tchunk
+    std::vector<BatchItem> titems;
+    b->tchunk = std::max(b->n_aln, 1);
+    b->tcap = std::min(kLanes, (b->tchunk + kWaves - 1) / kWaves);
+    for (int32_t q : order)
+        for (int32_t lo = 0; lo < b->n_aln; lo += b->tchunk) {
+            BatchItem it;
+            it.q = q;
+            it.lo = (uint32_t)lo;
+            it.hi = (uint32_t)std::min(lo + b->tchunk, b->n_aln);
+            it.pad_ = 0;
+            titems.push_back(it);
+        }
+    if ((int64_t)titems.size() > b->max_titems) return fail(HS_EINVAL, "too many alignment items");
+    b->n_titems = (int32_t)titems.size();
+    if (!items.empty())
         HIP_TRY(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(BatchItem),
                                hipMemcpyHostToDevice, st));
-        HIP_TRY(hipStreamSynchronize(st));
-    }
+    if (!titems.empty())
+        HIP_TRY(hipMemcpyAsync(b->d_titems, titems.data(), titems.size() * sizeof(BatchItem),
+                               hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
     const void* fn = batch_kernel(b->copies, false);
     const size_t lds = batch_lds(b, b->copies);
     int rc = set_lds_limit(fn, lds);
@@ -503,6 +540,12 @@ int upload_items(hs_batch* b, hipStream_t st) {
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds));
     if (per_cu < 1) return fail(HS_ENOMEM, "batch scoring kernel does not fit on a compute unit");
     b->grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * device_cus(), b->n_items));
+    const void* tfn = b->copies == 4 ? (const void*)k_trace_batch<4> : (const void*)k_trace_batch<1>;
+    if ((rc = set_lds_limit(tfn, lds))) return rc;
+    per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tfn, kThreads, lds));
+    if (per_cu < 1) return fail(HS_ENOMEM, "batch alignment kernel does not fit on a compute unit");
+    b->tgrid = (int32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * device_cus(), b->n_titems));
     drop_graph(b);
     return HS_OK;
 }
@@ -563,6 +606,17 @@ int enqueue_batch_score(const hs_batch* b, hipStream_t st, uint64_t* d_cells) {
     return HS_OK;
 }
 
+template <int kCopies>
+void launch_trace_batch(const hs_batch* b, hipStream_t st) {
+    hipLaunchKernelGGL((k_trace_batch<kCopies>), dim3(b->tgrid), dim3(kThreads),
+                       batch_lds(b, kCopies), st, b->db->view(), (const BatchQuery*)b->d_qs,
+                       (const KMatrix*)b->d_mats, (const uint8_t*)b->d_qcodes,
+                       (const BatchItem*)b->d_titems, b->n_titems, b->d_ctr + 1,
+                       (int32_t)batch_prof_bytes(b->cur_max_qlen, kCopies), b->tcap, b->k,
+                       (const DevHit*)b->d_hits, (const int32_t*)b->d_n_hits, b->n_aln,
+                       b->d_alns, b->d_ops, b->ops_stride);
+}
+
 // The whole search of the current batch: scoring, ranking, alignments.
 // Kernel launches only (no allocation, copy or fill), so it can be captured.
 int enqueue_batch(const hs_batch* b, hipStream_t st) {
@@ -571,13 +625,9 @@ int enqueue_batch(const hs_batch* b, hipStream_t st) {
     rc = launch_rank(b->db, st, b->d_scores, b->d_rounds, b->db->n_targets, b->nq, b->k, b->tw(),
                      b->d_hits, b->d_n_hits);
     if (rc) return rc;
-    if (b->n_aln > 0) {
-        const size_t lds = (size_t)profile_copy_bytes(profile_stride(b->cur_max_qlen));
-        hipLaunchKernelGGL(k_traceback_batch, dim3(b->n_aln, b->nq), dim3(64), lds, st,
-                           b->db->view(), (const BatchQuery*)b->d_qs, (const KMatrix*)b->d_mats,
-                           (const uint8_t*)b->d_qcodes, b->nq, b->k, (const DevHit*)b->d_hits,
-                           (const int32_t*)b->d_n_hits, b->n_aln, b->d_alns, b->d_ops,
-                           b->ops_stride);
+    if (b->n_aln > 0 && b->n_titems > 0) {
+        if (b->copies == 4) launch_trace_batch<4>(b, st);
+        else launch_trace_batch<1>(b, st);
         HIP_TRY(hipGetLastError());
     }
     return HS_OK;
@@ -849,16 +899,18 @@ int hs_batch_create(const hs_db* db, int32_t max_nq, int32_t max_qlen, int64_t m
     b->ops_stride = 2 * (int64_t)max_qlen + 2;
     const int64_t chunks = (db->n_queue + min_chunk(db) - 1) / min_chunk(db);
     b->max_items = (int64_t)max_nq * std::max<int64_t>(chunks, 1);
+    b->max_titems = (int64_t)max_nq;
     const size_t nt = (size_t)std::max<int64_t>(db->n_targets, 1);
     const size_t nal = (size_t)max_nq * (size_t)std::max(n_aln, 1);
     // one device allocation, carved below
-    size_t sz[16];
+    size_t sz[20];
     int ns = 0;
     sz[ns++] = align_up((size_t)max_residues);                                // codes
     sz[ns++] = align_up(sizeof(BatchQuery) * max_nq);
     sz[ns++] = align_up(sizeof(KMatrix) * max_nq);
     sz[ns++] = align_up(sizeof(BatchItem) * (size_t)b->max_items);
-    sz[ns++] = kAlign;                                                        // counter
+    sz[ns++] = align_up(sizeof(BatchItem) * (size_t)b->max_titems);
+    sz[ns++] = kAlign;                                                        // counters
     sz[ns++] = align_up(sizeof(int32_t) * nt * max_nq);                       // scores
     sz[ns++] = align_up(sizeof(int32_t) * nt * max_nq);                       // rounds
     sz[ns++] = align_up(sizeof(uint64_t) * 8 * (size_t)std::max<int64_t>(db->n_queue, 1));
@@ -883,6 +935,7 @@ int hs_batch_create(const hs_db* db, int32_t max_nq, int32_t max_qlen, int64_t m
     b->d_qs = (BatchQuery*)p; p += sz[i++];
     b->d_mats = (KMatrix*)p; p += sz[i++];
     b->d_items = (BatchItem*)p; p += sz[i++];
+    b->d_titems = (BatchItem*)p; p += sz[i++];
     b->d_ctr = (uint32_t*)p; p += sz[i++];
     b->d_scores = (int32_t*)p; p += sz[i++];
     b->d_rounds = (int32_t*)p; p += sz[i++];
@@ -896,12 +949,6 @@ int hs_batch_create(const hs_db* db, int32_t max_nq, int32_t max_qlen, int64_t m
     b->d_ops = (uint32_t*)p; p += sz[i++];
     b->d_pos = (int64_t*)p;
     b->d_packed = (uint32_t*)(p + align_up(sizeof(int64_t) * (nal + 1)));
-    int rc = set_lds_limit((const void*)k_traceback_batch,
-                           (size_t)profile_copy_bytes(profile_stride(max_qlen)));
-    if (rc) {
-        free_batch(b);
-        return rc;
-    }
     *out = b;
     return HS_OK;
 }

@@ -521,6 +521,92 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x, int32_t lane
     return x;
 }
 
+// Phases B and C of a wavefront: every slot with a step in progress
+// (`stepping`, window size ss, orientation tl) issues its remaining blocks
+// blk..nblk-1 (as many as fit), counting-sorted by (orientation, ss) so that
+// neighbouring lanes get blocks of equal length; every lane then scores
+// blocks, and the best placement of each step is folded into its slot's key
+// in LDS.
+template <int kCopies>
+__device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool stepping, bool tl,
+                                              int32_t ss, int32_t& blk, int32_t nblk,
+                                              const uint8_t* prof, int32_t ps, int32_t cpb,
+                                              int32_t bias, const uint8_t* __restrict__ letters) {
+    // ---- phase B: issue blocks, sorted by (orientation, ss) ----
+    W.bins[lane] = 0;
+    W.bins[lane + kLanes] = 0;
+    wave_sync();
+    const int32_t want = stepping ? nblk - blk : 0;
+    const int32_t bkey = ss_bin(tl, ss);
+    uint32_t off = 0;
+    if (want > 0) off = atomicAdd(&W.bins[bkey], (uint32_t)want);
+    wave_sync();
+    {
+        // exclusive scan over the 128 bins: lane l owns bins 2l, 2l + 1
+        const uint32_t a0 = W.bins[2 * lane], a1 = W.bins[2 * lane + 1];
+        const uint32_t inc = wave_inclusive_scan(a0 + a1, lane);
+        const uint32_t before = inc - (a0 + a1);
+        wave_sync();
+        W.bins[2 * lane] = before;
+        W.bins[2 * lane + 1] = before + a0;
+    }
+    wave_sync();
+    if (want > 0) {
+        const int32_t start = (int32_t)(W.bins[bkey] + off);
+        int32_t issue = kItemCap - start;
+        issue = issue < 0 ? 0 : (issue > want ? want : issue);
+        for (int32_t b = 0; b < issue; ++b)
+            W.items[start + b] = ((uint32_t)lane << 24) | (uint32_t)(blk + b);
+        blk += issue;
+    }
+    // blocks issued = number of slots' wants, capped
+    uint32_t nw = (uint32_t)(want > 0 ? want : 0);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nw += __shfl_xor(nw, o, kLanes);
+    const int32_t n_items = (int32_t)(nw < (uint32_t)kItemCap ? nw : (uint32_t)kItemCap);
+    wave_sync();
+
+    // ---- phase C: score the blocks; each lane fetches the letters of its
+    // next block before scoring the current one ----
+    {
+        int32_t i = lane;
+        bool have = i < n_items;
+        SlotInfo si;
+        int32_t sl = 0, k0 = 0;
+        BlockFetch f;
+        if (have) {
+            const uint32_t it = W.items[i];
+            sl = (int32_t)(it >> 24);
+            k0 = (int32_t)(it & 0xFFFFFFu) * kBlockDiags;
+            si = W.slots[sl];
+            fetch_block(si, k0, letters, f);
+        }
+        while (have) {
+            const int32_t in = i + kLanes;
+            const bool have_n = in < n_items;
+            SlotInfo si_n;
+            int32_t sl_n = 0, k0_n = 0;
+            BlockFetch f_n;
+            if (have_n) {
+                const uint32_t it = W.items[in];
+                sl_n = (int32_t)(it >> 24);
+                k0_n = (int32_t)(it & 0xFFFFFFu) * kBlockDiags;
+                si_n = W.slots[sl_n];
+                fetch_block(si_n, k0_n, letters, f_n);
+            }
+            const uint64_t key = score_block<kCopies>(prof, ps, cpb, bias, si, k0, f);
+            atomicMax((unsigned long long*)&W.slots[sl].key, (unsigned long long)key);
+            si = si_n;
+            sl = sl_n;
+            k0 = k0_n;
+            f = f_n;
+            i = in;
+            have = have_n;
+        }
+    }
+    wave_sync();
+}
+
 // One wavefront's share of the pairs of one query: hand-out positions below
 // `hi`, taken from the counter `ctr` -- kGrab at a time from a global
 // counter, or (kExact) exactly as many as the wavefront needs from a
@@ -606,79 +692,9 @@ __device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap
         }
         if (__ballot(s.id >= 0) == 0) break;
 
-        // ---- phase B: issue blocks, sorted by (orientation, ss) ----
-        W.bins[lane] = 0;
-        W.bins[lane + kLanes] = 0;
-        wave_sync();
-        const int32_t want = (s.id >= 0 && s.stepping) ? s.nblk - s.blk : 0;
-        const int32_t bkey = ss_bin(s.tl, s.ss);
-        uint32_t off = 0;
-        if (want > 0) off = atomicAdd(&W.bins[bkey], (uint32_t)want);
-        wave_sync();
-        {
-            // exclusive scan over the 128 bins: lane l owns bins 2l, 2l + 1
-            const uint32_t a0 = W.bins[2 * lane], a1 = W.bins[2 * lane + 1];
-            const uint32_t inc = wave_inclusive_scan(a0 + a1, lane);
-            const uint32_t before = inc - (a0 + a1);
-            wave_sync();
-            W.bins[2 * lane] = before;
-            W.bins[2 * lane + 1] = before + a0;
-        }
-        wave_sync();
-        if (want > 0) {
-            const int32_t start = (int32_t)(W.bins[bkey] + off);
-            int32_t issue = kItemCap - start;
-            issue = issue < 0 ? 0 : (issue > want ? want : issue);
-            for (int32_t b = 0; b < issue; ++b)
-                W.items[start + b] = ((uint32_t)lane << 24) | (uint32_t)(s.blk + b);
-            s.blk += issue;
-        }
-        // blocks issued = number of slots' wants, capped
-        uint32_t nw = (uint32_t)(want > 0 ? want : 0);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) nw += __shfl_xor(nw, o, kLanes);
-        const int32_t n_items = (int32_t)(nw < (uint32_t)kItemCap ? nw : (uint32_t)kItemCap);
-        wave_sync();
-
-        // ---- phase C: score the blocks; each lane fetches the letters of its
-        // next block before scoring the current one ----
-        {
-            int32_t i = lane;
-            bool have = i < n_items;
-            SlotInfo si;
-            int32_t sl = 0, k0 = 0;
-            BlockFetch f;
-            if (have) {
-                const uint32_t it = W.items[i];
-                sl = (int32_t)(it >> 24);
-                k0 = (int32_t)(it & 0xFFFFFFu) * kBlockDiags;
-                si = W.slots[sl];
-                fetch_block(si, k0, letters, f);
-            }
-            while (have) {
-                const int32_t in = i + kLanes;
-                const bool have_n = in < n_items;
-                SlotInfo si_n;
-                int32_t sl_n = 0, k0_n = 0;
-                BlockFetch f_n;
-                if (have_n) {
-                    const uint32_t it = W.items[in];
-                    sl_n = (int32_t)(it >> 24);
-                    k0_n = (int32_t)(it & 0xFFFFFFu) * kBlockDiags;
-                    si_n = W.slots[sl_n];
-                    fetch_block(si_n, k0_n, letters, f_n);
-                }
-                const uint64_t key = score_block<kCopies>(prof, ps, cpb, bias, si, k0, f);
-                atomicMax((unsigned long long*)&W.slots[sl].key, (unsigned long long)key);
-                si = si_n;
-                sl = sl_n;
-                k0 = k0_n;
-                f = f_n;
-                i = in;
-                have = have_n;
-            }
-        }
-        wave_sync();
+        // ---- phases B and C ----
+        score_pending<kCopies>(W, lane, s.id >= 0 && s.stepping, s.tl, s.ss, s.blk, s.nblk, prof,
+                               ps, cpb, bias, letters);
     }
 }
 

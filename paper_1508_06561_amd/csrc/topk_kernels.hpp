@@ -53,7 +53,7 @@ struct TopkWs {
 };
 
 // Before the scoring pass: reset the state and the histogram of every query
-// and, if given, a work counter.  The threshold is qs[q].kp.min_score for a
+// and, if given, two work counters (ctr[0], ctr[1]).  The threshold is qs[q].kp.min_score for a
 // batch, min_score otherwise.
 __global__ __launch_bounds__(256) void k_topk_reset(TopkWs w, int32_t min_score,
                                                     const BatchQuery* __restrict__ qs,
@@ -69,7 +69,10 @@ __global__ __launch_bounds__(256) void k_topk_reset(TopkWs w, int32_t min_score,
         s.min_score = qs ? qs[q].kp.min_score : min_score;
         s.pad_[0] = s.pad_[1] = 0;
         w.st[q] = s;
-        if (ctr && q == 0) *ctr = 0;
+        if (ctr && q == 0) {
+            ctr[0] = 0;
+            ctr[1] = 0;
+        }
     }
     uint32_t* h = w.hist + (int64_t)q * kWinBins;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kWinBins; i += gridDim.x * blockDim.x)

@@ -2,7 +2,10 @@
 // pass keeps no per-pair state beyond the score and the winning round (the
 // constant auxiliary space of Section III.B.4); the aligned rows of the top
 // hits are recovered by replaying that round, which is deterministic because
-// every draw is keyed by (seed, target, round, draw index).
+// every draw is keyed by (seed, target, round, draw index).  The replay runs
+// on the scoring pass's own wavefront scheduler and block scorer: each hit
+// is a slot, each step's placements are spread over the lanes in blocks of 8
+// diagonals, and each chosen placement becomes run-length ops.
 #pragma once
 
 #include "device_common.hpp"
@@ -20,143 +23,242 @@ struct DevAln {
     int64_t ops_off;
 };
 
-// Run-length writer that merges adjacent runs of the same op.
-struct OpWriter {
-    uint32_t* out;
-    int32_t n;
-    uint32_t op, len;
-    __device__ __forceinline__ void init(uint32_t* o) { out = o; n = 0; op = 0; len = 0; }
-    __device__ __forceinline__ void emit(uint32_t o, int32_t l) {
-        if (l <= 0) return;
-        if (len && o == op) {
-            len += (uint32_t)l;
-            return;
-        }
-        flush();
-        op = o;
-        len = (uint32_t)l;
-    }
-    __device__ __forceinline__ void flush() {
-        if (len) out[n++] = (len << 2) | op;
-        len = 0;
-    }
+// One alignment being recovered, held in the registers of its lane: the
+// winning round of a hit replayed step by step, each step's placement
+// appended to the alignment's ops.  Plain scalars only, so that the whole
+// state stays in registers.
+struct TraceState {
+    int32_t id;          // target index, -1 when the slot is empty
+    int32_t a;           // alignment index (hits[a], alns[a])
+    int32_t nl, ns;
+    bool tl;             // target is the large sequence
+    int32_t round, t;
+    uint32_t LF, SF;
+    int32_t pL, pS, score;
+    int32_t ss, blk, nblk;
+    bool stepping;
+    int64_t tbase;
+    int32_t dblk;                    // Philox block held in w0..w3 (-1: none)
+    uint64_t w0, w1, w2, w3;
+    uint32_t* out;                   // the alignment's ops
+    int32_t n_ops;
+    uint32_t op, len;                // run being merged
 };
 
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
-    for (int o = kLanes / 2; o > 0; o >>= 1) {
-        const uint64_t y = __shfl_xor(x, o, kLanes);
-        x = y > x ? y : x;
+// random() draw d of the replayed round (same stream as the scoring pass).
+__device__ __forceinline__ uint32_t trace_draw(TraceState& s, uint64_t seed, uint32_t d) {
+    const int32_t b = (int32_t)(d >> 4);
+    if (b != s.dblk) {
+        uint64_t w[4];
+        philox_block(seed, (uint64_t)s.id, (uint32_t)s.round, (uint32_t)b, w);
+        s.w0 = w[0];
+        s.w1 = w[1];
+        s.w2 = w[2];
+        s.w3 = w[3];
+        s.dblk = b;
     }
-    return x;
+    const uint32_t wi = (d >> 2) & 3;
+    const uint64_t x = wi == 0 ? s.w0 : wi == 1 ? s.w1 : wi == 2 ? s.w2 : s.w3;
+    return (uint32_t)(x >> (16 * (d & 3))) & 0xFFFFu;
 }
 
-// Replays the winning round of one hit with the query profile (one copy) in
-// LDS, lanes splitting each step's placements, and writes the alignment as
-// ops oriented (query, target).  Inside the chop-and-consume loop only the
-// small sequence receives gaps (Section III.B.3): the k* skipped letters of
-// large are target letters over gaps (D) when the target is large and query
-// letters over gaps (I) otherwise; after the loop the rest of whichever
+// Appends a run of l ops o, merging it with the previous run of the same op.
+__device__ __forceinline__ void trace_emit(TraceState& s, uint32_t o, int32_t l) {
+    if (l <= 0) return;
+    if (s.len && o == s.op) {
+        s.len += (uint32_t)l;
+        return;
+    }
+    if (s.len) s.out[s.n_ops++] = (s.len << 2) | s.op;
+    s.op = o;
+    s.len = (uint32_t)l;
+}
+
+// Draws the next step of the alignment or, after the last one, writes the
+// alignment: inside the chop-and-consume loop only the small sequence
+// receives gaps (Section III.B.3) -- the k* skipped letters of large are
+// target letters over gaps (D) when the target is large and query letters
+// over gaps (I) otherwise -- and after the loop the rest of whichever
 // sequence is left goes against gaps.
-__device__ __forceinline__ void traceback_one(const DbView& db, const uint8_t* prof, int32_t ps,
-                                              int32_t qlen, const KParams& kp, int32_t bias,
-                                              const DevHit& hit, DevAln* out_aln, uint32_t* ops,
-                                              int64_t ops_off) {
-    const int32_t lane = threadIdx.x;
-    const int32_t id = (int32_t)hit.target_id;
-    const int32_t r = hit.round;
-    if (id < 0 || id >= db.n || r < 0 || r >= kp.rounds) return;   // never for a valid hit
-    const int32_t tlen = db.lens[id];
-    const uint8_t* T = db.letters + db.offsets[id];
-
-    const bool tl = tlen >= qlen;
-    const int32_t nl = tl ? tlen : qlen;
-    const int32_t ns = tl ? qlen : tlen;
-    const uint32_t gap_in_small = tl ? kOpD : kOpI;   // large letter over a gap
-    const uint32_t gap_in_large = tl ? kOpI : kOpD;   // small letter over a gap
-
-    DrawStream ds;
-    ds.init(kp.seed, (uint64_t)id, (uint32_t)r);
-    const uint32_t LF = round_factor(kp.lfactor, kp.minfactor, ds.get(0));
-    const uint32_t SF = round_factor(kp.sfactor, kp.minfactor, ds.get(1));
-    OpWriter w;
-    w.init(ops + ops_off);
-    int32_t pL = 0, pS = 0, t = 0, score = 0;
-    while (pL < nl && pS < ns) {
-        const int32_t ls = window_large(nl - pL, LF);
-        const int32_t ss = window_small(ns - pS, SF, ds.get(2u + (uint32_t)t), ls);
+__device__ __forceinline__ void trace_advance(TraceState& s, const KParams& kp, SlotInfo* slot,
+                                              DevAln* __restrict__ alns, int64_t ops_off) {
+    if (s.id < 0 || s.stepping) return;
+    if (s.pL < s.nl && s.pS < s.ns) {
+        const int32_t ls = window_large(s.nl - s.pL, s.LF);
+        const int32_t ss =
+            window_small(s.ns - s.pS, s.SF, trace_draw(s, kp.seed, 2u + (uint32_t)s.t), ls);
         const int32_t nk = ls - ss + 1;
-        uint64_t best = 0;
-        for (int32_t k = lane; k < nk; k += kLanes) {
-            int32_t D = 0;
-            if (tl) {
-                const uint8_t* col = prof + pS + kPad;
-                for (int32_t j = 0; j < ss; ++j) D += col[(int32_t)T[pL + k + j] * ps + j];
-            } else {
-                const uint8_t* col = prof + pL + k + kPad;
-                for (int32_t j = 0; j < ss; ++j) D += col[(int32_t)T[pS + j] * ps + j];
+        s.ss = ss;
+        s.blk = 0;
+        s.nblk = (nk + kBlockDiags - 1) / kBlockDiags;
+        s.stepping = true;
+        SlotInfo si;
+        si.pL = s.pL;
+        si.pS = s.pS;
+        si.ss_tl = ss | (s.tl ? (int32_t)0x80000000 : 0);
+        si.nk = nk;
+        si.tbase = s.tbase;
+        si.key = 0;
+        *slot = si;
+        return;
+    }
+    s.score -= kp.pgp * ((s.nl - s.pL) + (s.ns - s.pS));
+    trace_emit(s, s.tl ? kOpD : kOpI, s.nl - s.pL);
+    trace_emit(s, s.tl ? kOpI : kOpD, s.ns - s.pS);
+    if (s.len) s.out[s.n_ops++] = (s.len << 2) | s.op;
+    DevAln out;
+    out.target_id = s.id;
+    out.score = s.score;
+    out.n_ops = s.n_ops;
+    out.ops_off = ops_off;
+    alns[s.a] = out;
+    s.id = -1;
+}
+
+// One wavefront's share of the alignments of one query: hit indices below
+// `hi` taken from the workgroup counter `ctr`, at most `cap` in flight.  The
+// winning round of each hit is replayed with the block scorer of the scoring
+// pass (so every step picks the same placement) and alignment a is written
+// to alns[a], its ops to ops[ops_base + a * ops_stride ...].
+template <int kCopies>
+__device__ __forceinline__ void wave_trace(WaveLds& W, int32_t lane, int32_t cap,
+                                           const uint8_t* prof, int32_t ps, int32_t cpb,
+                                           int32_t bias, int32_t qlen, const KParams& kp,
+                                           const DbView& db, const DevHit* __restrict__ hits,
+                                           uint32_t hi, uint32_t* ctr, DevAln* __restrict__ alns,
+                                           uint32_t* __restrict__ ops, int64_t ops_base,
+                                           int64_t ops_stride) {
+    TraceState s;
+    s.id = -1;
+    s.stepping = false;
+    bool exhausted = false;
+    for (;;) {
+        // ---- phase A: apply last step's winner, advance, refill ----
+        if (s.id >= 0 && s.stepping && s.blk >= s.nblk) {
+            const uint64_t key = W.slots[lane].key;
+            const int32_t kb = key_shift(key);
+            s.score += key_score(key) - shift_penalty(kp, s.t, kb);
+            trace_emit(s, s.tl ? kOpD : kOpI, kb);
+            trace_emit(s, kOpM, s.ss);
+            s.pL += kb + s.ss;
+            s.pS += s.ss;
+            ++s.t;
+            s.stepping = false;
+        }
+        trace_advance(s, kp, &W.slots[lane], alns, ops_base + (int64_t)s.a * ops_stride);
+        for (;;) {
+            const bool need = s.id < 0 && !exhausted && lane < cap;
+            const uint64_t mask = __ballot(need);
+            if (!mask) break;
+            const uint32_t cnt = (uint32_t)__popcll(mask);
+            const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1));
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(ctr, cnt);
+            base = __shfl(base, 0, kLanes);
+            const uint32_t a = base + rank;
+            if (need) {
+                if (a < hi) {
+                    const DevHit h = hits[a];
+                    const int32_t id = (int32_t)h.target_id;
+                    if (id >= 0 && id < db.n && h.round >= 0 && h.round < kp.rounds) {
+                        const int32_t tlen = db.lens[id];
+                        s.id = id;
+                        s.a = (int32_t)a;
+                        s.tl = tlen >= qlen;
+                        s.nl = s.tl ? tlen : qlen;
+                        s.ns = s.tl ? qlen : tlen;
+                        s.tbase = db.offsets[id];
+                        s.round = h.round;
+                        s.dblk = -1;
+                        s.LF = round_factor(kp.lfactor, kp.minfactor, trace_draw(s, kp.seed, 0));
+                        s.SF = round_factor(kp.sfactor, kp.minfactor, trace_draw(s, kp.seed, 1));
+                        s.pL = s.pS = s.t = s.score = 0;
+                        s.stepping = false;
+                        s.out = ops + ops_base + (int64_t)a * ops_stride;
+                        s.n_ops = 0;
+                        s.op = 0;
+                        s.len = 0;
+                        trace_advance(s, kp, &W.slots[lane], alns, ops_base + (int64_t)a * ops_stride);
+                    }
+                } else {
+                    exhausted = true;
+                }
             }
-            const uint64_t key = shift_key(D - bias * ss, k);
-            best = key > best ? key : best;
+            if (__ballot(s.id >= 0) != 0) break;
         }
-        best = wave_max_u64(best);
-        const int32_t kb = key_shift(best);
-        score += key_score(best) - shift_penalty(kp, t, kb);
-        if (lane == 0) {
-            w.emit(gap_in_small, kb);
-            w.emit(kOpM, ss);
-        }
-        pL += kb + ss;
-        pS += ss;
-        ++t;
-    }
-    score -= kp.pgp * ((nl - pL) + (ns - pS));
-    if (lane == 0) {
-        w.emit(gap_in_small, nl - pL);
-        w.emit(gap_in_large, ns - pS);
-        w.flush();
-        DevAln out;
-        out.target_id = id;
-        out.score = score;
-        out.n_ops = w.n;
-        out.ops_off = ops_off;
-        *out_aln = out;
+        if (__ballot(s.id >= 0) == 0) break;
+        // ---- phases B and C ----
+        score_pending<kCopies>(W, lane, s.id >= 0 && s.stepping, s.tl, s.ss, s.blk, s.nblk, prof,
+                               ps, cpb, bias, db.letters);
     }
 }
 
-// One wavefront per alignment a < min(n_aln, n_hits) of one query.
-__global__ __launch_bounds__(64) void k_traceback(DbView db, const uint8_t* __restrict__ qcodes,
-                                                  int32_t qlen, KParams kp, KMatrix km,
-                                                  int32_t bias, const DevHit* __restrict__ hits,
-                                                  const int32_t* __restrict__ n_hits, int32_t n_aln,
-                                                  DevAln* __restrict__ alns,
-                                                  uint32_t* __restrict__ ops, int64_t ops_stride) {
-    extern __shared__ __align__(16) uint8_t prof[];
-    const int32_t ps = profile_stride(qlen);
-    build_profile<1>(prof, ps, qcodes, qlen, km, bias);
-    __syncthreads();
-    const int32_t a = blockIdx.x;
-    if (a >= n_aln || a >= *n_hits) return;
-    traceback_one(db, prof, ps, qlen, kp, bias, hits[a], alns + a, ops, (int64_t)a * ops_stride);
-}
-
-// Batch form: alignment a = blockIdx.x of query q = blockIdx.y; query q's
-// hits start at hits[q * k], its alignments at alns[q * n_aln], and the ops
-// of alignment (q, a) at ops[(q * n_aln + a) * ops_stride].
-__global__ __launch_bounds__(64) void k_traceback_batch(
-    DbView db, const BatchQuery* __restrict__ qs, const KMatrix* __restrict__ mats,
-    const uint8_t* __restrict__ qcodes, int32_t nq, int32_t k, const DevHit* __restrict__ hits,
-    const int32_t* __restrict__ n_hits, int32_t n_aln, DevAln* __restrict__ alns,
+// Alignments of one query: workgroup g recovers hits [g * per_wg, (g + 1) *
+// per_wg) below min(n_aln, n_hits), at most `cap` per wavefront at a time.
+template <int kCopies>
+__global__ __launch_bounds__(kThreads) void k_trace_sched(
+    DbView db, const uint8_t* __restrict__ qcodes, int32_t qlen, KParams kp, KMatrix km,
+    int32_t bias, const DevHit* __restrict__ hits, const int32_t* __restrict__ n_hits,
+    int32_t n_aln, int32_t per_wg, int32_t cap, DevAln* __restrict__ alns,
     uint32_t* __restrict__ ops, int64_t ops_stride) {
-    extern __shared__ __align__(16) uint8_t prof[];
-    const int32_t a = blockIdx.x, q = blockIdx.y;
-    if (q >= nq || a >= n_aln || a >= n_hits[q]) return;
-    const BatchQuery Q = qs[q];
-    const int32_t ps = profile_stride(Q.qlen);
-    build_profile<1>(prof, ps, qcodes + Q.qoff, Q.qlen, mats[q], Q.bias);
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ uint32_t s_ctr;
+    const int32_t nh = *n_hits < n_aln ? *n_hits : n_aln;
+    const int32_t lo = blockIdx.x * per_wg;
+    const int32_t hi = lo + per_wg < nh ? lo + per_wg : nh;
+    if (lo >= hi) return;
+    const int32_t ps = profile_stride(qlen);
+    const int32_t cpb = profile_copy_bytes(ps);
+    build_profile<kCopies>(lds, ps, qcodes, qlen, km, bias);
+    if (threadIdx.x == 0) s_ctr = (uint32_t)lo;
     __syncthreads();
-    const int64_t slot = (int64_t)q * n_aln + a;
-    traceback_one(db, prof, ps, Q.qlen, Q.kp, Q.bias, hits[(int64_t)q * k + a], alns + slot, ops,
-                  slot * ops_stride);
+    const int32_t lane = threadIdx.x & (kLanes - 1);
+    WaveLds& W = ((WaveLds*)(lds + kCopies * cpb))[threadIdx.x / kLanes];
+    wave_trace<kCopies>(W, lane, cap, lds, ps, cpb, bias, qlen, kp, db, hits, (uint32_t)hi, &s_ctr,
+                        alns, ops, 0, ops_stride);
+}
+
+// Alignments of a batch, persistent: a workgroup takes work items (query q,
+// hit range [lo, hi)) from the counter, builds the query's profile and
+// recovers the item's hits below min(hi, n_hits[q]).  Query q's hits start at
+// hits[q * k], its alignments at alns[q * n_aln], and the ops of alignment
+// (q, a) at ops[(q * n_aln + a) * ops_stride].
+template <int kCopies>
+__global__ __launch_bounds__(kThreads) void k_trace_batch(
+    DbView db, const BatchQuery* __restrict__ qs, const KMatrix* __restrict__ mats,
+    const uint8_t* __restrict__ qcodes, const BatchItem* __restrict__ items, int32_t n_items,
+    uint32_t* item_ctr, int32_t prof_bytes, int32_t cap, int32_t k,
+    const DevHit* __restrict__ hits, const int32_t* __restrict__ n_hits, int32_t n_aln,
+    DevAln* __restrict__ alns, uint32_t* __restrict__ ops, int64_t ops_stride) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ uint32_t s_item, s_ctr;
+    const int32_t lane = threadIdx.x & (kLanes - 1);
+    WaveLds& W = ((WaveLds*)(lds + prof_bytes))[threadIdx.x / kLanes];
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint32_t it = atomicAdd(item_ctr, 1u);
+            s_item = it;
+            if (it < (uint32_t)n_items) s_ctr = items[it].lo;
+        }
+        __syncthreads();
+        const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it >= (uint32_t)n_items) break;
+        const BatchItem item = items[it];
+        const int32_t q = item.q;
+        const int32_t nh = n_hits[q] < n_aln ? n_hits[q] : n_aln;
+        const uint32_t hi = item.hi < (uint32_t)nh ? item.hi : (uint32_t)nh;
+        if (item.lo < hi) {
+            const BatchQuery Q = qs[q];
+            const int32_t ps = profile_stride(Q.qlen);
+            const int32_t cpb = profile_copy_bytes(ps);
+            build_profile<kCopies>(lds, ps, qcodes + Q.qoff, Q.qlen, mats[q], Q.bias);
+            __syncthreads();
+            wave_trace<kCopies>(W, lane, cap, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, db,
+                                hits + (int64_t)q * k, hi, &s_ctr, alns + (int64_t)q * n_aln, ops,
+                                (int64_t)q * n_aln * ops_stride, ops_stride);
+        }
+        __syncthreads();   // the profile and the counter are rewritten for the next item
+    }
 }
 
 // Packing of a batch's alignments: pos[i] = where alignment slot
