@@ -4,7 +4,8 @@ pair scoring, device ranking (top 500) and alignments of the top 50.
 `--workload batched` measures instead 256 queries of U[30, 1000] residues
 against the 2,020-target database as one batch (one persistent scoring launch,
 replayed from a captured graph), beside the same 256 queries searched one at
-a time.
+a time; `--workload long` does the same for 32 queries of U[2000, 5000]
+residues against that database plus 5,064 targets of 10,000-35,000 residues.
 
 Prints one JSON line.  `value` is query*database residues per second with the
 database and the query resident in device memory when timing starts.  The
@@ -82,22 +83,43 @@ def cpu_baseline(w, q, budget_s):
                       f"one query of {len(q)}, single thread, {dt:.1f} s"}
 
 
-def cpu_baseline_batched(w, budget_s):
-    """Oracle on the first m queries of the batch, m chosen so that the
-    sample takes about budget_s seconds."""
+def cpu_baseline_batched(w, budget_s, stride=1):
+    """Oracle on the first m queries of the batch against every stride-th
+    target, m chosen so that the sample takes about budget_s seconds."""
     import numpy as np
     import oracle as O
     codes = O.encode_db(w.residues, w.offsets)
+    ids = np.arange(0, w.n_targets, stride, dtype=np.int64)
+    tres = int(np.diff(w.offsets)[ids].sum())
     t = time.perf_counter()
     m, res = 0, 0
     while m < len(w.queries) and time.perf_counter() - t < budget_s:
-        O.score_all(codes, w.offsets, O.encode(bytes(w.queries[m])), O.Params())
-        res += len(w.queries[m]) * w.db_residues
+        O.score_all(codes, w.offsets, O.encode(bytes(w.queries[m])), O.Params(),
+                    ids=ids if stride > 1 else None)
+        res += len(w.queries[m]) * tres
         m += 1
     dt = time.perf_counter() - t
+    which = f"every {stride}th target ({len(ids)} of {w.n_targets})" if stride > 1 else \
+        f"all {w.n_targets} targets"
     return {"value": res / dt, "unit": "query*residues/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {m} of {len(w.queries)} queries against all {w.n_targets} targets, "
+            "sample": f"first {m} of {len(w.queries)} queries against {which}, "
                       f"single thread, {dt:.1f} s"}
+
+
+BATCH_WORKLOADS = {
+    "batched": dict(gen="config_batched", metric="batch of 256 queries",
+                    desc="256 queries U[30,1000] vs 2,020 targets U[50,500] (20 planted homologs); "
+                         "top 50 ranked and aligned per query; one persistent scoring launch, "
+                         "graph replay",
+                    data="synthetic (seeded; uniform query lengths, background residue composition)",
+                    cpu_stride=1),
+    "long": dict(gen="config_long", metric="batch of 32 long queries",
+                 desc="32 queries U[2000,5000] vs 2,020 targets U[50,500] plus 5,064 targets "
+                      "U[10000,35000] (64 planted homologs); top 50 ranked and aligned per query; "
+                      "one persistent scoring launch, graph replay",
+                 data="synthetic (seeded; uniform lengths, background residue composition)",
+                 cpu_stride=64),
+}
 
 
 def bench_batched(args):
@@ -107,10 +129,11 @@ def bench_batched(args):
     import paper_1508_06561_amd as H
     import synth
 
-    w = synth.config_batched()
+    spec = BATCH_WORKLOADS[args.workload]
+    w = getattr(synth, spec["gen"])()
     qs = [bytes(q) for q in w.queries]
     nres = sum(map(len, qs))
-    log(f"batched workload: {len(qs)} queries ({nres} residues) vs {w.n_targets} targets, "
+    log(f"{args.workload} workload: {len(qs)} queries ({nres} residues) vs {w.n_targets} targets, "
         f"{w.db_residues} residues")
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
@@ -119,7 +142,7 @@ def bench_batched(args):
     b = H.Batch(db, len(qs), max(map(len, qs)), nres, k=w.k, n_aln=w.n_aln)
     b.set(qs, p)
     log(f"default schedule {b.get_schedule()}")
-    tuned_ms = b.tune(reps=3)
+    tuned_ms = b.tune(reps=3 if args.workload == "batched" else 1)
     sched = b.get_schedule()
     log(f"tuned schedule {sched}: scoring {tuned_ms:.3f} ms")
     for _ in range(args.warmup):
@@ -180,7 +203,7 @@ def bench_batched(args):
 
     qres = nres * w.db_residues
     out = {
-        "metric": "query*DB residues/sec on 1 GPU (batch of 256 queries)",
+        "metric": f"query*DB residues/sec on 1 GPU ({spec['metric']})",
         "value": qres / (ms * 1e-3),
         "unit": "query*residues/s",
         "n_gpus": 1,
@@ -191,10 +214,8 @@ def bench_batched(args):
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
-        "data": "synthetic (seeded; uniform query lengths, background residue composition)",
-        "config": {"workload": "256 queries U[30,1000] vs 2,020 targets U[50,500] "
-                               "(20 planted homologs); top 50 ranked and aligned per query; "
-                               "one persistent scoring launch, graph replay",
+        "data": spec["data"],
+        "config": {"workload": spec["desc"],
                    "query_residues": nres, "db_residues": w.db_residues, "k": w.k,
                    "n_aln": w.n_aln, "schedule": sched,
                    "params": "PGP 0, GOP 10, GEP 5, LFactor 0.5, SFactor 1, MinFactor 0.5, "
@@ -209,7 +230,7 @@ def bench_batched(args):
                      "cells_per_s": cells / (k_ms * 1e-3)},
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline_batched(w, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline_batched(w, args.cpu_budget, spec["cpu_stride"])
         log(f"cpu baseline: {out['cpu_baseline']}")
     b.close()
     db.close()
@@ -223,7 +244,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["full", "batched"], default="full")
+    ap.add_argument("--workload", choices=["full", "batched", "long"], default="full")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device (counter calibration)")
     args = ap.parse_args()
@@ -242,7 +263,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "batched":
+    if args.workload in BATCH_WORKLOADS:
         return bench_batched(args)
 
     import numpy as np

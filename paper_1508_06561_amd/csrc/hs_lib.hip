@@ -284,24 +284,57 @@ int device_cus() {
     return v;
 }
 
+// Wavefronts per workgroup beside a profile region of prof_bytes: as many as
+// fit in LDS (8, 4, 2 or 1; 0 if none), each with its WaveLds record.
+int fit_waves(size_t prof_bytes) {
+    for (int w = kWaves; w >= 1; w >>= 1)
+        if (prof_bytes + sizeof(WaveLds) * w + 16 <= device_lds_limit()) return w;
+    return 0;
+}
+
+// Profile layout of a one-query launch: four copies when they fit beside a
+// full workgroup, else one copy (waves: the workgroup's wavefronts).
+struct QueryLayout {
+    int copies, waves;
+    size_t lds;
+};
+int query_layout(int32_t qlen, QueryLayout* L) {
+    const size_t p4 = (size_t)4 * profile_copy_bytes(profile_stride(qlen));
+    const size_t p1 = (size_t)profile_copy_bytes(profile_stride(qlen));
+    if (fit_waves(p4) == kWaves) {
+        L->copies = 4;
+        L->waves = kWaves;
+        L->lds = p4 + sizeof(WaveLds) * kWaves;
+        return HS_OK;
+    }
+    L->copies = 1;
+    L->waves = fit_waves(p1);
+    if (L->waves < 1) return fail(HS_EINVAL, "query too long for the device's LDS");
+    L->lds = p1 + sizeof(WaveLds) * L->waves;
+    return HS_OK;
+}
+
 template <int kCopies, bool kCount>
 int launch_sched(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParams& kp,
                  const KMatrix& km, int32_t bias, hipStream_t st, const QueryWs& w,
-                 int32_t* d_scores, int32_t* d_rounds, uint64_t* d_cells, int32_t* d_max) {
+                 int32_t* d_scores, int32_t* d_rounds, uint64_t* d_cells, int32_t* d_max,
+                 const QueryLayout& L) {
     const void* fn = (const void*)k_score_sched<kCopies, kCount>;
-    const size_t lds = sched_lds_bytes(qlen, kCopies);
-    int rc = set_lds_limit(fn, lds);
+    const int threads = L.waves * kLanes;
+    int rc = set_lds_limit(fn, L.lds);
     if (rc) return rc;
     int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, L.lds));
     if (per_cu < 1) return fail(HS_ENOMEM, "scoring kernel does not fit on a compute unit");
-    // every workgroup should get at least a quarter of its slots filled
-    // every wavefront should get at least a quarter of its slots filled
-    const int64_t want = (db->n_targets + kThreads / 4 - 1) / (kThreads / 4);
+    // Spread the pairs over every wavefront that can be resident: cap pairs
+    // in flight per wavefront, taken cap at a time, 64 for large databases.
+    const int64_t slots = (int64_t)per_cu * device_cus() * L.waves;
+    const int32_t cap = (int32_t)std::min<int64_t>(kLanes, std::max<int64_t>(1, (db->n_targets + slots - 1) / slots));
+    const int64_t want = (db->n_targets + (int64_t)cap * L.waves - 1) / ((int64_t)cap * L.waves);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * device_cus(), want));
-    hipLaunchKernelGGL((k_score_sched<kCopies, kCount>), dim3(grid), dim3(kThreads), lds, st,
+    hipLaunchKernelGGL((k_score_sched<kCopies, kCount>), dim3(grid), dim3(threads), L.lds, st,
                        (const PairRec*)db->d_recs, (int32_t)db->n_queue, db->d_letters, d_q, qlen,
-                       kp, km, bias, (const uint64_t*)w.draws, w.queue, d_scores, d_rounds,
+                       kp, km, bias, cap, (uint32_t)cap, (const uint64_t*)w.draws, w.queue, d_scores, d_rounds,
                        (unsigned long long*)d_cells, d_max);
     HIP_TRY(hipGetLastError());
     return HS_OK;
@@ -318,14 +351,15 @@ int launch_score(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_par
     hipLaunchKernelGGL(k_draws, dim3((nq + 255) / 256), dim3(256), 0, st, (const PairRec*)db->d_recs, nq,
                        kp.seed, w.draws, w.queue);
     HIP_TRY(hipGetLastError());
-    const bool four = sched_lds_bytes(qlen, 4) <= device_lds_limit();
-    if (!four && sched_lds_bytes(qlen, 1) > device_lds_limit())
-        return fail(HS_EINVAL, "query too long for the device's LDS");
+    QueryLayout L;
+    int rc = query_layout(qlen, &L);
+    if (rc) return rc;
+    const bool four = L.copies == 4;
     if (d_cells)
-        return four ? launch_sched<4, true>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, d_cells, d_max)
-                    : launch_sched<1, true>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, d_cells, d_max);
-    return four ? launch_sched<4, false>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, nullptr, d_max)
-                : launch_sched<1, false>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, nullptr, d_max);
+        return four ? launch_sched<4, true>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, d_cells, d_max, L)
+                    : launch_sched<1, true>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, d_cells, d_max, L);
+    return four ? launch_sched<4, false>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, nullptr, d_max, L)
+                : launch_sched<1, false>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, nullptr, d_max, L);
 }
 
 // Ranking of nq score arrays (query q's scores at scores + q * stride); the
@@ -348,18 +382,19 @@ int launch_rank(const hs_db* db, hipStream_t st, const int32_t* scores, const in
     return HS_OK;
 }
 
-// Alignments of one query's first n_aln hits: one hit per wavefront, eight
-// per workgroup, so that every alignment is recovered at once.
+// Alignments of one query's first n_aln hits: one hit per wavefront, so that
+// every alignment is recovered at once.
 template <int kCopies>
 int launch_trace(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParams& kp,
                  const KMatrix& km, hipStream_t st, const DevHit* d_hits, const int32_t* d_n_hits,
-                 int32_t n_aln, DevAln* d_alns, uint32_t* d_ops, int64_t ops_stride) {
-    constexpr int32_t per_wg = kWaves;
-    const size_t lds = sched_lds_bytes(qlen, kCopies);
-    int rc = set_lds_limit((const void*)k_trace_sched<kCopies>, lds);
+                 int32_t n_aln, DevAln* d_alns, uint32_t* d_ops, int64_t ops_stride,
+                 const QueryLayout& L) {
+    const int32_t per_wg = L.waves;
+    int rc = set_lds_limit((const void*)k_trace_sched<kCopies>, L.lds);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_trace_sched<kCopies>), dim3((n_aln + per_wg - 1) / per_wg), dim3(kThreads),
-                       lds, st, db->view(), d_q, qlen, kp, km, matrix_bias(km), d_hits, d_n_hits,
+    hipLaunchKernelGGL((k_trace_sched<kCopies>), dim3((n_aln + per_wg - 1) / per_wg),
+                       dim3(L.waves * kLanes), L.lds, st, db->view(), d_q, qlen, kp, km,
+                       matrix_bias(km), d_hits, d_n_hits,
                        n_aln, per_wg, 1, d_alns, d_ops, ops_stride);
     HIP_TRY(hipGetLastError());
     return HS_OK;
@@ -379,11 +414,13 @@ int launch_search(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_pa
     if (n_aln > 0) {
         const KParams kp = kparams(p);
         const KMatrix km = kmatrix(p);
-        rc = sched_lds_bytes(qlen, 4) <= device_lds_limit()
+        QueryLayout L;
+        if ((rc = query_layout(qlen, &L))) return rc;
+        rc = L.copies == 4
                  ? launch_trace<4>(db, d_q, qlen, kp, km, st, d_hits, d_n_hits, n_aln, d_alns, d_ops,
-                                   ops_stride)
+                                   ops_stride, L)
                  : launch_trace<1>(db, d_q, qlen, kp, km, st, d_hits, d_n_hits, n_aln, d_alns, d_ops,
-                                   ops_stride);
+                                   ops_stride, L);
         if (rc) return rc;
     }
     return HS_OK;
@@ -426,6 +463,7 @@ struct hs_batch {
     int32_t copies = 0, cap = 0, chunk = 0;
     int32_t fix_copies = 0, fix_cap = 0, fix_chunk = 0;   // 0: chosen automatically
     int32_t grid = 0, n_items = 0;
+    int32_t waves = kWaves;             // wavefronts per workgroup (LDS permitting)
     // alignment pass: hits per work item, in flight per wavefront, workgroups
     int32_t tchunk = 0, tcap = 0, tgrid = 0, n_titems = 0;
     // graph of one whole search
@@ -469,10 +507,10 @@ size_t batch_prof_bytes(int32_t qlen, int copies) {
     return align_up((size_t)copies * profile_copy_bytes(profile_stride(qlen)));
 }
 
-// The batch kernel's LDS for queries up to qlen: profile region, wavefront
-// records and two counters.
-bool copies_fit(int32_t qlen, int copies) {
-    return batch_prof_bytes(qlen, copies) + sizeof(WaveLds) * kWaves + 16 <= device_lds_limit();
+// Whether `copies` profile copies of queries up to qlen fit in LDS beside at
+// least min_waves wavefronts' records.
+bool copies_fit(int32_t qlen, int copies, int min_waves = 1) {
+    return fit_waves(batch_prof_bytes(qlen, copies)) >= min_waves;
 }
 
 template <int kCopies, bool kCount>
@@ -486,7 +524,7 @@ const void* batch_kernel(int copies, bool count) {
 }
 
 size_t batch_lds(const hs_batch* b, int copies) {
-    return batch_prof_bytes(b->cur_max_qlen, copies) + sizeof(WaveLds) * kWaves;
+    return batch_prof_bytes(b->cur_max_qlen, copies) + sizeof(WaveLds) * b->waves;
 }
 
 // Work items for the current queries: longest queries first, each cut into
@@ -512,7 +550,7 @@ int upload_items(hs_batch* b, hipStream_t st) {
     // alignment items: each query's first n_aln ranks, in ranges of tchunk
     std::vector<BatchItem> titems;
     b->tchunk = std::max(b->n_aln, 1);
-    b->tcap = std::min(kLanes, (b->tchunk + kWaves - 1) / kWaves);
+    b->tcap = std::min(kLanes, (b->tchunk + b->waves - 1) / b->waves);
     for (int32_t q : order)
         for (int32_t lo = 0; lo < b->n_aln; lo += b->tchunk) {
             BatchItem it;
@@ -533,17 +571,18 @@ int upload_items(hs_batch* b, hipStream_t st) {
     HIP_TRY(hipStreamSynchronize(st));
     const void* fn = batch_kernel(b->copies, false);
     const size_t lds = batch_lds(b, b->copies);
+    const int threads = b->waves * kLanes;
     int rc = set_lds_limit(fn, lds);
     if (!rc) rc = set_lds_limit(batch_kernel(b->copies, true), lds);
     if (rc) return rc;
     int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds));
     if (per_cu < 1) return fail(HS_ENOMEM, "batch scoring kernel does not fit on a compute unit");
     b->grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * device_cus(), b->n_items));
     const void* tfn = b->copies == 4 ? (const void*)k_trace_batch<4> : (const void*)k_trace_batch<1>;
     if ((rc = set_lds_limit(tfn, lds))) return rc;
     per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tfn, kThreads, lds));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tfn, threads, lds));
     if (per_cu < 1) return fail(HS_ENOMEM, "batch alignment kernel does not fit on a compute unit");
     b->tgrid = (int32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * device_cus(), b->n_titems));
     drop_graph(b);
@@ -554,9 +593,10 @@ int upload_items(hs_batch* b, hipStream_t st) {
 // they fit, 64 pairs in flight per wavefront, and items small enough that
 // every workgroup gets about four.
 int choose_schedule(hs_batch* b, hipStream_t st) {
-    b->copies = b->fix_copies ? b->fix_copies : (copies_fit(b->cur_max_qlen, 4) ? 4 : 1);
+    b->copies = b->fix_copies ? b->fix_copies : (copies_fit(b->cur_max_qlen, 4, kWaves) ? 4 : 1);
     if (!copies_fit(b->cur_max_qlen, b->copies))
         return fail(HS_EINVAL, "profile copies do not fit in LDS for the longest query");
+    b->waves = fit_waves(batch_prof_bytes(b->cur_max_qlen, b->copies));
     b->cap = b->fix_cap ? b->fix_cap : kLanes;
     if (b->fix_chunk) {
         b->chunk = std::max(b->fix_chunk, min_chunk(b->db));
@@ -566,7 +606,7 @@ int choose_schedule(hs_batch* b, hipStream_t st) {
         const size_t lds = batch_lds(b, b->copies);
         int rc = set_lds_limit(fn, lds);
         if (rc) return rc;
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, b->waves * kLanes, lds));
         const int64_t wgs = (int64_t)std::max(per_cu, 1) * device_cus();
         const int64_t want = (int64_t)b->nq * b->db->n_queue / (4 * wgs);
         b->chunk = (int32_t)std::min<int64_t>(round64(std::max<int64_t>(b->db->n_queue, 64)),
@@ -578,7 +618,7 @@ int choose_schedule(hs_batch* b, hipStream_t st) {
 template <int kCopies, bool kCount>
 void launch_batch_kernel(const hs_batch* b, hipStream_t st, uint64_t* d_cells) {
     const hs_db* db = b->db;
-    hipLaunchKernelGGL((k_score_batch<kCopies, kCount>), dim3(b->grid), dim3(kThreads),
+    hipLaunchKernelGGL((k_score_batch<kCopies, kCount>), dim3(b->grid), dim3(b->waves * kLanes),
                        batch_lds(b, kCopies), st, (const BatchQuery*)b->d_qs,
                        (const KMatrix*)b->d_mats, (const uint8_t*)b->d_qcodes,
                        (const BatchItem*)b->d_items, b->n_items, b->d_ctr,
@@ -608,7 +648,7 @@ int enqueue_batch_score(const hs_batch* b, hipStream_t st, uint64_t* d_cells) {
 
 template <int kCopies>
 void launch_trace_batch(const hs_batch* b, hipStream_t st) {
-    hipLaunchKernelGGL((k_trace_batch<kCopies>), dim3(b->tgrid), dim3(kThreads),
+    hipLaunchKernelGGL((k_trace_batch<kCopies>), dim3(b->tgrid), dim3(b->waves * kLanes),
                        batch_lds(b, kCopies), st, b->db->view(), (const BatchQuery*)b->d_qs,
                        (const KMatrix*)b->d_mats, (const uint8_t*)b->d_qcodes,
                        (const BatchItem*)b->d_titems, b->n_titems, b->d_ctr + 1,

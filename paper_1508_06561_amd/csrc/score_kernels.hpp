@@ -608,14 +608,14 @@ __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool ste
 }
 
 // One wavefront's share of the pairs of one query: hand-out positions below
-// `hi`, taken from the counter `ctr` -- kGrab at a time from a global
-// counter, or (kExact) exactly as many as the wavefront needs from a
-// workgroup counter in LDS -- with at most `cap` pairs in flight (lanes
-// 0..cap-1 hold them).  Returns when no pair is left; scores go to
-// scores[target], the best round to rounds[target].  kExact also allows a
-// missing draw table (see pair_draw).
+// `hi`, taken from the counter `ctr` (global, or a workgroup counter in LDS)
+// at least `grab` at a time -- a large grab keeps atomics on a global
+// counter rare, grab 0 takes exactly what the wavefront needs -- with at
+// most `cap` pairs in flight (lanes 0..cap-1 hold them).  Returns when no
+// pair is left; scores go to scores[target], the best round to
+// rounds[target].  kExact allows a missing draw table (see pair_draw).
 template <int kCopies, bool kCount, bool kExact>
-__device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap,
+__device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap, uint32_t grab,
                                            const uint8_t* prof, int32_t ps, int32_t cpb,
                                            int32_t bias, int32_t qlen, const KParams& kp,
                                            const PairRec* __restrict__ recs, uint32_t hi,
@@ -657,7 +657,7 @@ __device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap
             uint32_t qi = q_next + rank;
             q_next += take1;
             if (take1 < cnt) {
-                const uint32_t g = kExact ? cnt - take1 : kGrab;
+                const uint32_t g = cnt - take1 > grab ? cnt - take1 : grab;
                 uint32_t base = 0;
                 if (lane == 0) base = atomicAdd(ctr, g);
                 base = __shfl(base, 0, kLanes);
@@ -713,11 +713,14 @@ __host__ __device__ inline size_t sched_lds_bytes(int32_t qlen, int copies) {
 }
 
 // One query against the whole database: every workgroup holds the query
-// profile, every wavefront pulls pairs from the global queue.
+// profile, every wavefront pulls pairs from the global queue, `grab`
+// positions at a time with at most `cap` in flight (small databases spread
+// thin over all wavefronts, large ones in grabs of 64).
 template <int kCopies, bool kCount>
 __global__ __launch_bounds__(kThreads) void k_score_sched(
     const PairRec* __restrict__ recs, int32_t n, const uint8_t* __restrict__ letters,
     const uint8_t* __restrict__ qcodes, int32_t qlen, KParams kp, KMatrix km, int32_t bias,
+    int32_t cap, uint32_t grab,
     const uint64_t* __restrict__ draws, uint32_t* queue, int32_t* __restrict__ scores,
     int32_t* __restrict__ rounds, unsigned long long* cells_total, int32_t* max_score) {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -731,7 +734,7 @@ __global__ __launch_bounds__(kThreads) void k_score_sched(
     WaveLds& W = ((WaveLds*)(lds + kCopies * cpb))[threadIdx.x / kLanes];
     uint64_t cells = 0;
     int32_t best_seen = INT32_MIN;    // largest pair score written by this lane
-    wave_pairs<kCopies, kCount, false>(W, lane, kLanes, prof, ps, cpb, bias, qlen, kp, recs,
+    wave_pairs<kCopies, kCount, false>(W, lane, cap, grab, prof, ps, cpb, bias, qlen, kp, recs,
                                        (uint32_t)n, letters, draws, queue, scores, rounds, cells,
                                        best_seen);
     if (kCount) {
@@ -780,7 +783,7 @@ __global__ __launch_bounds__(kThreads) void k_score_batch(
         build_profile<kCopies>(lds, ps, qcodes + Q.qoff, Q.qlen, mats[q], Q.bias);
         __syncthreads();
         int32_t best_seen = INT32_MIN;
-        wave_pairs<kCopies, kCount, true>(W, lane, cap, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, recs,
+        wave_pairs<kCopies, kCount, true>(W, lane, cap, 0u, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, recs,
                                           item.hi, letters, Q.table ? draws : nullptr, &s_ctr,
                                           scores + (int64_t)q * stride,
                                           rounds ? rounds + (int64_t)q * stride : nullptr, cells,
