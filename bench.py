@@ -6,6 +6,9 @@ against the 2,020-target database as one batch (one persistent scoring launch,
 replayed from a captured graph), beside the same 256 queries searched one at
 a time; `--workload long` does the same for 32 queries of U[2000, 5000]
 residues against that database plus 5,064 targets of 10,000-35,000 residues.
+`--workload serving` replays Poisson query arrivals at 50, 200 and 500 queries/s
+(lengths log-normal, median 250) into the serving loop over the 2,020-target
+database and reports p50/p99 latency and the sustained rate.
 
 Prints one JSON line.  `value` is query*database residues per second with the
 database and the query resident in device memory when timing starts.  The
@@ -237,6 +240,85 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serving(args):
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_1508_06561_amd as H
+    import synth
+
+    torch.cuda.set_device(0)
+    w0 = synth.config_serving(50, duration_s=0.1)
+    db = H.Database(w0.residues, w0.offsets)
+    srv = H.Server(db, max_batch=64, max_qlen=2000, max_residues=64 * 2000, k=w0.k, n_aln=w0.n_aln)
+    # warm-up: first launches and allocations
+    for i, q in enumerate(w0.queries[:16]):
+        srv.submit(bytes(q), tag=(1 << 40) + i)
+    got = 0
+    while got < min(16, len(w0.queries)):
+        for t in srv.poll(timeout_ms=100):
+            srv.result(t)
+            got += 1
+    rows = []
+    for ri, rate in enumerate(args.rates):
+        w = synth.config_serving(rate, duration_s=args.serve_s)
+        qs = [bytes(q) for q in w.queries]
+        base = (ri + 1) << 32
+        t0 = time.perf_counter()
+
+        def feed():
+            for i, ta in enumerate(w.arrivals):
+                d = t0 + float(ta) - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                srv.submit(qs[i], tag=base + i)
+
+        th = threading.Thread(target=feed)
+        th.start()
+        timings = []
+        while len(timings) < len(qs):
+            for t in srv.poll(timeout_ms=200):
+                _, tm = srv.result(t)
+                timings.append(tm)
+        th.join()
+        lat = np.array([t["total_ms"] for t in timings])
+        start = min(t["submit_ms"] for t in timings)
+        end = max(t["submit_ms"] + t["total_ms"] for t in timings)
+        row = {"rate": rate, "queries": len(qs), "p50_ms": float(np.percentile(lat, 50)),
+               "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+               "sustained_qps": len(qs) / ((end - start) * 1e-3),
+               "mean_batch": float(np.mean([t["batch_size"] for t in timings])),
+               "mean_batch_ms": float(np.mean([t["batch_ms"] for t in timings]))}
+        log(f"rate {rate}/s: {row}")
+        rows.append(row)
+    srv.close()
+    db.close()
+    top = rows[-1]
+    out = {
+        "metric": f"p99 query latency (serving, Poisson {top['rate']} queries/s)",
+        "value": top["p99_ms"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": sum(r["queries"] for r in rows),
+        "warmup": 16,
+        "ms_per_step": top["mean_ms"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded; Poisson arrivals, log-normal query lengths)",
+        "config": {"workload": "Poisson arrivals at 50, 200 and 500 queries/s for "
+                               f"{args.serve_s} s each, |Q| log-normal (median 250, sigma 0.6, "
+                               "clip 20-2,000), vs 2,020 targets U[50,500]; top 500 hits and "
+                               "top 50 alignments per query; continuous batching (at most 64 "
+                               "queries per batch)"},
+        "serving": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,7 +326,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["full", "batched", "long"], default="full")
+    ap.add_argument("--workload", choices=["full", "batched", "long", "serving"], default="full")
+    ap.add_argument("--rates", type=float, nargs="+", default=[50, 200, 500])
+    ap.add_argument("--serve-s", type=float, default=2.0, help="seconds of arrivals per rate")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device (counter calibration)")
     args = ap.parse_args()
@@ -265,6 +349,8 @@ def main():
 
     if args.workload in BATCH_WORKLOADS:
         return bench_batched(args)
+    if args.workload == "serving":
+        return bench_serving(args)
 
     import numpy as np
     import torch

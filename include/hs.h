@@ -102,6 +102,10 @@ typedef struct hs_batch hs_batch;
  * III.B.3); seed 0, no threshold, built-in BLOSUM62. */
 void hs_params_default(hs_params* p);
 
+/* HS_OK if *p is a valid parameter set (ranges above), else HS_EINVAL with
+ * the reason in hs_last_error(). */
+int hs_params_check(const hs_params* p);
+
 /* Copies the built-in BLOSUM62 (Section III.A; 24x24 int8, alphabet order)
  * into out[576]. */
 void hs_builtin_matrix(int8_t* out);
@@ -274,6 +278,62 @@ int hs_search_batch(const hs_db* db, int32_t nq, const char* residues, const int
                     const hs_params* params, int32_t n_params, int32_t k, int32_t n_aln,
                     void* stream, hs_hit* hits, int32_t* n_hits, hs_aln* alns, int32_t* n_alns,
                     uint32_t* ops, int64_t ops_cap, int64_t* ops_used);
+
+/* ---------------------------------------------------------------------------
+ * Serving.  A server owns a batch handle and a worker thread that runs
+ * continuous batching: queries are submitted one at a time (from any thread)
+ * and queue up; whenever the device is free the worker takes every waiting
+ * query, first come first served, that fits the batch footprint fixed at
+ * creation -- at most max_batch queries and max_residues letters in all
+ * (device memory), each at most max_qlen letters (LDS) -- searches them as
+ * one batch on its own stream and publishes each query's results.  Results
+ * are identical to a separate hs_search of the same query and parameters.
+ * ------------------------------------------------------------------------- */
+typedef struct hs_server hs_server;
+
+/* Per-query timing (milliseconds, host steady clock). */
+typedef struct hs_server_timing {
+    double submit_ms;       /* submission time since the server was created */
+    double queue_ms;        /* submission to the start of its batch */
+    double batch_ms;        /* duration of its batch (upload, search, results) */
+    double total_ms;        /* submission to results available */
+    int32_t batch_size;     /* queries in its batch */
+    int32_t pad_;
+} hs_server_timing;
+
+/* Creates a server on the current device for searches returning k ranks and
+ * n_aln alignments per query (limits as in hs_batch_create).  The database
+ * must outlive the server. */
+int hs_server_create(const hs_db* db, int32_t max_batch, int32_t max_qlen, int64_t max_residues,
+                     int32_t k, int32_t n_aln, hs_server** out);
+
+/* Stops the worker after its current batch and releases the server; queries
+ * still waiting are dropped, unclaimed results discarded.  NULL is allowed. */
+int hs_server_free(hs_server* s);
+
+/* Queues one query (host ASCII, 1..max_qlen letters) with its parameters
+ * (copied, matrix included) under a caller-chosen tag that is not pending or
+ * unclaimed.  Validates the letters; returns at once. */
+int hs_server_submit(hs_server* s, const char* query, int32_t qlen, const hs_params* params,
+                     uint64_t tag);
+
+/* Tags of finished queries, oldest first: up to max_tags into tags,
+ * *n_tags set to the count; waits up to timeout_ms for the first one when
+ * none is ready (0: do not wait).  Each finished tag is reported once. */
+int hs_server_poll(hs_server* s, uint64_t* tags, int32_t max_tags, int32_t* n_tags,
+                   int32_t timeout_ms);
+
+/* Results of a finished query, as hs_search reports them (hits: k entries,
+ * alns: n_aln entries, ops_off into ops), and its timing (may be NULL).
+ * Claims the result, except on HS_ENOSPC (*ops_used = size needed).  If the
+ * query's batch failed, returns that error. */
+int hs_server_result(hs_server* s, uint64_t tag, hs_hit* hits, int32_t* n_hits, hs_aln* alns,
+                     int32_t* n_alns, uint32_t* ops, int64_t ops_cap, int64_t* ops_used,
+                     hs_server_timing* timing);
+
+/* Queries waiting, batches run and queries served so far (any pointer may be
+ * NULL). */
+int hs_server_stats(hs_server* s, int64_t* pending, int64_t* batches, int64_t* served);
 
 /* Thread-local description of the last failing call on this thread. */
 const char* hs_last_error(void);

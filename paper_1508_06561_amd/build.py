@@ -19,7 +19,8 @@ HIP_FLAGS = [
 def build(out=LIB, extra=()):
     """Compile every HIP source into one shared library (always recompiles)."""
     cmd = [HIPCC, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           os.path.join(CSRC, "hs_lib.hip"), "-o", out + ".tmp", *extra]
+           os.path.join(CSRC, "hs_lib.hip"), os.path.join(CSRC, "hs_server.cpp"),
+           "-lpthread", "-o", out + ".tmp", *extra]
     subprocess.run(cmd, check=True)
     os.replace(out + ".tmp", out)
     return out

@@ -89,6 +89,10 @@ __constant__ int8_t c_codes[256];
 
 }  // namespace
 
+namespace hs_internal {
+void set_error(const std::string& msg) { g_err = msg; }
+}  // namespace hs_internal
+
 // --------------------------------------------------------------------------
 // database image
 // --------------------------------------------------------------------------
@@ -699,6 +703,8 @@ void hs_params_default(hs_params* p) {
     p->seed = 0;
     p->matrix = nullptr;
 }
+
+int hs_params_check(const hs_params* p) { return check_params(p); }
 
 void hs_builtin_matrix(int8_t* out) {
     if (out) std::memcpy(out, kBlosum62, sizeof(kBlosum62));

@@ -45,6 +45,12 @@ class Aln(ctypes.Structure):
                 ("ops_off", ctypes.c_int64)]
 
 
+class ServerTiming(ctypes.Structure):
+    _fields_ = [("submit_ms", ctypes.c_double), ("queue_ms", ctypes.c_double),
+                ("batch_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("batch_size", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
 HIT_DTYPE = np.dtype([("target_id", np.int64), ("score", np.int32), ("round", np.int32)])
 ALN_DTYPE = np.dtype([("target_id", np.int64), ("score", np.int32), ("n_ops", np.int32),
                       ("ops_off", np.int64)])
@@ -99,6 +105,14 @@ def lib():
                                        P(vp)]
         L.hs_search_batch.argtypes = [vp, i32, vp, P(ctypes.c_int64), P(_CParams), i32, i32, i32,
                                       vp, vp, pi32, vp, pi32, vp, i64, P(ctypes.c_int64)]
+        L.hs_params_check.argtypes = [P(_CParams)]
+        L.hs_server_create.argtypes = [vp, i32, i32, i64, i32, i32, P(vp)]
+        L.hs_server_free.argtypes = [vp]
+        L.hs_server_submit.argtypes = [vp, ctypes.c_char_p, i32, P(_CParams), ctypes.c_uint64]
+        L.hs_server_poll.argtypes = [vp, P(ctypes.c_uint64), i32, pi32, i32]
+        L.hs_server_result.argtypes = [vp, ctypes.c_uint64, vp, pi32, vp, pi32, vp, i64,
+                                       P(ctypes.c_int64), P(ServerTiming)]
+        L.hs_server_stats.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
         L.hs_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -436,3 +450,62 @@ def search_batch(db, queries, params=None, k=50, n_aln=50, stream=None):
                                  alns.ctypes.data, n_alns.ctypes.data_as(P), ops.ctypes.data, cap,
                                  ctypes.byref(used)))
     return _split_batch(nq, k, n_aln, hits, n_hits, alns, n_alns, ops)
+
+
+class Server:
+    """A serving loop (hs_server_*): queries submitted one at a time are
+    searched in continuous batches by a native worker thread."""
+
+    def __init__(self, db, max_batch=64, max_qlen=2000, max_residues=None, k=500, n_aln=50):
+        self.db, self.k, self.n_aln, self.max_qlen = db, k, n_aln, max_qlen
+        h = ctypes.c_void_p()
+        _check(lib().hs_server_create(db._h, max_batch, max_qlen,
+                                      max_residues or max_batch * max_qlen, k, n_aln,
+                                      ctypes.byref(h)))
+        self._h = h
+        self._qlen = {}
+        self._params = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hs_server_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, query, tag, params=None):
+        q = query.encode() if isinstance(query, str) else bytes(query)
+        p = (params or Params()).c()
+        _check(lib().hs_server_submit(self._h, q, len(q), ctypes.byref(p), tag))
+        self._qlen[tag] = len(q)
+
+    def poll(self, max_tags=1024, timeout_ms=0):
+        tags = (ctypes.c_uint64 * max_tags)()
+        n = ctypes.c_int32()
+        _check(lib().hs_server_poll(self._h, tags, max_tags, ctypes.byref(n), timeout_ms))
+        return [int(tags[i]) for i in range(n.value)]
+
+    def result(self, tag):
+        """(Result, timing dict) of a finished query; claims it."""
+        k, na = self.k, self.n_aln
+        hits = np.zeros(k, dtype=HIT_DTYPE)
+        alns = np.zeros(max(na, 1), dtype=ALN_DTYPE)
+        cap = max(1, na * (2 * self._qlen.pop(tag, self.max_qlen) + 2))
+        ops = np.zeros(cap, dtype=np.uint32)
+        nh, nal, used = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        t = ServerTiming()
+        _check(lib().hs_server_result(self._h, tag, hits.ctypes.data, ctypes.byref(nh),
+                                      alns.ctypes.data, ctypes.byref(nal), ops.ctypes.data, cap,
+                                      ctypes.byref(used), ctypes.byref(t)))
+        n_a = nal.value if na > 0 else 0
+        timing = {f: getattr(t, f) for f, _ in ServerTiming._fields_ if f != "pad_"}
+        return Result(hits[:nh.value].copy(), alns[:n_a].copy(), ops[:used.value].copy()), timing
+
+    def stats(self):
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().hs_server_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return dict(pending=a.value, batches=b.value, served=c.value)

@@ -115,3 +115,23 @@ def test_batch_argument_errors_before_device_use():
     assert L.hs_search_batch(None, 1, b"ACD", off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                              ctypes.byref(p), 1, 4, 0, None, None, None, None, None, None, 0,
                              None) == E
+
+
+def test_server_argument_errors_before_device_use():
+    import paper_1508_06561_amd as H
+    L = H.lib()
+    E = H.hs.HS_EINVAL
+    h = ctypes.c_void_p()
+    assert L.hs_server_create(None, 4, 100, 400, 10, 5, ctypes.byref(h)) == E
+    assert L.hs_server_create(ctypes.c_void_p(1), 4, 100, 400, 10, 5, None) == E
+    assert L.hs_server_create(ctypes.c_void_p(1), 0, 100, 400, 10, 5, ctypes.byref(h)) == E
+    p = H.Params().c()
+    assert L.hs_server_submit(None, b"ACD", 3, ctypes.byref(p), 1) == E
+    n = ctypes.c_int32()
+    tags = (ctypes.c_uint64 * 4)()
+    assert L.hs_server_poll(None, tags, 4, ctypes.byref(n), 0) == E
+    assert L.hs_server_stats(None, None, None, None) == E
+    assert L.hs_server_free(None) == 0
+    assert L.hs_params_check(ctypes.byref(p)) == 0
+    assert L.hs_params_check(ctypes.byref(H.Params(gep=-1).c())) == E
+    assert L.hs_params_check(ctypes.byref(H.Params(rounds=0).c())) == E
