@@ -145,9 +145,14 @@ def bench_batched(args):
     b = H.Batch(db, len(qs), max(map(len, qs)), nres, k=w.k, n_aln=w.n_aln)
     b.set(qs, p)
     log(f"default schedule {b.get_schedule()}")
-    tuned_ms = b.tune(reps=3 if args.workload == "batched" else 1)
-    sched = b.get_schedule()
-    log(f"tuned schedule {sched}: scoring {tuned_ms:.3f} ms")
+    if args.schedule:
+        b.schedule(*args.schedule)
+        sched = b.get_schedule()
+        log(f"fixed schedule {sched}")
+    else:
+        tuned_ms = b.tune(reps=3 if args.workload == "batched" else 1)
+        sched = b.get_schedule()
+        log(f"tuned schedule {sched}: scoring {tuned_ms:.3f} ms")
     for _ in range(args.warmup):
         b.run(graph=True)
     torch.cuda.synchronize()
@@ -328,6 +333,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", choices=["full", "batched", "long", "serving"], default="full")
     ap.add_argument("--rates", type=float, nargs="+", default=[50, 200, 500])
+    ap.add_argument("--schedule", type=int, nargs=3, metavar=("COPIES", "CAP", "CHUNK"),
+                    help="batch workloads: fixed schedule instead of the autotuner")
     ap.add_argument("--serve-s", type=float, default=2.0, help="seconds of arrivals per rate")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device (counter calibration)")
