@@ -303,8 +303,8 @@ struct QueryLayout {
     size_t lds;
 };
 int query_layout(int32_t qlen, QueryLayout* L) {
-    const size_t p4 = (size_t)4 * profile_copy_bytes(profile_stride(qlen));
-    const size_t p1 = (size_t)profile_copy_bytes(profile_stride(qlen));
+    const size_t p4 = (size_t)profile_region_bytes(qlen, 4);
+    const size_t p1 = (size_t)profile_region_bytes(qlen, 1);
     if (fit_waves(p4) == kWaves) {
         L->copies = 4;
         L->waves = kWaves;

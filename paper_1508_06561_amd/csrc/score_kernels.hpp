@@ -41,12 +41,22 @@ constexpr int kBins = 128;           // (orientation, ss bucket)
 // Profile layout: copy s (0..kCopies-1) holds column c of row r at byte
 // s * cpb + r * ps + (c + kPad - s).  With four copies, column c is read from
 // copy (c + kPad) & 3 at a 4-aligned offset; with one copy (queries too long
-// for four copies in LDS) reads are unaligned.  Columns outside [0, qlen) and
+// for four copies in LDS) reads are assembled from aligned dwords.  Columns outside [0, qlen) and
 // row kZeroRow are 0.
+// The row stride is an odd number of dwords, so that the 25 rows start in
+// 25 different LDS banks: lanes reading different rows at one column (the
+// blocks of one step) then rarely conflict.
 __host__ __device__ inline int32_t profile_stride(int32_t qlen) {
-    return (qlen + 2 * kPad + 8 + 7) & ~7;
+    const int32_t ps = (qlen + 2 * kPad + 8 + 3) & ~3;
+    return ((ps >> 2) & 1) ? ps : ps + 4;
 }
 __host__ __device__ inline int32_t profile_copy_bytes(int32_t ps) { return kProfRows * ps; }
+
+// LDS bytes of the profile copies, rounded up to 16 so that the 64-bit
+// records placed after them stay aligned.
+__host__ __device__ inline int32_t profile_region_bytes(int32_t qlen, int copies) {
+    return (copies * profile_copy_bytes(profile_stride(qlen)) + 15) & ~15;
+}
 
 template <int kCopies>
 __device__ __forceinline__ void build_profile(uint8_t* prof, int32_t ps, const uint8_t* qcodes,
@@ -110,11 +120,13 @@ struct Bases {
     int32_t v0, v1, v2, v3;
     __device__ __forceinline__ void set(int32_t e, int32_t cpb) {
         if (kCopies == 4) {
-            const int32_t s0 = e & 3, s1 = (e + 1) & 3, s2 = (e + 2) & 3, s3 = (e + 3) & 3;
-            v0 = s0 * cpb + e - s0;
-            v1 = s1 * cpb + e + 1 - s1;
-            v2 = s2 * cpb + e + 2 - s2;
-            v3 = s3 * cpb + e + 3 - s3;
+            // s * cpb + e + v - s = s * (cpb - 1) + e + v; copy indices and
+            // strides fit 24 bits, so the full-rate 24-bit multiply is exact
+            const uint32_t cm = (uint32_t)cpb - 1u;
+            v0 = (int32_t)__umul24((uint32_t)e & 3u, cm) + e;
+            v1 = (int32_t)__umul24((uint32_t)(e + 1) & 3u, cm) + e + 1;
+            v2 = (int32_t)__umul24((uint32_t)(e + 2) & 3u, cm) + e + 2;
+            v3 = (int32_t)__umul24((uint32_t)(e + 3) & 3u, cm) + e + 3;
         } else {
             v0 = e; v1 = e + 1; v2 = e + 2; v3 = e + 3;
         }
@@ -122,15 +134,19 @@ struct Bases {
     __device__ __forceinline__ void advance(int32_t d) { v0 += d; v1 += d; v2 += d; v3 += d; }
 };
 
+// Eight profile bytes at byte address addr.  Four copies: the address is
+// dword aligned.  One copy: three aligned dwords, funnel-shifted by the low
+// two address bits (unaligned 8-byte LDS reads are several times slower).
 template <int kCopies>
 __device__ __forceinline__ uint2 lds8(const uint8_t* prof, int32_t addr) {
     if (kCopies == 4) {
         const uint32_t* p = (const uint32_t*)(prof + addr);
         return make_uint2(p[0], p[1]);
     }
-    uint2 x;
-    __builtin_memcpy(&x, prof + addr, 8);
-    return x;
+    const uint32_t* p = (const uint32_t*)(prof + (addr & ~3));
+    const uint32_t d0 = p[0], d1 = p[1], d2 = p[2];
+    return make_uint2(__builtin_amdgcn_alignbyte(d1, d0, (uint32_t)addr),
+                      __builtin_amdgcn_alignbyte(d2, d1, (uint32_t)addr));
 }
 
 __device__ __forceinline__ uint32_t load4(const uint8_t* p) {
@@ -224,27 +240,29 @@ __device__ __forceinline__ void acc_values(const Acc8& a, uint32_t v[8]) {
 }
 
 // Best placement of a block: byte b holds the biased sum of diagonal
-// k0 + b (kAscending) or k0 + 7 - b; only diagonals below nk are real.  The
-// largest sum wins, the smaller diagonal on ties.
-template <bool kAscending>
-__device__ __forceinline__ uint64_t block_best(const uint32_t v[8], int32_t k0, int32_t nk,
-                                               int32_t off) {
+// k0 + b (ascending) or k0 + 7 - b; only diagonals below nk are real.  The
+// largest sum wins, the smaller diagonal on ties: each real diagonal d gets
+// the key (sum + 1) * 8 + 7 - d (padding diagonals 0), so the largest key
+// names the winner.  Sums stay below 2^28 (at most 15 per letter, windows
+// of at most HS_MAX_SEQ letters), so the keys fit 32 bits.
+__device__ __forceinline__ uint64_t block_best_dir(const uint32_t v[8], int32_t k0, int32_t nk,
+                                                   int32_t off, bool ascending) {
     const int32_t nreal = nk - k0;          // >= 1
-    uint32_t m = 0;
+    uint32_t key[8];
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-        const int32_t d = kAscending ? b : 7 - b;
-        const uint32_t x = d < nreal ? v[b] + 1 : 0u;   // +1: a real diagonal beats a padding one
-        m = x > m ? x : m;
+        const int32_t d = ascending ? b : 7 - b;
+        key[b] = d < nreal ? (v[b] << 3) + (uint32_t)(15 - d) : 0u;
     }
-    int32_t dbest = 7;
-#pragma unroll
-    for (int b = 7; b >= 0; --b) {
-        const int32_t d = kAscending ? b : 7 - b;
-        const uint32_t x = d < nreal ? v[b] + 1 : 0u;
-        dbest = (x == m && d < dbest) ? d : dbest;
-    }
-    return shift_key((int32_t)(m - 1) - off, k0 + dbest);
+    const uint32_t m01 = key[0] > key[1] ? key[0] : key[1];
+    const uint32_t m23 = key[2] > key[3] ? key[2] : key[3];
+    const uint32_t m45 = key[4] > key[5] ? key[4] : key[5];
+    const uint32_t m67 = key[6] > key[7] ? key[6] : key[7];
+    const uint32_t ma = m01 > m23 ? m01 : m23;
+    const uint32_t mb = m45 > m67 ? m45 : m67;
+    const uint32_t m = ma > mb ? ma : mb;
+    const int32_t dbest = 7 - (int32_t)(m & 7u);
+    return shift_key((int32_t)(m >> 3) - 1 - off, k0 + dbest);
 }
 
 // Letters of one block, fetched before it is scored: the run of letters that
@@ -256,83 +274,6 @@ struct BlockFetch {
     int32_t count;
     uint4 first, tail, ramp_in, ramp_out;
 };
-
-// Target is small: cell (k, j) pairs target letter T[j] (row) with query
-// column pL + k + j.  Byte b of the read at letter j is diagonal k0 + b.
-template <int kCopies>
-__device__ __forceinline__ uint64_t block_target_small(const uint8_t* prof, int32_t ps,
-                                                       int32_t cpb, int32_t bias,
-                                                       const BlockFetch& f, int32_t pL, int32_t k0,
-                                                       int32_t ss, int32_t nk) {
-    Acc8 a;
-    a.zero();
-    Bases<kCopies> B;
-    B.set(pL + k0 + kPad, cpb);
-    int32_t sw = 0;
-    run_letters<kCopies>(prof, ps, f.run, ss, f.first, f.tail, B, a, sw);
-    uint32_t v[8];
-    acc_values(a, v);
-    return block_best<true>(v, k0, nk, bias * ss);
-}
-
-// Target is large: letter i (0 <= i < ss + 7) of the block is target letter
-// T[i], meeting query columns pS + i - 7 + b; byte b belongs to diagonal
-// k0 + 7 - b and is a real cell only if 0 <= i - (7 - b) < ss.
-template <int kCopies>
-__device__ __forceinline__ uint64_t block_target_large(const uint8_t* prof, int32_t ps,
-                                                       int32_t cpb, int32_t bias,
-                                                       const BlockFetch& f, const uint8_t* T,
-                                                       int32_t pS, int32_t k0, int32_t ss,
-                                                       int32_t nk) {
-    uint32_t v[8];
-    if (ss >= 7) {
-        Acc8 a;
-        a.zero();
-        Bases<kCopies> B;
-        const int32_t e = pS - 7 + kPad;
-        // entry ramp: letters 0..6, letter i keeps bytes >= 7 - i
-        {
-            B.set(e, cpb);
-            const uint32_t w0 = f.ramp_in.x, w1 = f.ramp_in.y;
-            step_letter<kCopies, 0u, 0xFF000000u>(prof, ps, B.v0, letter_of(w0, 0), a);
-            step_letter<kCopies, 0u, 0xFFFF0000u>(prof, ps, B.v1, letter_of(w0, 1), a);
-            step_letter<kCopies, 0u, 0xFFFFFF00u>(prof, ps, B.v2, letter_of(w0, 2), a);
-            step_letter<kCopies, 0u, 0xFFFFFFFFu>(prof, ps, B.v3, letter_of(w0, 3), a);
-            step_letter<kCopies, 0xFF000000u, 0xFFFFFFFFu>(prof, ps, B.v0 + 4, letter_of(w1, 0), a);
-            step_letter<kCopies, 0xFFFF0000u, 0xFFFFFFFFu>(prof, ps, B.v1 + 4, letter_of(w1, 1), a);
-            step_letter<kCopies, 0xFFFFFF00u, 0xFFFFFFFFu>(prof, ps, B.v2 + 4, letter_of(w1, 2), a);
-            a.flush();
-        }
-        // middle: letters 7 .. ss - 1, every byte real
-        int32_t sw = 0;
-        B.set(e + 7, cpb);
-        run_letters<kCopies>(prof, ps, f.run, f.count, f.first, f.tail, B, a, sw);
-        // exit ramp: letters ss .. ss + 6; letter ss + u keeps bytes < 7 - u
-        {
-            B.set(e + ss, cpb);
-            const uint32_t w0 = f.ramp_out.x, w1 = f.ramp_out.y;
-            step_letter<kCopies, 0xFFFFFFFFu, 0x00FFFFFFu>(prof, ps, B.v0, letter_of(w0, 0), a);
-            step_letter<kCopies, 0xFFFFFFFFu, 0x0000FFFFu>(prof, ps, B.v1, letter_of(w0, 1), a);
-            step_letter<kCopies, 0xFFFFFFFFu, 0x000000FFu>(prof, ps, B.v2, letter_of(w0, 2), a);
-            step_letter<kCopies, 0xFFFFFFFFu, 0u>(prof, ps, B.v3, letter_of(w0, 3), a);
-            step_letter<kCopies, 0x00FFFFFFu, 0u>(prof, ps, B.v0 + 4, letter_of(w1, 0), a);
-            step_letter<kCopies, 0x0000FFFFu, 0u>(prof, ps, B.v1 + 4, letter_of(w1, 1), a);
-            step_letter<kCopies, 0x000000FFu, 0u>(prof, ps, B.v2 + 4, letter_of(w1, 2), a);
-            a.flush();
-        }
-        acc_values(a, v);
-    } else {
-        // short windows: cell by cell from copy 0 (column c at c + kPad)
-#pragma unroll
-        for (int b = 0; b < 8; ++b) v[b] = 0;
-        for (int32_t j = 0; j < ss; ++j) {
-            const uint8_t* col = prof + pS + j + kPad;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) v[7 - m] += col[(int32_t)T[m + j] * ps];
-        }
-    }
-    return block_best<false>(v, k0, nk, bias * ss);
-}
 
 // LDS slot record read by the block scorers.
 struct SlotInfo {
@@ -365,14 +306,69 @@ __device__ __forceinline__ void fetch_block(const SlotInfo& si, int32_t k0,
     }
 }
 
+// Scores one block.  Both orientations share one pass over the unmasked run
+// of letters, so that lanes holding blocks of either orientation run the same
+// loop; blocks of a large target add their masked entry and exit ramps, and
+// short windows of a large target (ss < 7) are summed cell by cell.
 template <int kCopies>
 __device__ __forceinline__ uint64_t score_block(const uint8_t* prof, int32_t ps, int32_t cpb,
                                                 int32_t bias, const SlotInfo& si, int32_t k0,
                                                 const BlockFetch& f) {
     const int32_t ss = si.ss_tl & 0x7FFFFFFF;
-    if (si.ss_tl < 0)
-        return block_target_large<kCopies>(prof, ps, cpb, bias, f, f.run - 7, si.pS, k0, ss, si.nk);
-    return block_target_small<kCopies>(prof, ps, cpb, bias, f, si.pL, k0, ss, si.nk);
+    const bool tl = si.ss_tl < 0;
+    const int32_t off = (int32_t)__umul24((uint32_t)bias, (uint32_t)ss);
+    uint32_t v[8];
+    if (tl && ss < 7) {
+        // short windows: cell by cell from copy 0 (column c at c + kPad)
+        const uint8_t* T = f.run - 7;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) v[b] = 0;
+        for (int32_t j = 0; j < ss; ++j) {
+            const uint8_t* col = prof + si.pS + j + kPad;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) v[7 - m] += col[__umul24((uint32_t)T[m + j], (uint32_t)ps)];
+        }
+        return block_best_dir(v, k0, si.nk, off, false);
+    }
+    Acc8 a;
+    a.zero();
+    Bases<kCopies> B;
+    // large target: letter i of the block meets query columns pS + i - 7 + b
+    const int32_t e = si.pS - 7 + kPad;
+    if (tl) {
+        // entry ramp: letters 0..6, letter i keeps bytes >= 7 - i
+        B.set(e, cpb);
+        const uint32_t w0 = f.ramp_in.x, w1 = f.ramp_in.y;
+        step_letter<kCopies, 0u, 0xFF000000u>(prof, ps, B.v0, letter_of(w0, 0), a);
+        step_letter<kCopies, 0u, 0xFFFF0000u>(prof, ps, B.v1, letter_of(w0, 1), a);
+        step_letter<kCopies, 0u, 0xFFFFFF00u>(prof, ps, B.v2, letter_of(w0, 2), a);
+        step_letter<kCopies, 0u, 0xFFFFFFFFu>(prof, ps, B.v3, letter_of(w0, 3), a);
+        step_letter<kCopies, 0xFF000000u, 0xFFFFFFFFu>(prof, ps, B.v0 + 4, letter_of(w1, 0), a);
+        step_letter<kCopies, 0xFFFF0000u, 0xFFFFFFFFu>(prof, ps, B.v1 + 4, letter_of(w1, 1), a);
+        step_letter<kCopies, 0xFFFFFF00u, 0xFFFFFFFFu>(prof, ps, B.v2 + 4, letter_of(w1, 2), a);
+        a.flush();
+    }
+    // the unmasked run: letters 7 .. ss - 1 of a large target (columns from
+    // pS), or the ss letters of a small target (columns from pL + k0)
+    int32_t sw = 0;
+    B.set(tl ? e + 7 : si.pL + k0 + kPad, cpb);
+    run_letters<kCopies>(prof, ps, f.run, f.count, f.first, f.tail, B, a, sw);
+    if (tl) {
+        // exit ramp: letters ss .. ss + 6; letter ss + u keeps bytes < 7 - u
+        B.set(e + ss, cpb);
+        const uint32_t w0 = f.ramp_out.x, w1 = f.ramp_out.y;
+        step_letter<kCopies, 0xFFFFFFFFu, 0x00FFFFFFu>(prof, ps, B.v0, letter_of(w0, 0), a);
+        step_letter<kCopies, 0xFFFFFFFFu, 0x0000FFFFu>(prof, ps, B.v1, letter_of(w0, 1), a);
+        step_letter<kCopies, 0xFFFFFFFFu, 0x000000FFu>(prof, ps, B.v2, letter_of(w0, 2), a);
+        step_letter<kCopies, 0xFFFFFFFFu, 0u>(prof, ps, B.v3, letter_of(w0, 3), a);
+        step_letter<kCopies, 0x00FFFFFFu, 0u>(prof, ps, B.v0 + 4, letter_of(w1, 0), a);
+        step_letter<kCopies, 0x0000FFFFu, 0u>(prof, ps, B.v1 + 4, letter_of(w1, 1), a);
+        step_letter<kCopies, 0x000000FFu, 0u>(prof, ps, B.v2 + 4, letter_of(w1, 2), a);
+        a.flush();
+    }
+    acc_values(a, v);
+    // byte b is diagonal k0 + b of a small target, k0 + 7 - b of a large one
+    return block_best_dir(v, k0, si.nk, off, !tl);
 }
 
 // A target as handed out by the queue (stored in hand-out order).
@@ -706,11 +702,6 @@ __device__ __forceinline__ int32_t wave_max_i32(int32_t x) {
     return x;
 }
 
-// Dynamic LDS: [profile copies][kWaves x WaveLds].
-__host__ __device__ inline size_t sched_lds_bytes(int32_t qlen, int copies) {
-    const int32_t ps = profile_stride(qlen);
-    return (size_t)copies * profile_copy_bytes(ps) + sizeof(WaveLds) * kWaves;
-}
 
 // One query against the whole database: every workgroup holds the query
 // profile, every wavefront pulls pairs from the global queue, `grab`
@@ -731,7 +722,7 @@ __global__ __launch_bounds__(kThreads) void k_score_sched(
     __syncthreads();   // the only workgroup barrier: wavefronts run independently from here
 
     const int32_t lane = threadIdx.x & (kLanes - 1);
-    WaveLds& W = ((WaveLds*)(lds + kCopies * cpb))[threadIdx.x / kLanes];
+    WaveLds& W = ((WaveLds*)(lds + profile_region_bytes(qlen, kCopies)))[threadIdx.x / kLanes];
     uint64_t cells = 0;
     int32_t best_seen = INT32_MIN;    // largest pair score written by this lane
     wave_pairs<kCopies, kCount, false>(W, lane, cap, grab, prof, ps, cpb, bias, qlen, kp, recs,

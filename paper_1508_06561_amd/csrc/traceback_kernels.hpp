@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_sched(
     if (threadIdx.x == 0) s_ctr = (uint32_t)lo;
     __syncthreads();
     const int32_t lane = threadIdx.x & (kLanes - 1);
-    WaveLds& W = ((WaveLds*)(lds + kCopies * cpb))[threadIdx.x / kLanes];
+    WaveLds& W = ((WaveLds*)(lds + profile_region_bytes(qlen, kCopies)))[threadIdx.x / kLanes];
     wave_trace<kCopies>(W, lane, cap, lds, ps, cpb, bias, qlen, kp, db, hits, (uint32_t)hi, &s_ctr,
                         alns, ops, 0, ops_stride);
 }
