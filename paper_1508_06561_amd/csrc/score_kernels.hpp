@@ -519,21 +519,23 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x, int32_t lane
 
 // Phases B and C of a wavefront: every slot with a step in progress
 // (`stepping`, window size ss, orientation tl) issues its remaining blocks
-// blk..nblk-1 (as many as fit), counting-sorted by (orientation, ss) so that
-// neighbouring lanes get blocks of equal length; every lane then scores
-// blocks, and the best placement of each step is folded into its slot's key
-// in LDS.
+// blk..nblk-1 (as many as fit), counting-sorted by (orientation, ss),
+// longest first, so that neighbouring lanes get blocks of equal length;
+// every lane then scores blocks, and the best placement of each step is
+// folded into its slot's key in LDS.
 template <int kCopies>
 __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool stepping, bool tl,
                                               int32_t ss, int32_t& blk, int32_t nblk,
                                               const uint8_t* prof, int32_t ps, int32_t cpb,
                                               int32_t bias, const uint8_t* __restrict__ letters) {
-    // ---- phase B: issue blocks, sorted by (orientation, ss) ----
+    // ---- phase B: issue blocks, sorted by (orientation, ss) descending ----
     W.bins[lane] = 0;
     W.bins[lane + kLanes] = 0;
     wave_sync();
     const int32_t want = stepping ? nblk - blk : 0;
-    const int32_t bkey = ss_bin(tl, ss);
+    // descending bins: the last, partly filled round of 64 blocks then holds
+    // the shortest blocks rather than the longest
+    const int32_t bkey = (kBins - 1) - ss_bin(tl, ss);
     uint32_t off = 0;
     if (want > 0) off = atomicAdd(&W.bins[bkey], (uint32_t)want);
     wave_sync();
