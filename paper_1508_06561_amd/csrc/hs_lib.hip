@@ -318,12 +318,34 @@ int query_layout(int32_t qlen, QueryLayout* L) {
     return HS_OK;
 }
 
-template <int kCopies, bool kCount>
+// Workgroups of `fn` resident per compute unit at `lds` bytes of LDS.
+int resident_wgs(const void* fn, int threads, size_t lds, int* per_cu) {
+    *per_cu = 0;
+    int rc = set_lds_limit(fn, lds);
+    if (rc) return rc;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, threads, lds));
+    return HS_OK;
+}
+
+// Whether the high-ILP letter loop (more registers per lane) keeps as many
+// workgroups resident as the default loop at this LDS footprint: true when
+// LDS, not registers, bounds residency (long queries), where the extra reads
+// in flight are free.
+int prefer_ilp(const void* fn_default, const void* fn_ilp, int threads, size_t lds, bool* ilp) {
+    int a = 0, b = 0;
+    int rc = resident_wgs(fn_default, threads, lds, &a);
+    if (!rc) rc = resident_wgs(fn_ilp, threads, lds, &b);
+    if (rc) return rc;
+    *ilp = b >= a && b > 0;
+    return HS_OK;
+}
+
+template <int kCopies, bool kCount, bool kIlp>
 int launch_sched(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParams& kp,
                  const KMatrix& km, int32_t bias, hipStream_t st, const QueryWs& w,
                  int32_t* d_scores, int32_t* d_rounds, uint64_t* d_cells, int32_t* d_max,
                  const QueryLayout& L) {
-    const void* fn = (const void*)k_score_sched<kCopies, kCount>;
+    const void* fn = (const void*)k_score_sched<kCopies, kCount, kIlp>;
     const int threads = L.waves * kLanes;
     int rc = set_lds_limit(fn, L.lds);
     if (rc) return rc;
@@ -336,7 +358,7 @@ int launch_sched(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParam
     const int32_t cap = (int32_t)std::min<int64_t>(kLanes, std::max<int64_t>(1, (db->n_targets + slots - 1) / slots));
     const int64_t want = (db->n_targets + (int64_t)cap * L.waves - 1) / ((int64_t)cap * L.waves);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * device_cus(), want));
-    hipLaunchKernelGGL((k_score_sched<kCopies, kCount>), dim3(grid), dim3(threads), L.lds, st,
+    hipLaunchKernelGGL((k_score_sched<kCopies, kCount, kIlp>), dim3(grid), dim3(threads), L.lds, st,
                        (const PairRec*)db->d_recs, (int32_t)db->n_queue, db->d_letters, d_q, qlen,
                        kp, km, bias, cap, (uint32_t)cap, (const uint64_t*)w.draws, w.queue, d_scores, d_rounds,
                        (unsigned long long*)d_cells, d_max);
@@ -359,11 +381,21 @@ int launch_score(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_par
     int rc = query_layout(qlen, &L);
     if (rc) return rc;
     const bool four = L.copies == 4;
-    if (d_cells)
-        return four ? launch_sched<4, true>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, d_cells, d_max, L)
-                    : launch_sched<1, true>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, d_cells, d_max, L);
-    return four ? launch_sched<4, false>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, nullptr, d_max, L)
-                : launch_sched<1, false>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, nullptr, d_max, L);
+    bool ilp = false;
+    rc = four ? prefer_ilp((const void*)k_score_sched<4, false, false>,
+                           (const void*)k_score_sched<4, false, true>, L.waves * kLanes, L.lds, &ilp)
+              : prefer_ilp((const void*)k_score_sched<1, false, false>,
+                           (const void*)k_score_sched<1, false, true>, L.waves * kLanes, L.lds, &ilp);
+    if (rc) return rc;
+#define HS_SCHED(C, K, I, cells) \
+    launch_sched<C, K, I>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, cells, d_max, L)
+    if (d_cells) {
+        if (four) return ilp ? HS_SCHED(4, true, true, d_cells) : HS_SCHED(4, true, false, d_cells);
+        return ilp ? HS_SCHED(1, true, true, d_cells) : HS_SCHED(1, true, false, d_cells);
+    }
+    if (four) return ilp ? HS_SCHED(4, false, true, nullptr) : HS_SCHED(4, false, false, nullptr);
+    return ilp ? HS_SCHED(1, false, true, nullptr) : HS_SCHED(1, false, false, nullptr);
+#undef HS_SCHED
 }
 
 // Ranking of nq score arrays (query q's scores at scores + q * stride); the
@@ -466,6 +498,7 @@ struct hs_batch {
     // schedule: profile copies, pairs in flight per wavefront, positions per item
     int32_t copies = 0, cap = 0, chunk = 0;
     int32_t fix_copies = 0, fix_cap = 0, fix_chunk = 0;   // 0: chosen automatically
+    bool ilp = false;                   // high-ILP letter loop (see prefer_ilp)
     int32_t grid = 0, n_items = 0;
     int32_t waves = kWaves;             // wavefronts per workgroup (LDS permitting)
     // alignment pass: hits per work item, in flight per wavefront, workgroups
@@ -518,13 +551,14 @@ bool copies_fit(int32_t qlen, int copies, int min_waves = 1) {
 }
 
 template <int kCopies, bool kCount>
-const void* batch_fn() {
-    return (const void*)k_score_batch<kCopies, kCount>;
+const void* batch_fn(bool ilp) {
+    return ilp ? (const void*)k_score_batch<kCopies, kCount, true>
+               : (const void*)k_score_batch<kCopies, kCount, false>;
 }
 
-const void* batch_kernel(int copies, bool count) {
-    if (copies == 4) return count ? batch_fn<4, true>() : batch_fn<4, false>();
-    return count ? batch_fn<1, true>() : batch_fn<1, false>();
+const void* batch_kernel(int copies, bool count, bool ilp) {
+    if (copies == 4) return count ? batch_fn<4, true>(ilp) : batch_fn<4, false>(ilp);
+    return count ? batch_fn<1, true>(ilp) : batch_fn<1, false>(ilp);
 }
 
 size_t batch_lds(const hs_batch* b, int copies) {
@@ -573,11 +607,11 @@ int upload_items(hs_batch* b, hipStream_t st) {
         HIP_TRY(hipMemcpyAsync(b->d_titems, titems.data(), titems.size() * sizeof(BatchItem),
                                hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
-    const void* fn = batch_kernel(b->copies, false);
+    const void* fn = batch_kernel(b->copies, false, b->ilp);
     const size_t lds = batch_lds(b, b->copies);
     const int threads = b->waves * kLanes;
     int rc = set_lds_limit(fn, lds);
-    if (!rc) rc = set_lds_limit(batch_kernel(b->copies, true), lds);
+    if (!rc) rc = set_lds_limit(batch_kernel(b->copies, true, b->ilp), lds);
     if (rc) return rc;
     int per_cu = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds));
@@ -602,13 +636,16 @@ int choose_schedule(hs_batch* b, hipStream_t st) {
         return fail(HS_EINVAL, "profile copies do not fit in LDS for the longest query");
     b->waves = fit_waves(batch_prof_bytes(b->cur_max_qlen, b->copies));
     b->cap = b->fix_cap ? b->fix_cap : kLanes;
+    int rc = prefer_ilp(batch_kernel(b->copies, false, false), batch_kernel(b->copies, false, true),
+                        b->waves * kLanes, batch_lds(b, b->copies), &b->ilp);
+    if (rc) return rc;
     if (b->fix_chunk) {
         b->chunk = std::max(b->fix_chunk, min_chunk(b->db));
     } else {
         int per_cu = 0;
-        const void* fn = batch_kernel(b->copies, false);
+        const void* fn = batch_kernel(b->copies, false, b->ilp);
         const size_t lds = batch_lds(b, b->copies);
-        int rc = set_lds_limit(fn, lds);
+        rc = set_lds_limit(fn, lds);
         if (rc) return rc;
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, b->waves * kLanes, lds));
         const int64_t wgs = (int64_t)std::max(per_cu, 1) * device_cus();
@@ -619,10 +656,10 @@ int choose_schedule(hs_batch* b, hipStream_t st) {
     return upload_items(b, st);
 }
 
-template <int kCopies, bool kCount>
+template <int kCopies, bool kCount, bool kIlp>
 void launch_batch_kernel(const hs_batch* b, hipStream_t st, uint64_t* d_cells) {
     const hs_db* db = b->db;
-    hipLaunchKernelGGL((k_score_batch<kCopies, kCount>), dim3(b->grid), dim3(b->waves * kLanes),
+    hipLaunchKernelGGL((k_score_batch<kCopies, kCount, kIlp>), dim3(b->grid), dim3(b->waves * kLanes),
                        batch_lds(b, kCopies), st, (const BatchQuery*)b->d_qs,
                        (const KMatrix*)b->d_mats, (const uint8_t*)b->d_qcodes,
                        (const BatchItem*)b->d_items, b->n_items, b->d_ctr,
@@ -639,12 +676,17 @@ int enqueue_batch_score(const hs_batch* b, hipStream_t st, uint64_t* d_cells) {
                        (const BatchQuery*)b->d_qs, b->d_ctr);
     HIP_TRY(hipGetLastError());
     if (b->db->n_targets == 0 || b->n_items == 0) return HS_OK;
+    const bool c = d_cells != nullptr;
     if (b->copies == 4) {
-        if (d_cells) launch_batch_kernel<4, true>(b, st, d_cells);
-        else launch_batch_kernel<4, false>(b, st, nullptr);
+        if (b->ilp) c ? launch_batch_kernel<4, true, true>(b, st, d_cells)
+                      : launch_batch_kernel<4, false, true>(b, st, nullptr);
+        else c ? launch_batch_kernel<4, true, false>(b, st, d_cells)
+               : launch_batch_kernel<4, false, false>(b, st, nullptr);
     } else {
-        if (d_cells) launch_batch_kernel<1, true>(b, st, d_cells);
-        else launch_batch_kernel<1, false>(b, st, nullptr);
+        if (b->ilp) c ? launch_batch_kernel<1, true, true>(b, st, d_cells)
+                      : launch_batch_kernel<1, false, true>(b, st, nullptr);
+        else c ? launch_batch_kernel<1, true, false>(b, st, d_cells)
+               : launch_batch_kernel<1, false, false>(b, st, nullptr);
     }
     HIP_TRY(hipGetLastError());
     return HS_OK;

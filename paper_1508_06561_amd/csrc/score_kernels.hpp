@@ -95,10 +95,11 @@ struct Acc8 {
         for (int i = 0; i < 8; ++i) w[i] = 0;
     }
     __device__ __forceinline__ void flush() {
+        // odd bytes 1 and 3 moved to 16-bit lanes in one byte permute
         h0 += b0 & 0x00FF00FFu;
-        h1 += (b0 >> 8) & 0x00FF00FFu;
+        h1 += __builtin_amdgcn_perm(0u, b0, 0x0c030c01u);
         h2 += b1 & 0x00FF00FFu;
-        h3 += (b1 >> 8) & 0x00FF00FFu;
+        h3 += __builtin_amdgcn_perm(0u, b1, 0x0c030c01u);
         b0 = b1 = 0;
     }
     // 16-bit lanes stay below 65536 for 4096 letters (4096 * 15)
@@ -172,6 +173,18 @@ __device__ __forceinline__ void step_letter(const uint8_t* prof, int32_t ps, int
     if (kMaskHi) a.b1 += x.y & kMaskHi;
 }
 
+// Profile row r of one letter of the unmasked run: `o` is the aligned
+// offset of this letter position's read in row 0, plus `m` bytes (one copy:
+// the low bits of `sh` give the byte offset within the aligned read).
+template <int kCopies>
+__device__ __forceinline__ uint2 row8(const uint8_t* prof, uint32_t o, int32_t m, int32_t ps,
+                                      uint32_t sh, uint32_t r) {
+    const uint32_t* p = (const uint32_t*)(prof + __umul24(r, (uint32_t)ps) + o) + (m >> 2);
+    if (kCopies == 4) return make_uint2(p[0], p[1]);
+    const uint32_t d0 = p[0], d1 = p[1], d2 = p[2];
+    return make_uint2(__builtin_amdgcn_alignbyte(d1, d0, sh), __builtin_amdgcn_alignbyte(d2, d1, sh));
+}
+
 __device__ __forceinline__ uint32_t pick4(const uint4& w, int32_t i) {
     return i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w;
 }
@@ -179,29 +192,75 @@ __device__ __forceinline__ uint32_t pick4(const uint4& w, int32_t i) {
 // Unmasked run of `count` letters starting at T with read bases B.  Letters
 // come 16 at a time, fetched one chunk ahead; `first` holds letters 0..15 and
 // `tail` the 16 letters from count & ~15 on, both fetched by the caller.
-template <int kCopies>
+// kIlp issues the sixteen profile reads of a chunk before summing them: more
+// reads in flight for more registers (three wavefronts per SIMD instead of
+// four), which pays for long blocks only.
+template <int kCopies, bool kIlp = false>
 __device__ __forceinline__ void run_letters(const uint8_t* prof, int32_t ps, const uint8_t* T,
                                             int32_t count, uint4 first, uint4 tail,
                                             Bases<kCopies>& B, Acc8& a, int32_t& since_widen) {
     const int32_t n16 = count >> 4;
-    uint4 wn = first;
-    for (int32_t q = 0; q < n16; ++q) {
-        const uint4 w = wn;
-        T += 16;
-        wn = load16(T);          // the letter array is padded, so this stays in range
+    if (kIlp && n16 > 0) {
+        // one LDS pointer per letter position mod 4 (aligned down with one
+        // copy, the low address bits then select the bytes), so that a
+        // letter's address is one multiply-add and the position within the
+        // chunk folds into the read's offset
+        const uint32_t am = kCopies == 4 ? ~0u : ~3u;
+        uint32_t o0 = (uint32_t)B.v0 & am, o1 = (uint32_t)B.v1 & am;
+        uint32_t o2 = (uint32_t)B.v2 & am, o3 = (uint32_t)B.v3 & am;
+        const uint32_t s0 = (uint32_t)B.v0 & 3u, s1 = (uint32_t)B.v1 & 3u;
+        const uint32_t s2 = (uint32_t)B.v2 & 3u, s3 = (uint32_t)B.v3 & 3u;
+        uint4 wn = first;
+        for (int32_t q = 0; q < n16; ++q) {
+            const uint4 w = wn;
+            T += 16;
+            wn = load16(T);      // the letter array is padded, so this stays in range
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const uint32_t wm = pick4(w, m);
-            step_letter<kCopies>(prof, ps, B.v0 + 4 * m, letter_of(wm, 0), a);
-            step_letter<kCopies>(prof, ps, B.v1 + 4 * m, letter_of(wm, 1), a);
-            step_letter<kCopies>(prof, ps, B.v2 + 4 * m, letter_of(wm, 2), a);
-            step_letter<kCopies>(prof, ps, B.v3 + 4 * m, letter_of(wm, 3), a);
+            for (int m = 0; m < 4; ++m) {
+                // the four letters of a dword: reads first, then the sums
+                const uint32_t wm = pick4(w, m);
+                const uint2 x0 = row8<kCopies>(prof, o0, 4 * m, ps, s0, letter_of(wm, 0));
+                const uint2 x1 = row8<kCopies>(prof, o1, 4 * m, ps, s1, letter_of(wm, 1));
+                const uint2 x2 = row8<kCopies>(prof, o2, 4 * m, ps, s2, letter_of(wm, 2));
+                const uint2 x3 = row8<kCopies>(prof, o3, 4 * m, ps, s3, letter_of(wm, 3));
+                a.b0 += (x0.x + x1.x) + (x2.x + x3.x);
+                a.b1 += (x0.y + x1.y) + (x2.y + x3.y);
+            }
+            // advance the four offsets after this chunk's reads: as one
+            // induction variable they would cost an extra add per letter
+            asm volatile(
+                "v_add_u32 %0, 16, %0\n\t"
+                "v_add_u32 %1, 16, %1\n\t"
+                "v_add_u32 %2, 16, %2\n\t"
+                "v_add_u32 %3, 16, %3"
+                : "+v"(o0), "+v"(o1), "+v"(o2), "+v"(o3));
+            a.flush();
+            if (++since_widen == 256) {
+                a.widen();
+                since_widen = 0;
+            }
         }
-        B.advance(16);
-        a.flush();
-        if (++since_widen == 256) {
-            a.widen();
-            since_widen = 0;
+        B.advance(16 * n16);
+    } else {
+        uint4 wn = first;
+        for (int32_t q = 0; q < n16; ++q) {
+            const uint4 w = wn;
+            T += 16;
+            wn = load16(T);          // the letter array is padded, so this stays in range
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const uint32_t wm = pick4(w, m);
+                step_letter<kCopies>(prof, ps, B.v0 + 4 * m, letter_of(wm, 0), a);
+                step_letter<kCopies>(prof, ps, B.v1 + 4 * m, letter_of(wm, 1), a);
+                step_letter<kCopies>(prof, ps, B.v2 + 4 * m, letter_of(wm, 2), a);
+                step_letter<kCopies>(prof, ps, B.v3 + 4 * m, letter_of(wm, 3), a);
+            }
+            B.advance(16);
+            a.flush();
+            if (++since_widen == 256) {
+                a.widen();
+                since_widen = 0;
+            }
         }
     }
     const int32_t n4 = (count >> 2) & 3;
@@ -310,7 +369,7 @@ __device__ __forceinline__ void fetch_block(const SlotInfo& si, int32_t k0,
 // of letters, so that lanes holding blocks of either orientation run the same
 // loop; blocks of a large target add their masked entry and exit ramps, and
 // short windows of a large target (ss < 7) are summed cell by cell.
-template <int kCopies>
+template <int kCopies, bool kIlp = false>
 __device__ __forceinline__ uint64_t score_block(const uint8_t* prof, int32_t ps, int32_t cpb,
                                                 int32_t bias, const SlotInfo& si, int32_t k0,
                                                 const BlockFetch& f) {
@@ -352,7 +411,7 @@ __device__ __forceinline__ uint64_t score_block(const uint8_t* prof, int32_t ps,
     // pS), or the ss letters of a small target (columns from pL + k0)
     int32_t sw = 0;
     B.set(tl ? e + 7 : si.pL + k0 + kPad, cpb);
-    run_letters<kCopies>(prof, ps, f.run, f.count, f.first, f.tail, B, a, sw);
+    run_letters<kCopies, kIlp>(prof, ps, f.run, f.count, f.first, f.tail, B, a, sw);
     if (tl) {
         // exit ramp: letters ss .. ss + 6; letter ss + u keeps bytes < 7 - u
         B.set(e + ss, cpb);
@@ -523,7 +582,7 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x, int32_t lane
 // longest first, so that neighbouring lanes get blocks of equal length;
 // every lane then scores blocks, and the best placement of each step is
 // folded into its slot's key in LDS.
-template <int kCopies>
+template <int kCopies, bool kIlp = false>
 __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool stepping, bool tl,
                                               int32_t ss, int32_t& blk, int32_t nblk,
                                               const uint8_t* prof, int32_t ps, int32_t cpb,
@@ -592,7 +651,7 @@ __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool ste
                 si_n = W.slots[sl_n];
                 fetch_block(si_n, k0_n, letters, f_n);
             }
-            const uint64_t key = score_block<kCopies>(prof, ps, cpb, bias, si, k0, f);
+            const uint64_t key = score_block<kCopies, kIlp>(prof, ps, cpb, bias, si, k0, f);
             atomicMax((unsigned long long*)&W.slots[sl].key, (unsigned long long)key);
             si = si_n;
             sl = sl_n;
@@ -612,7 +671,7 @@ __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool ste
 // most `cap` pairs in flight (lanes 0..cap-1 hold them).  Returns when no
 // pair is left; scores go to scores[target], the best round to
 // rounds[target].  kExact allows a missing draw table (see pair_draw).
-template <int kCopies, bool kCount, bool kExact>
+template <int kCopies, bool kCount, bool kExact, bool kIlp>
 __device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap, uint32_t grab,
                                            const uint8_t* prof, int32_t ps, int32_t cpb,
                                            int32_t bias, int32_t qlen, const KParams& kp,
@@ -691,8 +750,8 @@ __device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap
         if (__ballot(s.id >= 0) == 0) break;
 
         // ---- phases B and C ----
-        score_pending<kCopies>(W, lane, s.id >= 0 && s.stepping, s.tl, s.ss, s.blk, s.nblk, prof,
-                               ps, cpb, bias, letters);
+        score_pending<kCopies, kIlp>(W, lane, s.id >= 0 && s.stepping, s.tl, s.ss, s.blk, s.nblk,
+                                     prof, ps, cpb, bias, letters);
     }
 }
 
@@ -709,7 +768,7 @@ __device__ __forceinline__ int32_t wave_max_i32(int32_t x) {
 // profile, every wavefront pulls pairs from the global queue, `grab`
 // positions at a time with at most `cap` in flight (small databases spread
 // thin over all wavefronts, large ones in grabs of 64).
-template <int kCopies, bool kCount>
+template <int kCopies, bool kCount, bool kIlp>
 __global__ __launch_bounds__(kThreads) void k_score_sched(
     const PairRec* __restrict__ recs, int32_t n, const uint8_t* __restrict__ letters,
     const uint8_t* __restrict__ qcodes, int32_t qlen, KParams kp, KMatrix km, int32_t bias,
@@ -727,9 +786,9 @@ __global__ __launch_bounds__(kThreads) void k_score_sched(
     WaveLds& W = ((WaveLds*)(lds + profile_region_bytes(qlen, kCopies)))[threadIdx.x / kLanes];
     uint64_t cells = 0;
     int32_t best_seen = INT32_MIN;    // largest pair score written by this lane
-    wave_pairs<kCopies, kCount, false>(W, lane, cap, grab, prof, ps, cpb, bias, qlen, kp, recs,
-                                       (uint32_t)n, letters, draws, queue, scores, rounds, cells,
-                                       best_seen);
+    wave_pairs<kCopies, kCount, false, kIlp>(W, lane, cap, grab, prof, ps, cpb, bias, qlen, kp,
+                                             recs, (uint32_t)n, letters, draws, queue, scores,
+                                             rounds, cells, best_seen);
     if (kCount) {
         for (int o = kLanes / 2; o > 0; o >>= 1) cells += __shfl_xor(cells, o, kLanes);
         if (lane == 0) atomicAdd(cells_total, (unsigned long long)cells);
@@ -746,7 +805,7 @@ __global__ __launch_bounds__(kThreads) void k_score_sched(
 // profile, then its wavefronts pull the item's pairs from a counter in LDS,
 // at most `cap` in flight per wavefront.  Query q's scores go to
 // scores[q * stride + target], its maximum score to max_score[q * ms_stride].
-template <int kCopies, bool kCount>
+template <int kCopies, bool kCount, bool kIlp>
 __global__ __launch_bounds__(kThreads) void k_score_batch(
     const BatchQuery* __restrict__ qs, const KMatrix* __restrict__ mats,
     const uint8_t* __restrict__ qcodes, const BatchItem* __restrict__ items, int32_t n_items,
@@ -776,11 +835,12 @@ __global__ __launch_bounds__(kThreads) void k_score_batch(
         build_profile<kCopies>(lds, ps, qcodes + Q.qoff, Q.qlen, mats[q], Q.bias);
         __syncthreads();
         int32_t best_seen = INT32_MIN;
-        wave_pairs<kCopies, kCount, true>(W, lane, cap, 0u, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, recs,
-                                          item.hi, letters, Q.table ? draws : nullptr, &s_ctr,
-                                          scores + (int64_t)q * stride,
-                                          rounds ? rounds + (int64_t)q * stride : nullptr, cells,
-                                          best_seen);
+        wave_pairs<kCopies, kCount, true, kIlp>(W, lane, cap, 0u, lds, ps, cpb, Q.bias, Q.qlen,
+                                                Q.kp, recs, item.hi, letters,
+                                                Q.table ? draws : nullptr, &s_ctr,
+                                                scores + (int64_t)q * stride,
+                                                rounds ? rounds + (int64_t)q * stride : nullptr,
+                                                cells, best_seen);
         best_seen = wave_max_i32(best_seen);
         if (lane == 0 && best_seen != INT32_MIN) atomicMax(max_score + (int64_t)q * ms_stride, best_seen);
         __syncthreads();   // the profile and the counter are rewritten for the next item
