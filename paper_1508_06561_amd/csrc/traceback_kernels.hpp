@@ -188,8 +188,10 @@ __device__ __forceinline__ void wave_trace(WaveLds& W, int32_t lane, int32_t cap
         }
         if (__ballot(s.id >= 0) == 0) break;
         // ---- phases B and C ----
-        score_pending<kCopies>(W, lane, s.id >= 0 && s.stepping, s.tl, s.ss, s.blk, s.nblk, prof,
-                               ps, cpb, bias, db.letters);
+        // a few hits run on an otherwise idle device: latency, not occupancy,
+        // bounds the replay, so it takes the high-ILP letter loop
+        score_pending<kCopies, true>(W, lane, s.id >= 0 && s.stepping, s.tl, s.ss, s.blk, s.nblk,
+                                     prof, ps, cpb, bias, db.letters);
     }
 }
 
