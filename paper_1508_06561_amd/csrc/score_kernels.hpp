@@ -598,11 +598,13 @@ __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool ste
     uint32_t off = 0;
     if (want > 0) off = atomicAdd(&W.bins[bkey], (uint32_t)want);
     wave_sync();
+    uint32_t nw;   // blocks wanted by all slots = the scan's total
     {
         // exclusive scan over the 128 bins: lane l owns bins 2l, 2l + 1
         const uint32_t a0 = W.bins[2 * lane], a1 = W.bins[2 * lane + 1];
         const uint32_t inc = wave_inclusive_scan(a0 + a1, lane);
         const uint32_t before = inc - (a0 + a1);
+        nw = (uint32_t)__builtin_amdgcn_readlane((int)inc, kLanes - 1);
         wave_sync();
         W.bins[2 * lane] = before;
         W.bins[2 * lane + 1] = before + a0;
@@ -617,9 +619,6 @@ __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool ste
         blk += issue;
     }
     // blocks issued = number of slots' wants, capped
-    uint32_t nw = (uint32_t)(want > 0 ? want : 0);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) nw += __shfl_xor(nw, o, kLanes);
     const int32_t n_items = (int32_t)(nw < (uint32_t)kItemCap ? nw : (uint32_t)kItemCap);
     wave_sync();
 
@@ -722,10 +721,13 @@ __device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap
                 q_next = base + (cnt - take1);
                 q_end = base + g;
             }
-            if (need) {
-                if (qi < hi && recs[qi].id >= 0) {
-                    const PairRec r = recs[qi];
-                    s.dw = (!kExact || draws != nullptr) ? draws[(int64_t)qi * 8] : 0ull;
+            if (need && qi < hi) {
+                // the record and the first draw word load together (the
+                // draw word of a padding position is read and ignored)
+                const PairRec r = recs[qi];
+                const uint64_t dw0 = (!kExact || draws != nullptr) ? draws[(int64_t)qi * 8] : 0ull;
+                if (r.id >= 0) {
+                    s.dw = dw0;
                     s.dw_i = 0;
                     s.pf_i = 0xFFFFFFFFu;
                     s.id = r.id;
@@ -741,9 +743,9 @@ __device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap
                     start_round<kExact>(s, kp, draws);
                     advance_pair<kCount, kExact>(s, kp, draws, &W.slots[lane], scores, rounds,
                                                  cells, best_seen);
-                } else if (qi >= hi) {
-                    exhausted = true;
                 }
+            } else if (need) {
+                exhausted = true;
             }
             if (__ballot(s.id >= 0) != 0) break;
         }
