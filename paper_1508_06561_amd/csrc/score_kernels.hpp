@@ -766,12 +766,18 @@ __device__ __forceinline__ int32_t wave_max_i32(int32_t x) {
 }
 
 
+// The default scoring kernels ask for four wavefronts per SIMD (at most 128
+// VGPRs): below that occupancy the phases' latency is no longer hidden.  The
+// high-ILP variants run where LDS already limits residency, and take the
+// registers their reads in flight need.
+//
 // One query against the whole database: every workgroup holds the query
 // profile, every wavefront pulls pairs from the global queue, `grab`
 // positions at a time with at most `cap` in flight (small databases spread
 // thin over all wavefronts, large ones in grabs of 64).
 template <int kCopies, bool kCount, bool kIlp>
-__global__ __launch_bounds__(kThreads) void k_score_sched(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kIlp ? 1 : 4)))
+void k_score_sched(
     const PairRec* __restrict__ recs, int32_t n, const uint8_t* __restrict__ letters,
     const uint8_t* __restrict__ qcodes, int32_t qlen, KParams kp, KMatrix km, int32_t bias,
     int32_t cap, uint32_t grab,
@@ -808,7 +814,8 @@ __global__ __launch_bounds__(kThreads) void k_score_sched(
 // at most `cap` in flight per wavefront.  Query q's scores go to
 // scores[q * stride + target], its maximum score to max_score[q * ms_stride].
 template <int kCopies, bool kCount, bool kIlp>
-__global__ __launch_bounds__(kThreads) void k_score_batch(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kIlp ? 1 : 4)))
+void k_score_batch(
     const BatchQuery* __restrict__ qs, const KMatrix* __restrict__ mats,
     const uint8_t* __restrict__ qcodes, const BatchItem* __restrict__ items, int32_t n_items,
     uint32_t* item_ctr, int32_t prof_bytes, int32_t cap, const PairRec* __restrict__ recs,
