@@ -255,14 +255,38 @@ __global__ __launch_bounds__(1024) void k_topk_final(const int32_t* __restrict__
     int32_t n_out;
     if (!st->fallback) {
         const int32_t c = st->count < kSortCap ? st->count : kSortCap;
-        int32_t m = 1;
-        while (m < c) m <<= 1;
         const uint64_t* keys = w.keys + (int64_t)q * kSortCap;
-        for (int i = threadIdx.x; i < m; i += blockDim.x) s[i] = i < c ? keys[i] : 0ull;
-        __syncthreads();
-        bitonic_desc(s, m);
-        m_keys = c;
         n_out = st->n_sel < c ? st->n_sel : c;
+        m_keys = c;
+        if (c <= (int32_t)blockDim.x) {
+            // one key per thread: its rank is the number of larger keys (all
+            // keys differ), found in one pass over the keys in LDS
+            const uint64_t mine = threadIdx.x < (uint32_t)c ? keys[threadIdx.x] : 0ull;
+            s[threadIdx.x] = mine;
+            __syncthreads();
+            // keys past c are 0 and never larger, so the scan may run to a
+            // multiple of 8 (two keys per LDS read, four reads in flight)
+            if (threadIdx.x < 8u) s[c + threadIdx.x] = 0ull;
+            __syncthreads();
+            int32_t r = 0;
+            const uint4* s2 = (const uint4*)s;
+            for (int32_t j = 0; j < c; j += 8) {
+                const uint4 a = s2[j / 2], b = s2[j / 2 + 1], e = s2[j / 2 + 2], f = s2[j / 2 + 3];
+                r += (((uint64_t)a.y << 32 | a.x) > mine) + (((uint64_t)a.w << 32 | a.z) > mine);
+                r += (((uint64_t)b.y << 32 | b.x) > mine) + (((uint64_t)b.w << 32 | b.z) > mine);
+                r += (((uint64_t)e.y << 32 | e.x) > mine) + (((uint64_t)e.w << 32 | e.z) > mine);
+                r += (((uint64_t)f.y << 32 | f.x) > mine) + (((uint64_t)f.w << 32 | f.z) > mine);
+            }
+            __syncthreads();
+            if (threadIdx.x < (uint32_t)c && r < n_out) s[r] = mine;
+            __syncthreads();
+        } else {
+            int32_t m = 1;
+            while (m < c) m <<= 1;
+            for (int i = threadIdx.x; i < m; i += blockDim.x) s[i] = i < c ? keys[i] : 0ull;
+            __syncthreads();
+            bitonic_desc(s, m);
+        }
     } else {
         // k-th largest key, then gather the keys at or above it
         int32_t eligible = 0;
