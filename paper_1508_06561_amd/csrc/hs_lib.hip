@@ -289,9 +289,9 @@ int device_cus() {
 }
 
 // Wavefronts per workgroup beside a profile region of prof_bytes: as many as
-// fit in LDS (8, 4, 2 or 1; 0 if none), each with its WaveLds record.
+// fit in LDS (at most 8; 0 if none), each with its WaveLds record.
 int fit_waves(size_t prof_bytes) {
-    for (int w = kWaves; w >= 1; w >>= 1)
+    for (int w = kWaves; w >= 1; --w)
         if (prof_bytes + sizeof(WaveLds) * w + 16 <= device_lds_limit()) return w;
     return 0;
 }
