@@ -309,9 +309,12 @@ __device__ __forceinline__ uint64_t block_best_dir(const uint32_t v[8], int32_t 
     const int32_t nreal = nk - k0;          // >= 1
     uint32_t key[8];
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const int32_t d = ascending ? b : 7 - b;
-        key[b] = d < nreal ? (v[b] << 3) + (uint32_t)(15 - d) : 0u;
+    for (int d = 0; d < 8; ++d) {
+        // diagonal k0 + d: byte d, or byte 7 - d of a large target's reads
+        // (indexing by diagonal keeps every constant a compile-time one)
+        const uint32_t va = v[d], vd = v[7 - d];
+        const uint32_t x = ascending ? va : vd;
+        key[d] = d < nreal ? (x << 3) + (uint32_t)(15 - d) : 0u;
     }
     const uint32_t m01 = key[0] > key[1] ? key[0] : key[1];
     const uint32_t m23 = key[2] > key[3] ? key[2] : key[3];
