@@ -65,6 +65,37 @@ def test_long_query_full_parity(small, qlen):
     check_full(r, codes, off, q, H().Params(), 40, 10)
 
 
+@pytest.mark.parametrize("qlen", [500, 1000, 1200])
+def test_four_copy_one_workgroup_parity(small, qlen):
+    """Queries of 450-1,200 letters keep four profile copies but leave LDS
+    for one workgroup per compute unit, so the launch takes the high-ILP
+    letter loop: every rank and alignment equals the oracle."""
+    res, off, codes, db = small
+    rng = np.random.default_rng(1000 + qlen)
+    q = synth.random_protein(rng, qlen)
+    say(f"query of {qlen}")
+    r = db.search(bytes(q), H().Params(), k=40, n_aln=10)
+    check_full(r, codes, off, q, H().Params(), 40, 10)
+
+
+def test_four_copy_batch_parity(small):
+    """A batch of 460-1,200-letter queries with four profile copies
+    requested: one workgroup fits per compute unit, the batch kernel takes
+    the high-ILP letter loop, and every query equals the oracle."""
+    res, off, codes, db = small
+    rng = np.random.default_rng(4242)
+    qs = [synth.random_protein(rng, n) for n in (460, 700, 1000, 1200, 512)]
+    b = H().Batch(db, len(qs), 1200, sum(map(len, qs)), k=30, n_aln=8)
+    b.set([bytes(q) for q in qs])
+    b.schedule(4, 0, 0)
+    say(f"schedule {b.get_schedule()}")
+    assert b.get_schedule()["copies"] == 4
+    b.run(graph=True)
+    for q, r in zip(qs, b.results()):
+        check_full(r, codes, off, q, H().Params(), 30, 8)
+    b.close()
+
+
 def test_mixed_lengths_batch(small):
     """One batch holding the longest and shortest queries: the launch is laid
     out for the longest, every query still equals the oracle."""
