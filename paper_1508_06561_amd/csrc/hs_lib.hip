@@ -374,7 +374,7 @@ int launch_score(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_par
     const KMatrix km = kmatrix(p);
     const int32_t bias = matrix_bias(km);
     const int32_t nq = (int32_t)db->n_queue;
-    hipLaunchKernelGGL(k_draws, dim3((nq + 255) / 256), dim3(256), 0, st, (const PairRec*)db->d_recs, nq,
+    hipLaunchKernelGGL(k_draws, dim3((2 * (int64_t)nq + 255) / 256), dim3(256), 0, st, (const PairRec*)db->d_recs, nq,
                        kp.seed, w.draws, w.queue);
     HIP_TRY(hipGetLastError());
     QueryLayout L;
@@ -1095,7 +1095,7 @@ int hs_batch_set(hs_batch* b, int32_t nq, const char* residues, const int64_t* o
     HIP_TRY(hipMemcpyAsync(b->d_mats, mats.data(), mats.size() * sizeof(KMatrix), hipMemcpyHostToDevice, st));
     if (new_table && b->db->n_queue > 0) {
         const int32_t nqueue = (int32_t)b->db->n_queue;
-        hipLaunchKernelGGL(k_draws, dim3((nqueue + 255) / 256), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_draws, dim3((2 * (int64_t)nqueue + 255) / 256), dim3(256), 0, st,
                            (const PairRec*)b->db->d_recs, nqueue, seed0, b->d_draws, b->d_ctr);
         HIP_TRY(hipGetLastError());
     }

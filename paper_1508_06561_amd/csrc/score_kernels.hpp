@@ -864,26 +864,23 @@ void k_score_batch(
 }
 
 // Random draws 0..31 of round 0 for every target in hand-out order (two
-// Philox blocks each), and the queue counter reset: run before the scoring
-// kernel.
+// Philox blocks each, one thread per block), and the queue counter reset:
+// run before the scoring kernel with 2n threads.
 __global__ __launch_bounds__(256) void k_draws(const PairRec* __restrict__ recs, int32_t n,
                                                uint64_t seed, uint64_t* __restrict__ out,
                                                uint32_t* queue) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *queue = 0;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) *queue = 0;
+    const int64_t i = t >> 1;
+    const uint32_t half = (uint32_t)(t & 1);
     if (i >= n || recs[i].id < 0) return;
-    const uint64_t id = (uint64_t)recs[i].id;
     uint64_t w[4];
-    philox_block(seed, id, 0, 0, w);
-    out[(int64_t)i * 8 + 0] = w[0];
-    out[(int64_t)i * 8 + 1] = w[1];
-    out[(int64_t)i * 8 + 2] = w[2];
-    out[(int64_t)i * 8 + 3] = w[3];
-    philox_block(seed, id, 0, 1, w);
-    out[(int64_t)i * 8 + 4] = w[0];
-    out[(int64_t)i * 8 + 5] = w[1];
-    out[(int64_t)i * 8 + 6] = w[2];
-    out[(int64_t)i * 8 + 7] = w[3];
+    philox_block(seed, (uint64_t)recs[i].id, 0, half, w);
+    uint64_t* o = out + i * 8 + half * 4;
+    o[0] = w[0];
+    o[1] = w[1];
+    o[2] = w[2];
+    o[3] = w[3];
 }
 
 }  // namespace hs
