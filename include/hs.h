@@ -312,8 +312,9 @@ int hs_server_create(const hs_db* db, int32_t max_batch, int32_t max_qlen, int64
 int hs_server_free(hs_server* s);
 
 /* Queues one query (host ASCII, 1..max_qlen letters) with its parameters
- * (copied, matrix included) under a caller-chosen tag that is not pending or
- * unclaimed.  Validates the letters; returns at once. */
+ * (copied, matrix included) under a caller-chosen tag that is not pending
+ * (queued or being searched) or unclaimed: HS_EINVAL otherwise.  Validates
+ * the letters; returns at once. */
 int hs_server_submit(hs_server* s, const char* query, int32_t qlen, const hs_params* params,
                      uint64_t tag);
 

@@ -15,6 +15,7 @@
 #include <string>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "hs.h"
@@ -73,6 +74,7 @@ struct hs_server {
     std::condition_variable cv_work, cv_done;
     bool stop = false;
     std::deque<Pending> queue;
+    std::unordered_set<uint64_t> inflight;   // tags taken by the worker, results not yet published
     std::unordered_map<uint64_t, Done> done;
     std::deque<uint64_t> done_order;
     int64_t n_batches = 0, n_served = 0;
@@ -102,6 +104,7 @@ void hs_server::run() {
             while (!queue.empty() && (int32_t)cur.size() < max_batch &&
                    res + (int64_t)queue.front().query.size() <= max_residues) {
                 res += (int64_t)queue.front().query.size();
+                inflight.insert(queue.front().tag);
                 cur.push_back(std::move(queue.front()));
                 queue.pop_front();
             }
@@ -159,6 +162,7 @@ void hs_server::run() {
                 }
                 done[cur[(size_t)i].tag] = std::move(d);
                 done_order.push_back(cur[(size_t)i].tag);
+                inflight.erase(cur[(size_t)i].tag);
             }
             ++n_batches;
             n_served += nq;
@@ -229,6 +233,7 @@ int hs_server_submit(hs_server* s, const char* query, int32_t qlen, const hs_par
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->done.count(tag)) return sfail(HS_EINVAL, "tag already holds an unclaimed result");
+        if (s->inflight.count(tag)) return sfail(HS_EINVAL, "tag already being searched");
         for (const Pending& q : s->queue)
             if (q.tag == tag) return sfail(HS_EINVAL, "tag already pending");
         s->queue.push_back(std::move(p));
