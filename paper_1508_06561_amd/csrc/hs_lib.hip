@@ -366,16 +366,19 @@ int launch_sched(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParam
     return HS_OK;
 }
 
+// With `reset`, the draw kernel also sets up the ranking state of the search
+// (which then needs no reset launch of its own).
 int launch_score(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_params* p,
                  hipStream_t st, const QueryWs& w, int32_t* d_scores, int32_t* d_rounds,
-                 uint64_t* d_cells, int32_t* d_max) {
+                 uint64_t* d_cells, int32_t* d_max, bool reset = false) {
     if (db->n_targets == 0) return HS_OK;
     const KParams kp = kparams(p);
     const KMatrix km = kmatrix(p);
     const int32_t bias = matrix_bias(km);
     const int32_t nq = (int32_t)db->n_queue;
-    hipLaunchKernelGGL(k_draws, dim3((2 * (int64_t)nq + 255) / 256), dim3(256), 0, st, (const PairRec*)db->d_recs, nq,
-                       kp.seed, w.draws, w.queue);
+    hipLaunchKernelGGL(k_draws, dim3((2 * (int64_t)nq + 255) / 256), dim3(256), 0, st,
+                       (const PairRec*)db->d_recs, nq, kp.seed, w.draws, w.queue, w.tw(),
+                       p->min_score, reset ? 1 : 0);
     HIP_TRY(hipGetLastError());
     QueryLayout L;
     int rc = query_layout(qlen, &L);
@@ -441,9 +444,11 @@ int launch_search(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_pa
                   int32_t n_aln, hipStream_t st, void* d_ws, DevHit* d_hits, int32_t* d_n_hits,
                   DevAln* d_alns, uint32_t* d_ops, int64_t ops_stride) {
     QueryWs w = carve(d_ws, db->n_targets, db->n_queue);
-    hipLaunchKernelGGL(k_topk_reset, dim3(1, 1), dim3(256), 0, st, w.tw(), p->min_score,
-                       (const BatchQuery*)nullptr, (uint32_t*)nullptr);
-    int rc = launch_score(db, d_q, qlen, p, st, w, w.scores, w.rounds, nullptr, &w.topk->max_score);
+    if (db->n_targets == 0)   // no draw kernel runs: reset the ranking state here
+        hipLaunchKernelGGL(k_topk_reset, dim3(1, 1), dim3(256), 0, st, w.tw(), p->min_score,
+                           (const BatchQuery*)nullptr, (uint32_t*)nullptr);
+    int rc = launch_score(db, d_q, qlen, p, st, w, w.scores, w.rounds, nullptr, &w.topk->max_score,
+                          true);
     if (rc) return rc;
     rc = launch_rank(db, st, w.scores, w.rounds, 0, 1, k, w.tw(), d_hits, d_n_hits);
     if (rc) return rc;
@@ -1096,7 +1101,8 @@ int hs_batch_set(hs_batch* b, int32_t nq, const char* residues, const int64_t* o
     if (new_table && b->db->n_queue > 0) {
         const int32_t nqueue = (int32_t)b->db->n_queue;
         hipLaunchKernelGGL(k_draws, dim3((2 * (int64_t)nqueue + 255) / 256), dim3(256), 0, st,
-                           (const PairRec*)b->db->d_recs, nqueue, seed0, b->d_draws, b->d_ctr);
+                           (const PairRec*)b->db->d_recs, nqueue, seed0, b->d_draws, b->d_ctr,
+                           TopkWs{}, 0, 0);
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipStreamSynchronize(st));

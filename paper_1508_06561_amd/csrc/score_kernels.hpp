@@ -29,6 +29,7 @@
 #pragma once
 
 #include "device_common.hpp"
+#include "topk_kernels.hpp"
 
 namespace hs {
 
@@ -591,30 +592,37 @@ __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool ste
                                               const uint8_t* prof, int32_t ps, int32_t cpb,
                                               int32_t bias, const uint8_t* __restrict__ letters) {
     // ---- phase B: issue blocks, sorted by (orientation, ss) descending ----
-    W.bins[lane] = 0;
-    W.bins[lane + kLanes] = 0;
-    wave_sync();
     const int32_t want = stepping ? nblk - blk : 0;
-    // descending bins: the last, partly filled round of 64 blocks then holds
-    // the shortest blocks rather than the longest
-    const int32_t bkey = (kBins - 1) - ss_bin(tl, ss);
-    uint32_t off = 0;
-    if (want > 0) off = atomicAdd(&W.bins[bkey], (uint32_t)want);
-    wave_sync();
-    uint32_t nw;   // blocks wanted by all slots = the scan's total
-    {
-        // exclusive scan over the 128 bins: lane l owns bins 2l, 2l + 1
-        const uint32_t a0 = W.bins[2 * lane], a1 = W.bins[2 * lane + 1];
-        const uint32_t inc = wave_inclusive_scan(a0 + a1, lane);
-        const uint32_t before = inc - (a0 + a1);
-        nw = (uint32_t)__builtin_amdgcn_readlane((int)inc, kLanes - 1);
+    const uint32_t winc = wave_inclusive_scan((uint32_t)want, lane);
+    const uint32_t nw = (uint32_t)__builtin_amdgcn_readlane((int)winc, kLanes - 1);  // all wants
+    int32_t start;
+    if (nw <= (uint32_t)kLanes) {
+        // one round of 64 lanes holds every block: their order does not
+        // matter, so they go in slot order without the counting sort
+        start = (int32_t)(winc - (uint32_t)want);
+    } else {
+        W.bins[lane] = 0;
+        W.bins[lane + kLanes] = 0;
         wave_sync();
-        W.bins[2 * lane] = before;
-        W.bins[2 * lane + 1] = before + a0;
+        // descending bins: the last, partly filled round of 64 blocks then
+        // holds the shortest blocks rather than the longest
+        const int32_t bkey = (kBins - 1) - ss_bin(tl, ss);
+        uint32_t off = 0;
+        if (want > 0) off = atomicAdd(&W.bins[bkey], (uint32_t)want);
+        wave_sync();
+        {
+            // exclusive scan over the 128 bins: lane l owns bins 2l, 2l + 1
+            const uint32_t a0 = W.bins[2 * lane], a1 = W.bins[2 * lane + 1];
+            const uint32_t inc = wave_inclusive_scan(a0 + a1, lane);
+            const uint32_t before = inc - (a0 + a1);
+            wave_sync();
+            W.bins[2 * lane] = before;
+            W.bins[2 * lane + 1] = before + a0;
+        }
+        wave_sync();
+        start = (int32_t)(W.bins[bkey] + off);
     }
-    wave_sync();
     if (want > 0) {
-        const int32_t start = (int32_t)(W.bins[bkey] + off);
         int32_t issue = kItemCap - start;
         issue = issue < 0 ? 0 : (issue > want ? want : issue);
         for (int32_t b = 0; b < issue; ++b)
@@ -865,12 +873,15 @@ void k_score_batch(
 
 // Random draws 0..31 of round 0 for every target in hand-out order (two
 // Philox blocks each, one thread per block), and the queue counter reset:
-// run before the scoring kernel with 2n threads.
+// run before the scoring kernel with 2n threads.  With `reset`, the first
+// workgroup also sets up the ranking state of query 0 (a one-query search).
 __global__ __launch_bounds__(256) void k_draws(const PairRec* __restrict__ recs, int32_t n,
                                                uint64_t seed, uint64_t* __restrict__ out,
-                                               uint32_t* queue) {
+                                               uint32_t* queue, TopkWs tw, int32_t min_score,
+                                               int32_t reset) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t == 0) *queue = 0;
+    if (reset && blockIdx.x == 0) topk_state_init(tw, 0, min_score, threadIdx.x, blockDim.x);
     const int64_t i = t >> 1;
     const uint32_t half = (uint32_t)(t & 1);
     if (i >= n || recs[i].id < 0) return;

@@ -52,6 +52,25 @@ struct TopkWs {
     uint64_t* keys;         // [nq][kSortCap]
 };
 
+// Initial ranking state of query q (eligibility threshold min_score), and
+// its histogram cleared by the calling workgroup's threads.
+__device__ __forceinline__ void topk_state_init(const TopkWs& w, int q, int32_t min_score,
+                                                int32_t first, int32_t step) {
+    if (first == 0) {
+        TopkState s;
+        s.max_score = INT32_MIN;
+        s.thr = 0;
+        s.n_sel = 0;
+        s.fallback = 0;
+        s.count = 0;
+        s.min_score = min_score;
+        s.pad_[0] = s.pad_[1] = 0;
+        w.st[q] = s;
+    }
+    uint32_t* h = w.hist + (int64_t)q * kWinBins;
+    for (int i = first; i < kWinBins; i += step) h[i] = 0;
+}
+
 // Before the scoring pass: reset the state and the histogram of every query
 // and, if given, two work counters (ctr[0], ctr[1]).  The threshold is qs[q].kp.min_score for a
 // batch, min_score otherwise.
@@ -59,24 +78,12 @@ __global__ __launch_bounds__(256) void k_topk_reset(TopkWs w, int32_t min_score,
                                                     const BatchQuery* __restrict__ qs,
                                                     uint32_t* ctr) {
     const int q = blockIdx.y;
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        TopkState s;
-        s.max_score = INT32_MIN;
-        s.thr = 0;
-        s.n_sel = 0;
-        s.fallback = 0;
-        s.count = 0;
-        s.min_score = qs ? qs[q].kp.min_score : min_score;
-        s.pad_[0] = s.pad_[1] = 0;
-        w.st[q] = s;
-        if (ctr && q == 0) {
-            ctr[0] = 0;
-            ctr[1] = 0;
-        }
+    const int32_t first = blockIdx.x * blockDim.x + threadIdx.x;
+    topk_state_init(w, q, qs ? qs[q].kp.min_score : min_score, first, gridDim.x * blockDim.x);
+    if (first == 0 && ctr && q == 0) {
+        ctr[0] = 0;
+        ctr[1] = 0;
     }
-    uint32_t* h = w.hist + (int64_t)q * kWinBins;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kWinBins; i += gridDim.x * blockDim.x)
-        h[i] = 0;
 }
 
 // Histogram of eligible scores within [M - kWinBins + 1, M].
