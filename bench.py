@@ -269,7 +269,8 @@ def bench_serving(args):
     torch.cuda.set_device(0)
     w0 = synth.config_serving(50, duration_s=0.1)
     db = H.Database(w0.residues, w0.offsets)
-    srv = H.Server(db, max_batch=64, max_qlen=2000, max_residues=64 * 2000, k=w0.k, n_aln=w0.n_aln)
+    srv = H.Server(db, max_batch=64, max_qlen=2000, max_residues=64 * 2000, k=w0.k, n_aln=w0.n_aln,
+                   workers=2)
     # warm-up: first launches and allocations
     for i, q in enumerate(w0.queries[:16]):
         srv.submit(bytes(q), tag=(1 << 40) + i)
@@ -330,7 +331,7 @@ def bench_serving(args):
                                f"{args.serve_s} s each, |Q| log-normal (median 250, sigma 0.6, "
                                "clip 20-2,000), vs 2,020 targets U[50,500]; top 500 hits and "
                                "top 50 alignments per query; continuous batching (at most 64 "
-                               "queries per batch)"},
+                               "queries per batch, two batches in flight)"},
         "serving": rows,
     }
     print(json.dumps(out), flush=True)

@@ -53,6 +53,7 @@ extern "C" {
 #define HS_MAX_QUERY 5600      /* longest query: its score profile lives in LDS */
 #define HS_MAX_PENALTY 1000    /* largest GOP, GEP or PGP */
 #define HS_MAX_BATCH 4096      /* most queries in one batch */
+#define HS_MAX_SERVER_WORKERS 8 /* most batches a server keeps in flight */
 
 /* Parameters of Section III.B.1.  Factors are Q16 fixed point (65536 = 1.0)
  * and lie in [0, 65536]; penalties lie in [0, HS_MAX_PENALTY].
@@ -280,14 +281,16 @@ int hs_search_batch(const hs_db* db, int32_t nq, const char* residues, const int
                     uint32_t* ops, int64_t ops_cap, int64_t* ops_used);
 
 /* ---------------------------------------------------------------------------
- * Serving.  A server owns a batch handle and a worker thread that runs
- * continuous batching: queries are submitted one at a time (from any thread)
- * and queue up; whenever the device is free the worker takes every waiting
- * query, first come first served, that fits the batch footprint fixed at
- * creation -- at most max_batch queries and max_residues letters in all
- * (device memory), each at most max_qlen letters (LDS) -- searches them as
- * one batch on its own stream and publishes each query's results.  Results
- * are identical to a separate hs_search of the same query and parameters.
+ * Serving.  A server owns a few workers, each a batch handle, a stream and a
+ * thread, that run continuous batching: queries are submitted one at a time
+ * (from any thread) and queue up; whenever a worker is free it takes every
+ * waiting query, first come first served, that fits the batch footprint
+ * fixed at creation -- at most max_batch queries and max_residues letters in
+ * all (device memory, per worker), each at most max_qlen letters (LDS) --
+ * searches them as one batch on its stream and publishes each query's
+ * results.  With more than one worker, queries that arrive while a batch is
+ * on the device start beside it.  Results are identical to a separate
+ * hs_search of the same query and parameters.
  * ------------------------------------------------------------------------- */
 typedef struct hs_server hs_server;
 
@@ -301,13 +304,19 @@ typedef struct hs_server_timing {
     int32_t pad_;
 } hs_server_timing;
 
-/* Creates a server on the current device for searches returning k ranks and
- * n_aln alignments per query (limits as in hs_batch_create).  The database
- * must outlive the server. */
+/* Creates a server with two workers on the current device for searches
+ * returning k ranks and n_aln alignments per query (limits as in
+ * hs_batch_create).  The database must outlive the server. */
 int hs_server_create(const hs_db* db, int32_t max_batch, int32_t max_qlen, int64_t max_residues,
                      int32_t k, int32_t n_aln, hs_server** out);
 
-/* Stops the worker after its current batch and releases the server; queries
+/* As hs_server_create with n_workers (1..HS_MAX_SERVER_WORKERS) workers, i.e.
+ * at most that many batches in flight; each holds its own device buffers. */
+int hs_server_create_workers(const hs_db* db, int32_t max_batch, int32_t max_qlen,
+                             int64_t max_residues, int32_t k, int32_t n_aln, int32_t n_workers,
+                             hs_server** out);
+
+/* Stops the workers after their current batches and releases the server; queries
  * still waiting are dropped, unclaimed results discarded.  NULL is allowed. */
 int hs_server_free(hs_server* s);
 

@@ -1,10 +1,12 @@
 // hs_server.cpp -- serving loop of the C ABI (include/hs.h): queries are
-// submitted one at a time from any thread; a worker thread owns a batch
-// handle and runs continuous batching -- whenever the device is free it takes
-// every waiting query that fits the batch's footprint (count, total letters,
-// longest query; fixed when the server is created), searches them as one
-// batch on its own stream and publishes each query's results.  Every result
-// equals a separate hs_search of that query: batching never changes results.
+// submitted one at a time from any thread; each of a few worker threads owns
+// a batch handle and a stream and runs continuous batching -- whenever it is
+// free it takes every waiting query that fits its batch's footprint (count,
+// total letters, longest query; fixed when the server is created), searches
+// them as one batch on its stream and publishes each query's results.  With
+// two workers, queries that arrive while one batch is on the device start at
+// once beside it.  Every result equals a separate hs_search of that query:
+// batching never changes results.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -62,10 +64,22 @@ int sfail(int code, const std::string& msg) {
 
 }  // namespace
 
-struct hs_server {
-    const hs_db* db = nullptr;
+struct hs_server;
+
+namespace {
+
+// One worker: a batch handle, a stream and the thread that drives them.
+struct Worker {
     hs_batch* batch = nullptr;
     hipStream_t stream = nullptr;
+    std::thread thread;
+};
+
+}  // namespace
+
+struct hs_server {
+    const hs_db* db = nullptr;
+    std::vector<Worker> workers;
     int device = 0;
     int32_t max_batch = 0, max_qlen = 0, k = 0, n_aln = 0;
     int64_t max_residues = 0;
@@ -80,11 +94,13 @@ struct hs_server {
     int64_t n_batches = 0, n_served = 0;
     Clock::time_point t0 = Clock::now();
 
-    void run();
+    void run(Worker& wk);
 };
 
-void hs_server::run() {
+void hs_server::run(Worker& wk) {
     (void)hipSetDevice(device);
+    hs_batch* batch = wk.batch;
+    hipStream_t stream = wk.stream;
     std::vector<Pending> cur;
     std::vector<char> residues;
     std::vector<int64_t> offsets;
@@ -173,20 +189,29 @@ void hs_server::run() {
 
 extern "C" {
 
-int hs_server_create(const hs_db* db, int32_t max_batch, int32_t max_qlen, int64_t max_residues,
-                     int32_t k, int32_t n_aln, hs_server** out) {
+int hs_server_create_workers(const hs_db* db, int32_t max_batch, int32_t max_qlen,
+                             int64_t max_residues, int32_t k, int32_t n_aln, int32_t n_workers,
+                             hs_server** out) {
     if (!out) return sfail(HS_EINVAL, "out is NULL");
+    if (n_workers < 1 || n_workers > HS_MAX_SERVER_WORKERS)
+        return sfail(HS_EINVAL, "n_workers must lie in [1, HS_MAX_SERVER_WORKERS]");
     hs_server* s = new hs_server();
-    int rc = hs_batch_create(db, max_batch, max_qlen, max_residues, k, n_aln, &s->batch);
+    s->workers.resize((size_t)n_workers);
+    int rc = HS_OK;
+    for (Worker& wk : s->workers) {   // the first batch handle validates the arguments
+        if (rc) break;
+        rc = hs_batch_create(db, max_batch, max_qlen, max_residues, k, n_aln, &wk.batch);
+        if (!rc && hipStreamCreateWithFlags(&wk.stream, hipStreamNonBlocking) != hipSuccess)
+            rc = sfail(HS_EDEVICE, "stream creation failed");
+    }
+    if (!rc && hipGetDevice(&s->device) != hipSuccess) rc = sfail(HS_EDEVICE, "no current device");
     if (rc) {
+        for (Worker& wk : s->workers) {
+            if (wk.stream) (void)hipStreamDestroy(wk.stream);
+            if (wk.batch) hs_batch_free(wk.batch);
+        }
         delete s;
         return rc;
-    }
-    if (hipGetDevice(&s->device) != hipSuccess ||
-        hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
-        hs_batch_free(s->batch);
-        delete s;
-        return sfail(HS_EDEVICE, "stream creation failed");
     }
     s->db = db;
     s->max_batch = max_batch;
@@ -194,9 +219,17 @@ int hs_server_create(const hs_db* db, int32_t max_batch, int32_t max_qlen, int64
     s->max_residues = max_residues;
     s->k = k;
     s->n_aln = n_aln;
-    s->worker = std::thread([s] { s->run(); });
+    for (Worker& wk : s->workers) {
+        Worker* w = &wk;
+        wk.thread = std::thread([s, w] { s->run(*w); });
+    }
     *out = s;
     return HS_OK;
+}
+
+int hs_server_create(const hs_db* db, int32_t max_batch, int32_t max_qlen, int64_t max_residues,
+                     int32_t k, int32_t n_aln, hs_server** out) {
+    return hs_server_create_workers(db, max_batch, max_qlen, max_residues, k, n_aln, 2, out);
 }
 
 int hs_server_free(hs_server* s) {
@@ -206,10 +239,13 @@ int hs_server_free(hs_server* s) {
         s->stop = true;
     }
     s->cv_work.notify_all();
-    if (s->worker.joinable()) s->worker.join();
-    (void)hipStreamSynchronize(s->stream);
-    (void)hipStreamDestroy(s->stream);
-    hs_batch_free(s->batch);
+    for (Worker& wk : s->workers)
+        if (wk.thread.joinable()) wk.thread.join();
+    for (Worker& wk : s->workers) {
+        (void)hipStreamSynchronize(wk.stream);
+        (void)hipStreamDestroy(wk.stream);
+        hs_batch_free(wk.batch);
+    }
     delete s;
     return HS_OK;
 }

@@ -19,6 +19,7 @@ OP_M, OP_I, OP_D = 0, 1, 2
 MAX_K = 4096
 MAX_QUERY = 5600
 MAX_BATCH = 4096
+MAX_SERVER_WORKERS = 8
 ALPHABET = "ARNDCQEGHILKMFPSTWYVBZX*"
 
 
@@ -107,6 +108,7 @@ def lib():
                                       vp, vp, pi32, vp, pi32, vp, i64, P(ctypes.c_int64)]
         L.hs_params_check.argtypes = [P(_CParams)]
         L.hs_server_create.argtypes = [vp, i32, i32, i64, i32, i32, P(vp)]
+        L.hs_server_create_workers.argtypes = [vp, i32, i32, i64, i32, i32, i32, P(vp)]
         L.hs_server_free.argtypes = [vp]
         L.hs_server_submit.argtypes = [vp, ctypes.c_char_p, i32, P(_CParams), ctypes.c_uint64]
         L.hs_server_poll.argtypes = [vp, P(ctypes.c_uint64), i32, pi32, i32]
@@ -454,14 +456,16 @@ def search_batch(db, queries, params=None, k=50, n_aln=50, stream=None):
 
 class Server:
     """A serving loop (hs_server_*): queries submitted one at a time are
-    searched in continuous batches by a native worker thread."""
+    searched in continuous batches by native worker threads, up to `workers`
+    batches in flight."""
 
-    def __init__(self, db, max_batch=64, max_qlen=2000, max_residues=None, k=500, n_aln=50):
+    def __init__(self, db, max_batch=64, max_qlen=2000, max_residues=None, k=500, n_aln=50,
+                 workers=2):
         self.db, self.k, self.n_aln, self.max_qlen = db, k, n_aln, max_qlen
         h = ctypes.c_void_p()
-        _check(lib().hs_server_create(db._h, max_batch, max_qlen,
-                                      max_residues or max_batch * max_qlen, k, n_aln,
-                                      ctypes.byref(h)))
+        _check(lib().hs_server_create_workers(db._h, max_batch, max_qlen,
+                                              max_residues or max_batch * max_qlen, k, n_aln,
+                                              workers, ctypes.byref(h)))
         self._h = h
         self._qlen = {}
         self._params = {}

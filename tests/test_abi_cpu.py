@@ -125,6 +125,9 @@ def test_server_argument_errors_before_device_use():
     assert L.hs_server_create(None, 4, 100, 400, 10, 5, ctypes.byref(h)) == E
     assert L.hs_server_create(ctypes.c_void_p(1), 4, 100, 400, 10, 5, None) == E
     assert L.hs_server_create(ctypes.c_void_p(1), 0, 100, 400, 10, 5, ctypes.byref(h)) == E
+    for n_workers in (0, H.hs.MAX_SERVER_WORKERS + 1):
+        assert L.hs_server_create_workers(ctypes.c_void_p(1), 4, 100, 400, 10, 5, n_workers,
+                                          ctypes.byref(h)) == E
     p = H.Params().c()
     assert L.hs_server_submit(None, b"ACD", 3, ctypes.byref(p), 1) == E
     n = ctypes.c_int32()

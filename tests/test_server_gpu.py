@@ -116,3 +116,32 @@ def test_server_errors_and_shutdown(served):
     t0 = time.time()
     srv.close()
     assert time.time() - t0 < 30
+
+
+def test_two_workers_overlap_on_device(served):
+    """With two workers, a query submitted while another one's batch is on the
+    device starts beside it: of six long queries submitted at once (one query
+    per batch), some batches overlap in time, and every result still equals
+    a separate search."""
+    w, codes, db = served
+    rng = np.random.default_rng(11)
+    qs = [bytes(synth.random_protein(rng, 1500)) for _ in range(6)]
+    srv = H().Server(db, max_batch=1, max_qlen=1500, k=20, n_aln=3, workers=2)
+    for i, q in enumerate(qs):
+        srv.submit(q, tag=i)
+    tags = drain(srv, len(qs))
+    assert sorted(tags) == list(range(len(qs)))
+    spans = []
+    for tag in tags:
+        r, t = srv.result(tag)
+        assert t["batch_size"] == 1
+        start = t["submit_ms"] + t["queue_ms"]
+        spans.append((start, start + t["batch_ms"]))
+        alone = db.search(qs[tag], H().Params(), k=20, n_aln=3)
+        assert (r.hits == alone.hits).all() and (r.ops == alone.ops).all()
+    spans.sort()
+    overlaps = sum(b[0] < a[1] for a, b in zip(spans, spans[1:]))
+    print(f"batch spans (ms): {[(round(a, 2), round(b, 2)) for a, b in spans]}", flush=True)
+    assert overlaps >= 1
+    assert srv.stats()["batches"] == len(qs)
+    srv.close()
