@@ -355,8 +355,9 @@ __device__ __forceinline__ void fetch_block(const SlotInfo& si, int32_t k0,
         const uint8_t* T = letters + si.tbase + si.pL + k0;
         f.run = T + 7;
         f.count = ss - 7;
+        // letters 0..15: the entry ramp, or all ss + 7 letters of a short window
+        f.ramp_in = load16(T);
         if (ss >= 7) {
-            f.ramp_in = load16(T);
             f.ramp_out = load16(T + ss);
             f.first = load16(f.run);
             f.tail = load16(f.run + (f.count & ~15));
@@ -382,15 +383,30 @@ __device__ __forceinline__ uint64_t score_block(const uint8_t* prof, int32_t ps,
     const int32_t off = (int32_t)__umul24((uint32_t)bias, (uint32_t)ss);
     uint32_t v[8];
     if (tl && ss < 7) {
-        // short windows: cell by cell from copy 0 (column c at c + kPad)
-        const uint8_t* T = f.run - 7;
+        // short window of a large target: letters 0 .. ss + 6 (prefetched,
+        // at most 12) all carry out-of-window cells.  Letter i meets query
+        // columns pS + i - 7 + b; byte b is real when 7 - i <= b < ss + 7 - i.
+        // Byte sums stay below 256 (at most 6 cells of at most 15 each).
+        uint32_t b0 = 0, b1 = 0;
+        Bases<kCopies> Bs;
+        Bs.set(si.pS - 7 + kPad, cpb);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) v[b] = 0;
-        for (int32_t j = 0; j < ss; ++j) {
-            const uint8_t* col = prof + si.pS + j + kPad;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) v[7 - m] += col[__umul24((uint32_t)T[m + j], (uint32_t)ps)];
+        for (int i = 0; i < 13; ++i) {
+            const int32_t n = ss + 7 - i;          // bytes below this one are real
+            if (n > 0) {
+                const int32_t base = (i & 3) == 0 ? Bs.v0 : (i & 3) == 1 ? Bs.v1 : (i & 3) == 2 ? Bs.v2 : Bs.v3;
+                const uint32_t r = letter_of(pick4(f.ramp_in, i >> 2), i & 3);
+                const uint2 x = lds8<kCopies>(prof, (int32_t)(__umul24(r, (uint32_t)ps) + (uint32_t)base) + 4 * (i >> 2));
+                const uint64_t lo = i < 7 ? (~0ull << (8 * (7 - i))) : ~0ull;
+                const uint64_t hi = n >= 8 ? ~0ull : ((1ull << (8 * n)) - 1ull);
+                const uint64_t m = lo & hi;
+                b0 += x.x & (uint32_t)m;
+                b1 += x.y & (uint32_t)(m >> 32);
+            }
         }
+        // byte b of the reads is diagonal k0 + 7 - b
+        v[0] = b0 & 0xFFu; v[1] = (b0 >> 8) & 0xFFu; v[2] = (b0 >> 16) & 0xFFu; v[3] = b0 >> 24;
+        v[4] = b1 & 0xFFu; v[5] = (b1 >> 8) & 0xFFu; v[6] = (b1 >> 16) & 0xFFu; v[7] = b1 >> 24;
         return block_best_dir(v, k0, si.nk, off, false);
     }
     Acc8 a;
