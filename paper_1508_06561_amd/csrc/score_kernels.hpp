@@ -586,13 +586,18 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Inclusive prefix sum across the wavefront.
-__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x, int32_t lane) {
-#pragma unroll
-    for (int o = 1; o < kLanes; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, kLanes);
-        if (lane >= o) x += y;
-    }
+// Inclusive prefix sum across the wavefront (all 64 lanes active), in
+// registers: sums within each row of 16 lanes by DPP row shifts of 1, 2, 4
+// and 8 (lanes without a source add 0), then lane 15's row total is
+// broadcast into rows 1 and 3 and lane 31's into rows 2 and 3.  A shuffle
+// through LDS would take six dependent LDS round trips instead.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
     return x;
 }
 
@@ -609,7 +614,7 @@ __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool ste
                                               int32_t bias, const uint8_t* __restrict__ letters) {
     // ---- phase B: issue blocks, sorted by (orientation, ss) descending ----
     const int32_t want = stepping ? nblk - blk : 0;
-    const uint32_t winc = wave_inclusive_scan((uint32_t)want, lane);
+    const uint32_t winc = wave_inclusive_scan((uint32_t)want);
     const uint32_t nw = (uint32_t)__builtin_amdgcn_readlane((int)winc, kLanes - 1);  // all wants
     int32_t start;
     if (nw <= (uint32_t)kLanes) {
@@ -629,7 +634,7 @@ __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool ste
         {
             // exclusive scan over the 128 bins: lane l owns bins 2l, 2l + 1
             const uint32_t a0 = W.bins[2 * lane], a1 = W.bins[2 * lane + 1];
-            const uint32_t inc = wave_inclusive_scan(a0 + a1, lane);
+            const uint32_t inc = wave_inclusive_scan(a0 + a1);
             const uint32_t before = inc - (a0 + a1);
             wave_sync();
             W.bins[2 * lane] = before;
@@ -743,7 +748,7 @@ __device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap
                 const uint32_t g = cnt - take1 > grab ? cnt - take1 : grab;
                 uint32_t base = 0;
                 if (lane == 0) base = atomicAdd(ctr, g);
-                base = __shfl(base, 0, kLanes);
+                base = (uint32_t)__builtin_amdgcn_readlane((int)base, 0);
                 if (rank >= take1) qi = base + (rank - take1);
                 q_next = base + (cnt - take1);
                 q_end = base + g;

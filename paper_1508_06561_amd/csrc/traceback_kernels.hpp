@@ -154,7 +154,7 @@ __device__ __forceinline__ void wave_trace(WaveLds& W, int32_t lane, int32_t cap
             const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1));
             uint32_t base = 0;
             if (lane == 0) base = atomicAdd(ctr, cnt);
-            base = __shfl(base, 0, kLanes);
+            base = (uint32_t)__builtin_amdgcn_readlane((int)base, 0);
             const uint32_t a = base + rank;
             if (need) {
                 if (a < hi) {
