@@ -59,24 +59,40 @@ __host__ __device__ inline int32_t profile_region_bytes(int32_t qlen, int copies
     return (copies * profile_copy_bytes(profile_stride(qlen)) + 15) & ~15;
 }
 
+// Builds the profile with all threads tid = 0 .. nthreads - 1 of the
+// workgroup (every thread must call it: it holds a workgroup barrier).  The
+// biased substitution rows (row kZeroRow zero) go to `tmp` first, LDS outside
+// the profile (at least kProfRows * kNsym bytes), so that each profile dword
+// costs one memory round trip for its four query letters and four LDS
+// lookups, instead of a dependent pair of global loads per byte.
 template <int kCopies>
 __device__ __forceinline__ void build_profile(uint8_t* prof, int32_t ps, const uint8_t* qcodes,
-                                              int32_t qlen, const KMatrix& km, int32_t bias) {
+                                              int32_t qlen, const int8_t* mat, int32_t bias,
+                                              uint8_t* tmp, int32_t tid, int32_t nthreads) {
+    for (int32_t i = tid; i < kProfRows * kNsym; i += nthreads)
+        tmp[i] = i < kNsym * kNsym ? (uint8_t)(mat[i] + bias) : (uint8_t)0;
+    __syncthreads();
     const int32_t cpb = profile_copy_bytes(ps);
     uint32_t* p32 = (uint32_t*)prof;
     const int32_t nw = kCopies * cpb / 4;
-    for (int32_t w = threadIdx.x; w < nw; w += blockDim.x) {
+    for (int32_t w = tid; w < nw; w += nthreads) {
         const int32_t byte0 = w * 4;
         const int32_t s = byte0 / cpb;
         const int32_t rem = byte0 - s * cpb;
         const int32_t r = rem / ps;
-        const int32_t x0 = rem - r * ps;
+        const int32_t c0 = rem - r * ps + s - kPad;     // column of byte 0
+        uint32_t code[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int32_t c = c0 + b;
+            code[b] = qcodes[(uint32_t)c < (uint32_t)qlen ? c : 0];   // qlen >= 1
+        }
+        const uint8_t* row = tmp + r * kNsym;              // r <= kZeroRow
         uint32_t v = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int32_t c = x0 + b + s - kPad;
-            uint32_t e = 0;
-            if (r < kNsym && c >= 0 && c < qlen) e = (uint32_t)(km.m[r * kNsym + qcodes[c]] + bias);
+            const int32_t c = c0 + b;
+            const uint32_t e = (uint32_t)c < (uint32_t)qlen ? (uint32_t)row[code[b]] : 0u;
             v |= e << (8 * b);
         }
         p32[w] = v;
@@ -450,11 +466,13 @@ __device__ __forceinline__ uint64_t score_block(const uint8_t* prof, int32_t ps,
     return block_best_dir(v, k0, si.nk, off, !tl);
 }
 
-// A target as handed out by the queue (stored in hand-out order).
+// A target as handed out by the queue (stored in hand-out order); 16 bytes,
+// read as one vector.
 struct PairRec {
     int32_t id, len;
     int64_t offset;
 };
+static_assert(sizeof(PairRec) == 16, "PairRec is read as one 16-byte vector");
 
 // One pair's progress, held in the registers of the slot's lane.
 struct PairState {
@@ -754,20 +772,24 @@ __device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap
                 q_end = base + g;
             }
             if (need && qi < hi) {
-                // the record and the first draw word load together (the
-                // draw word of a padding position is read and ignored)
-                const PairRec r = recs[qi];
-                const uint64_t dw0 = (!kExact || draws != nullptr) ? draws[(int64_t)qi * 8] : 0ull;
-                if (r.id >= 0) {
-                    s.dw = dw0;
+                // Every field of the record and the first draw word are
+                // consumed before the id is tested, so that all of them load
+                // in one memory round trip (tested first, the id would be
+                // fetched alone and the rest after it).  For a padding
+                // position (id -1) they are read and ignored: the slot stays
+                // empty.
+                const uint4 rv = *(const uint4*)(recs + qi);
+                s.dw = (!kExact || draws != nullptr) ? draws[(int64_t)qi * 8] : 0ull;
+                const int32_t rid = (int32_t)rv.x, rlen = (int32_t)rv.y;
+                s.tl = rlen >= qlen;
+                s.nl = s.tl ? rlen : qlen;
+                s.ns = s.tl ? qlen : rlen;
+                s.tbase = (int64_t)(((uint64_t)rv.w << 32) | rv.z);
+                if (rid >= 0) {
                     s.dw_i = 0;
                     s.pf_i = 0xFFFFFFFFu;
-                    s.id = r.id;
+                    s.id = rid;
                     s.qi = (int32_t)qi;
-                    s.tl = r.len >= qlen;
-                    s.nl = s.tl ? r.len : qlen;
-                    s.ns = s.tl ? qlen : r.len;
-                    s.tbase = r.offset;
                     s.round = 0;
                     s.best = INT32_MIN;
                     s.best_round = 0;
@@ -819,7 +841,8 @@ void k_score_sched(
     const int32_t ps = profile_stride(qlen);
     const int32_t cpb = profile_copy_bytes(ps);
     uint8_t* prof = lds;
-    build_profile<kCopies>(prof, ps, qcodes, qlen, km, bias);
+    build_profile<kCopies>(prof, ps, qcodes, qlen, km.m, bias, lds + profile_region_bytes(qlen, kCopies),
+                           threadIdx.x, blockDim.x);
     __syncthreads();   // the only workgroup barrier: wavefronts run independently from here
 
     const int32_t lane = threadIdx.x & (kLanes - 1);
@@ -873,7 +896,8 @@ void k_score_batch(
         const BatchQuery Q = qs[q];
         const int32_t ps = profile_stride(Q.qlen);
         const int32_t cpb = profile_copy_bytes(ps);
-        build_profile<kCopies>(lds, ps, qcodes + Q.qoff, Q.qlen, mats[q], Q.bias);
+        build_profile<kCopies>(lds, ps, qcodes + Q.qoff, Q.qlen, mats[q].m, Q.bias, lds + prof_bytes,
+                               threadIdx.x, blockDim.x);
         __syncthreads();
         int32_t best_seen = INT32_MIN;
         wave_pairs<kCopies, kCount, true, kIlp>(W, lane, cap, 0u, lds, ps, cpb, Q.bias, Q.qlen,

@@ -211,7 +211,8 @@ __global__ __launch_bounds__(kThreads) void k_trace_sched(
     if (lo >= hi) return;
     const int32_t ps = profile_stride(qlen);
     const int32_t cpb = profile_copy_bytes(ps);
-    build_profile<kCopies>(lds, ps, qcodes, qlen, km, bias);
+    build_profile<kCopies>(lds, ps, qcodes, qlen, km.m, bias, lds + profile_region_bytes(qlen, kCopies),
+                           threadIdx.x, blockDim.x);
     if (threadIdx.x == 0) s_ctr = (uint32_t)lo;
     __syncthreads();
     const int32_t lane = threadIdx.x & (kLanes - 1);
@@ -253,7 +254,8 @@ __global__ __launch_bounds__(kThreads) void k_trace_batch(
             const BatchQuery Q = qs[q];
             const int32_t ps = profile_stride(Q.qlen);
             const int32_t cpb = profile_copy_bytes(ps);
-            build_profile<kCopies>(lds, ps, qcodes + Q.qoff, Q.qlen, mats[q], Q.bias);
+            build_profile<kCopies>(lds, ps, qcodes + Q.qoff, Q.qlen, mats[q].m, Q.bias, lds + prof_bytes,
+                                   threadIdx.x, blockDim.x);
             __syncthreads();
             wave_trace<kCopies>(W, lane, cap, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, db,
                                 hits + (int64_t)q * k, hi, &s_ctr, alns + (int64_t)q * n_aln, ops,
