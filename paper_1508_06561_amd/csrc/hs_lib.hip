@@ -429,12 +429,12 @@ int launch_trace(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParam
                  int32_t n_aln, DevAln* d_alns, uint32_t* d_ops, int64_t ops_stride,
                  const QueryLayout& L) {
     const int32_t per_wg = L.waves;
-    int rc = set_lds_limit((const void*)k_trace_sched<kCopies>, L.lds);
+    const size_t lds = (size_t)trace_lds_bytes(profile_region_bytes(qlen, kCopies));
+    int rc = set_lds_limit((const void*)k_trace_sched<kCopies>, lds);
     if (rc) return rc;
     hipLaunchKernelGGL((k_trace_sched<kCopies>), dim3((n_aln + per_wg - 1) / per_wg),
-                       dim3(L.waves * kLanes), L.lds, st, db->view(), d_q, qlen, kp, km,
-                       matrix_bias(km), d_hits, d_n_hits,
-                       n_aln, per_wg, 1, d_alns, d_ops, ops_stride);
+                       dim3(L.waves * kLanes), lds, st, db->view(), d_q, qlen, kp, km,
+                       matrix_bias(km), d_hits, d_n_hits, n_aln, per_wg, d_alns, d_ops, ops_stride);
     HIP_TRY(hipGetLastError());
     return HS_OK;
 }

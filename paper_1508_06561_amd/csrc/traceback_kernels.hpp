@@ -2,10 +2,17 @@
 // pass keeps no per-pair state beyond the score and the winning round (the
 // constant auxiliary space of Section III.B.4); the aligned rows of the top
 // hits are recovered by replaying that round, which is deterministic because
-// every draw is keyed by (seed, target, round, draw index).  The replay runs
-// on the scoring pass's own wavefront scheduler and block scorer: each hit
-// is a slot, each step's placements are spread over the lanes in blocks of 8
-// diagonals, and each chosen placement becomes run-length ops.
+// every draw is keyed by (seed, target, round, draw index).  Every step's
+// placements are scored in blocks of 8 diagonals by the scoring pass's own
+// block scorer, so every step picks the placement the scoring pass picked,
+// and each chosen placement becomes run-length ops.  Two replays:
+//   * wave_trace_one (one query's hits): a wavefront replays one hit at a
+//     time, all its lanes sharing the pair state and taking a step's blocks
+//     side by side -- the fewest instructions per step, for hits that run
+//     on an otherwise idle device;
+//   * wave_trace_slots (a batch's hits): the scoring pass's slot scheduler
+//     with several hits per wavefront, so that they share each phase's
+//     fixed cost.
 #pragma once
 
 #include "device_common.hpp"
@@ -23,10 +30,10 @@ struct DevAln {
     int64_t ops_off;
 };
 
-// One alignment being recovered, held in the registers of its lane: the
-// winning round of a hit replayed step by step, each step's placement
-// appended to the alignment's ops.  Plain scalars only, so that the whole
-// state stays in registers.
+// One alignment being recovered (held by its lane in wave_trace_slots, by
+// every lane of the wavefront in wave_trace_one): the winning round of a hit
+// replayed step by step, each step's placement appended to the alignment's
+// ops.  Plain scalars only, so that the whole state stays in registers.
 struct TraceState {
     int32_t id;          // target index, -1 when the slot is empty
     int32_t a;           // alignment index (hits[a], alns[a])
@@ -62,16 +69,43 @@ __device__ __forceinline__ uint32_t trace_draw(TraceState& s, uint64_t seed, uin
     return (uint32_t)(x >> (16 * (d & 3))) & 0xFFFFu;
 }
 
-// Appends a run of l ops o, merging it with the previous run of the same op.
-__device__ __forceinline__ void trace_emit(TraceState& s, uint32_t o, int32_t l) {
+// Appends a run of l ops o, merging it with the previous run of the same op
+// (only the lane with `w` stores).
+__device__ __forceinline__ void trace_emit(TraceState& s, uint32_t o, int32_t l, bool w) {
     if (l <= 0) return;
     if (s.len && o == s.op) {
         s.len += (uint32_t)l;
         return;
     }
-    if (s.len) s.out[s.n_ops++] = (s.len << 2) | s.op;
+    if (s.len) {
+        if (w) s.out[s.n_ops] = (s.len << 2) | s.op;
+        ++s.n_ops;
+    }
     s.op = o;
     s.len = (uint32_t)l;
+}
+
+// Maximum over the wavefront (all 64 lanes active), in registers: DPP row
+// shifts give every row's maximum in its lane 15, row broadcasts carry it
+// to lane 63.  Lanes without a source contribute 0.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+    uint32_t y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false); x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false); x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false); x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false); x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false); x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false); x = x > y ? x : y;
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, kLanes - 1);
+}
+
+// Largest 64-bit key over the wavefront: the largest high word, then the
+// largest low word among the lanes holding it.
+__device__ __forceinline__ uint64_t wave_max_key(uint64_t key) {
+    const uint32_t h = (uint32_t)(key >> 32), l = (uint32_t)key;
+    const uint32_t hm = wave_max_u32(h);
+    const uint32_t lm = wave_max_u32(h == hm ? l : 0u);
+    return ((uint64_t)hm << 32) | lm;
 }
 
 // Draws the next step of the alignment or, after the last one, writes the
@@ -103,8 +137,8 @@ __device__ __forceinline__ void trace_advance(TraceState& s, const KParams& kp, 
         return;
     }
     s.score -= kp.pgp * ((s.nl - s.pL) + (s.ns - s.pS));
-    trace_emit(s, s.tl ? kOpD : kOpI, s.nl - s.pL);
-    trace_emit(s, s.tl ? kOpI : kOpD, s.ns - s.pS);
+    trace_emit(s, s.tl ? kOpD : kOpI, s.nl - s.pL, true);
+    trace_emit(s, s.tl ? kOpI : kOpD, s.ns - s.pS, true);
     if (s.len) s.out[s.n_ops++] = (s.len << 2) | s.op;
     DevAln out;
     out.target_id = s.id;
@@ -121,7 +155,7 @@ __device__ __forceinline__ void trace_advance(TraceState& s, const KParams& kp, 
 // pass (so every step picks the same placement) and alignment a is written
 // to alns[a], its ops to ops[ops_base + a * ops_stride ...].
 template <int kCopies>
-__device__ __forceinline__ void wave_trace(WaveLds& W, int32_t lane, int32_t cap,
+__device__ __forceinline__ void wave_trace_slots(WaveLds& W, int32_t lane, int32_t cap,
                                            const uint8_t* prof, int32_t ps, int32_t cpb,
                                            int32_t bias, int32_t qlen, const KParams& kp,
                                            const DbView& db, const DevHit* __restrict__ hits,
@@ -138,8 +172,8 @@ __device__ __forceinline__ void wave_trace(WaveLds& W, int32_t lane, int32_t cap
             const uint64_t key = W.slots[lane].key;
             const int32_t kb = key_shift(key);
             s.score += key_score(key) - shift_penalty(kp, s.t, kb);
-            trace_emit(s, s.tl ? kOpD : kOpI, kb);
-            trace_emit(s, kOpM, s.ss);
+            trace_emit(s, s.tl ? kOpD : kOpI, kb, true);
+            trace_emit(s, kOpM, s.ss, true);
             s.pL += kb + s.ss;
             s.pS += s.ss;
             ++s.t;
@@ -195,14 +229,115 @@ __device__ __forceinline__ void wave_trace(WaveLds& W, int32_t lane, int32_t cap
     }
 }
 
+// One wavefront's share of the alignments of one query: hit indices below
+// `hi`, taken one at a time from the workgroup counter `ctr`; alignment a is
+// written to alns[a], its ops to ops[ops_base + a * ops_stride ...].
+//
+// The winning round of each hit is replayed step by step.  Inside the
+// chop-and-consume loop only the small sequence receives gaps (Section
+// III.B.3) -- the k* skipped letters of large are target letters over gaps
+// (D) when the target is large and query letters over gaps (I) otherwise --
+// and after the loop the rest of whichever sequence is left goes against
+// gaps.  A step's blocks of 8 placements go to lanes 0, 1, ... (64 at a
+// time); the best block key over the wavefront is the step's placement.
+template <int kCopies>
+__device__ __forceinline__ void wave_trace_one(int32_t lane, const uint8_t* prof, int32_t ps,
+                                           int32_t cpb, int32_t bias, int32_t qlen,
+                                           const KParams& kp, const DbView& db,
+                                           const DevHit* __restrict__ hits, uint32_t hi,
+                                           uint32_t* ctr, DevAln* __restrict__ alns,
+                                           uint32_t* __restrict__ ops, int64_t ops_base,
+                                           int64_t ops_stride) {
+    const bool w = lane == 0;     // the lane that stores
+    for (;;) {
+        uint32_t a = 0;
+        if (w) a = atomicAdd(ctr, 1u);
+        a = (uint32_t)__builtin_amdgcn_readlane((int)a, 0);
+        if (a >= hi) return;
+        const DevHit h = hits[a];
+        const int32_t id = (int32_t)h.target_id;
+        if (id < 0 || id >= db.n || h.round < 0 || h.round >= kp.rounds) continue;
+        TraceState s;
+        const int32_t tlen = db.lens[id];
+        s.id = id;
+        s.tl = tlen >= qlen;
+        s.nl = s.tl ? tlen : qlen;
+        s.ns = s.tl ? qlen : tlen;
+        s.tbase = db.offsets[id];
+        s.round = h.round;
+        s.dblk = -1;
+        s.LF = round_factor(kp.lfactor, kp.minfactor, trace_draw(s, kp.seed, 0));
+        s.SF = round_factor(kp.sfactor, kp.minfactor, trace_draw(s, kp.seed, 1));
+        s.pL = s.pS = s.t = s.score = 0;
+        s.out = ops + ops_base + (int64_t)a * ops_stride;
+        s.n_ops = 0;
+        s.op = 0;
+        s.len = 0;
+        while (s.pL < s.nl && s.pS < s.ns) {
+            const int32_t ls = window_large(s.nl - s.pL, s.LF);
+            const int32_t ss =
+                window_small(s.ns - s.pS, s.SF, trace_draw(s, kp.seed, 2u + (uint32_t)s.t), ls);
+            const int32_t nk = ls - ss + 1;
+            const int32_t nblk = (nk + kBlockDiags - 1) / kBlockDiags;
+            SlotInfo si;
+            si.pL = s.pL;
+            si.pS = s.pS;
+            si.ss_tl = ss | (s.tl ? (int32_t)0x80000000 : 0);
+            si.nk = nk;
+            si.tbase = s.tbase;
+            si.key = 0;
+            uint64_t best = 0;       // below every placement's key
+            for (int32_t b0 = 0; b0 < nblk; b0 += kLanes) {
+                const int32_t k0 = (b0 + lane) * kBlockDiags;
+                if (k0 < nk) {
+                    BlockFetch f;
+                    fetch_block(si, k0, db.letters, f);
+                    // a lone wavefront is bound by latency: the high-ILP loop
+                    const uint64_t key = score_block<kCopies, true>(prof, ps, cpb, bias, si, k0, f);
+                    best = key > best ? key : best;
+                }
+            }
+            best = wave_max_key(best);
+            const int32_t kb = key_shift(best);
+            s.score += key_score(best) - shift_penalty(kp, s.t, kb);
+            trace_emit(s, s.tl ? kOpD : kOpI, kb, w);
+            trace_emit(s, kOpM, ss, w);
+            s.pL += kb + ss;
+            s.pS += ss;
+            ++s.t;
+        }
+        s.score -= kp.pgp * ((s.nl - s.pL) + (s.ns - s.pS));
+        trace_emit(s, s.tl ? kOpD : kOpI, s.nl - s.pL, w);
+        trace_emit(s, s.tl ? kOpI : kOpD, s.ns - s.pS, w);
+        if (s.len) {
+            if (w) s.out[s.n_ops] = (s.len << 2) | s.op;
+            ++s.n_ops;
+        }
+        if (w) {
+            DevAln out;
+            out.target_id = s.id;
+            out.score = s.score;
+            out.n_ops = s.n_ops;
+            out.ops_off = ops_base + (int64_t)a * ops_stride;
+            alns[a] = out;
+        }
+    }
+}
+
+// LDS of a replay workgroup: the profile region, then the substitution rows
+// staged by build_profile.
+__host__ __device__ inline int32_t trace_lds_bytes(int32_t prof_bytes) {
+    return prof_bytes + ((kProfRows * kNsym + 15) & ~15);
+}
+
 // Alignments of one query: workgroup g recovers hits [g * per_wg, (g + 1) *
-// per_wg) below min(n_aln, n_hits), at most `cap` per wavefront at a time.
+// per_wg) below min(n_aln, n_hits), one per wavefront at a time.
 template <int kCopies>
 __global__ __launch_bounds__(kThreads) void k_trace_sched(
     DbView db, const uint8_t* __restrict__ qcodes, int32_t qlen, KParams kp, KMatrix km,
     int32_t bias, const DevHit* __restrict__ hits, const int32_t* __restrict__ n_hits,
-    int32_t n_aln, int32_t per_wg, int32_t cap, DevAln* __restrict__ alns,
-    uint32_t* __restrict__ ops, int64_t ops_stride) {
+    int32_t n_aln, int32_t per_wg, DevAln* __restrict__ alns, uint32_t* __restrict__ ops,
+    int64_t ops_stride) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t s_ctr;
     const int32_t nh = *n_hits < n_aln ? *n_hits : n_aln;
@@ -215,15 +350,15 @@ __global__ __launch_bounds__(kThreads) void k_trace_sched(
                            threadIdx.x, blockDim.x);
     if (threadIdx.x == 0) s_ctr = (uint32_t)lo;
     __syncthreads();
-    const int32_t lane = threadIdx.x & (kLanes - 1);
-    WaveLds& W = ((WaveLds*)(lds + profile_region_bytes(qlen, kCopies)))[threadIdx.x / kLanes];
-    wave_trace<kCopies>(W, lane, cap, lds, ps, cpb, bias, qlen, kp, db, hits, (uint32_t)hi, &s_ctr,
-                        alns, ops, 0, ops_stride);
+    wave_trace_one<kCopies>(threadIdx.x & (kLanes - 1), lds, ps, cpb, bias, qlen, kp, db, hits,
+                        (uint32_t)hi, &s_ctr, alns, ops, 0, ops_stride);
 }
 
 // Alignments of a batch, persistent: a workgroup takes work items (query q,
 // hit range [lo, hi)) from the counter, builds the query's profile and
-// recovers the item's hits below min(hi, n_hits[q]).  Query q's hits start at
+// recovers the item's hits below min(hi, n_hits[q]), up to `cap` per
+// wavefront in flight (slot-based replay: a wavefront's hits share each
+// phase's fixed cost).  Query q's hits start at
 // hits[q * k], its alignments at alns[q * n_aln], and the ops of alignment
 // (q, a) at ops[(q * n_aln + a) * ops_stride].
 template <int kCopies>
@@ -257,7 +392,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_batch(
             build_profile<kCopies>(lds, ps, qcodes + Q.qoff, Q.qlen, mats[q].m, Q.bias, lds + prof_bytes,
                                    threadIdx.x, blockDim.x);
             __syncthreads();
-            wave_trace<kCopies>(W, lane, cap, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, db,
+            wave_trace_slots<kCopies>(W, lane, cap, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, db,
                                 hits + (int64_t)q * k, hi, &s_ctr, alns + (int64_t)q * n_aln, ops,
                                 (int64_t)q * n_aln * ops_stride, ops_stride);
         }
