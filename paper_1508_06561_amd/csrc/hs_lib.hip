@@ -407,16 +407,20 @@ int launch_rank(const hs_db* db, hipStream_t st, const int32_t* scores, const in
                 int64_t stride, int32_t nq, int32_t k, const TopkWs& tw, DevHit* d_hits,
                 int32_t* d_n_hits) {
     const int32_t n = (int32_t)db->n_targets;
-    // about 512 workgroups over all queries
-    const int tb = std::max(1, std::min(std::max(1, 512 / nq), (n + 255) / 256));
+    // about 128 workgroups over all queries (each merges its histogram into
+    // the query's with one global atomic per non-empty bin, so fewer, fuller
+    // workgroups contend less), at least 1024 scores each
+    const int tb = std::max(1, std::min(std::max(1, 128 / nq), (n + 1023) / 1024));
     hipLaunchKernelGGL(k_topk_hist, dim3(tb, nq), dim3(256), 0, st, scores, stride, n, tw);
     hipLaunchKernelGGL(k_topk_pick, dim3(1, nq), dim3(256), 0, st, k, n, tw);
     hipLaunchKernelGGL(k_topk_collect, dim3(tb, nq), dim3(256), 0, st, scores, stride, n, tw);
-    const size_t lds = sizeof(uint64_t) * kSortCap;
+    const size_t lds = sizeof(uint64_t) * (kSortCap + 8);
     int rc = set_lds_limit((const void*)k_topk_final, lds);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_topk_final, dim3(1, nq), dim3(1024), lds, st, scores, stride, rounds, n,
-                       k, tw, d_hits, d_n_hits);
+    // enough workgroups for k keys and some ties; more keys are strided
+    const int fg = std::max(1, std::min(kFinalGroups, (k + kFinalThreads - 1) / kFinalThreads + 1));
+    hipLaunchKernelGGL(k_topk_final, dim3(fg, nq), dim3(kFinalThreads), lds, st, scores, stride,
+                       rounds, n, k, tw, d_hits, d_n_hits);
     HIP_TRY(hipGetLastError());
     return HS_OK;
 }

@@ -242,13 +242,20 @@ __device__ uint64_t radix_select_block(const int32_t* sc, int32_t n, int32_t min
     return prefix;
 }
 
-// One workgroup per query: sorts the gathered keys (fast path) or runs the
-// radix select (fallback), then writes the ranked hits.
-__global__ __launch_bounds__(1024) void k_topk_final(const int32_t* __restrict__ scores, int64_t stride,
-                                                     const int32_t* __restrict__ rounds, int32_t n,
-                                                     int32_t k, TopkWs w,
-                                                     DevHit* __restrict__ hits, int32_t* __restrict__ n_hits) {
-    extern __shared__ __align__(16) uint64_t s[];        // kSortCap keys
+// Keys ranked per workgroup of k_topk_final's fast path.
+constexpr int kFinalThreads = 256;
+constexpr int kFinalGroups = kSortCap / kFinalThreads;
+
+// Writes the ranked hits: blockIdx.y is the query.  Fast path: every
+// workgroup loads all gathered keys into LDS and ranks its share of them
+// (keys blockIdx.x * kFinalThreads + t, strided by the grid) -- a key's rank
+// is the number of larger keys (all keys differ) -- writing each hit
+// straight to its rank, so that the workgroups need no synchronisation.
+// Fallback: workgroup 0 runs the radix select and sorts.
+__global__ __launch_bounds__(kFinalThreads) void k_topk_final(
+    const int32_t* __restrict__ scores, int64_t stride, const int32_t* __restrict__ rounds,
+    int32_t n, int32_t k, TopkWs w, DevHit* __restrict__ hits, int32_t* __restrict__ n_hits) {
+    extern __shared__ __align__(16) uint64_t s[];        // kSortCap + 8 keys
     __shared__ uint32_t hist[256];
     __shared__ uint32_t part[4];
     __shared__ uint32_t cnt;
@@ -258,23 +265,21 @@ __global__ __launch_bounds__(1024) void k_topk_final(const int32_t* __restrict__
     const int32_t* sc = scores + (int64_t)q * stride;
     const int32_t* rd = rounds + (int64_t)q * stride;
     DevHit* out = hits + (int64_t)q * k;
-    int32_t m_keys;
-    int32_t n_out;
     if (!st->fallback) {
         const int32_t c = st->count < kSortCap ? st->count : kSortCap;
+        const int32_t n_out = st->n_sel < c ? st->n_sel : c;
+        if (blockIdx.x == 0 && threadIdx.x == 0) n_hits[q] = n_out;
+        const int32_t first = blockIdx.x * kFinalThreads;
+        if (first >= c) return;
         const uint64_t* keys = w.keys + (int64_t)q * kSortCap;
-        n_out = st->n_sel < c ? st->n_sel : c;
-        m_keys = c;
-        if (c <= (int32_t)blockDim.x) {
-            // one key per thread: its rank is the number of larger keys (all
-            // keys differ), found in one pass over the keys in LDS
-            const uint64_t mine = threadIdx.x < (uint32_t)c ? keys[threadIdx.x] : 0ull;
-            s[threadIdx.x] = mine;
-            __syncthreads();
-            // keys past c are 0 and never larger, so the scan may run to a
-            // multiple of 8 (two keys per LDS read, four reads in flight)
-            if (threadIdx.x < 8u) s[c + threadIdx.x] = 0ull;
-            __syncthreads();
+        for (int32_t i = threadIdx.x; i < c; i += kFinalThreads) s[i] = keys[i];
+        // keys past c are 0 and never larger, so the scan may run to a
+        // multiple of 8 (two keys per LDS read, four reads in flight)
+        if (threadIdx.x < 8u) s[c + threadIdx.x] = 0ull;
+        __syncthreads();
+        // keys first, first + 1, ... of every kFinalThreads * gridDim.x
+        for (int32_t i = first + (int32_t)threadIdx.x; i < c; i += kFinalThreads * (int32_t)gridDim.x) {
+            const uint64_t mine = s[i];
             int32_t r = 0;
             const uint4* s2 = (const uint4*)s;
             for (int32_t j = 0; j < c; j += 8) {
@@ -284,49 +289,46 @@ __global__ __launch_bounds__(1024) void k_topk_final(const int32_t* __restrict__
                 r += (((uint64_t)e.y << 32 | e.x) > mine) + (((uint64_t)e.w << 32 | e.z) > mine);
                 r += (((uint64_t)f.y << 32 | f.x) > mine) + (((uint64_t)f.w << 32 | f.z) > mine);
             }
-            __syncthreads();
-            if (threadIdx.x < (uint32_t)c && r < n_out) s[r] = mine;
-            __syncthreads();
-        } else {
-            int32_t m = 1;
-            while (m < c) m <<= 1;
-            for (int i = threadIdx.x; i < m; i += blockDim.x) s[i] = i < c ? keys[i] : 0ull;
-            __syncthreads();
-            bitonic_desc(s, m);
-        }
-    } else {
-        // k-th largest key, then gather the keys at or above it
-        int32_t eligible = 0;
-        if (threadIdx.x == 0) cnt = 0;
-        __syncthreads();
-        for (int32_t i = threadIdx.x; i < n; i += blockDim.x)
-            if (sc[i] >= min_score) atomicAdd(&cnt, 1u);
-        __syncthreads();
-        eligible = (int32_t)cnt;
-        n_out = eligible < k ? eligible : k;
-        const uint64_t kth = n_out > 0 ? radix_select_block(sc, n, min_score, n_out, hist, part) : ~0ull;
-        if (threadIdx.x == 0) cnt = 0;
-        __syncthreads();
-        for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const int32_t v = sc[i];
-            if (v < min_score) continue;
-            const uint64_t key = rank_key(v, i);
-            if (key >= kth) {
-                const uint32_t slot = atomicAdd(&cnt, 1u);
-                if (slot < (uint32_t)kSortCap) s[slot] = key;
+            if (r < n_out) {
+                const int32_t id = rank_key_id(mine);
+                DevHit h;
+                h.target_id = id;
+                h.score = rank_key_score(mine);
+                h.round = (id >= 0 && id < n) ? rd[id] : -1;
+                out[r] = h;
             }
         }
-        __syncthreads();
-        int32_t c = (int32_t)cnt < kSortCap ? (int32_t)cnt : kSortCap;
-        int32_t m = 1;
-        while (m < c) m <<= 1;
-        for (int i = c + threadIdx.x; i < m; i += blockDim.x) s[i] = 0ull;
-        __syncthreads();
-        bitonic_desc(s, m);
-        m_keys = c;
-        n_out = n_out < c ? n_out : c;
+        return;
     }
-    (void)m_keys;
+    if (blockIdx.x != 0) return;
+    // k-th largest key, then gather the keys at or above it and sort them
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x)
+        if (sc[i] >= min_score) atomicAdd(&cnt, 1u);
+    __syncthreads();
+    const int32_t eligible = (int32_t)cnt;
+    int32_t n_out = eligible < k ? eligible : k;
+    const uint64_t kth = n_out > 0 ? radix_select_block(sc, n, min_score, n_out, hist, part) : ~0ull;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int32_t v = sc[i];
+        if (v < min_score) continue;
+        const uint64_t key = rank_key(v, i);
+        if (key >= kth) {
+            const uint32_t slot = atomicAdd(&cnt, 1u);
+            if (slot < (uint32_t)kSortCap) s[slot] = key;
+        }
+    }
+    __syncthreads();
+    const int32_t c = (int32_t)cnt < kSortCap ? (int32_t)cnt : kSortCap;
+    int32_t m = 1;
+    while (m < c) m <<= 1;
+    for (int i = c + threadIdx.x; i < m; i += blockDim.x) s[i] = 0ull;
+    __syncthreads();
+    bitonic_desc(s, m);
+    n_out = n_out < c ? n_out : c;
     for (int i = threadIdx.x; i < n_out; i += blockDim.x) {
         const uint64_t key = s[i];
         const int32_t id = rank_key_id(key);
