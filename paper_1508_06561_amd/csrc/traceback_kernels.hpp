@@ -149,19 +149,20 @@ __device__ __forceinline__ void trace_advance(TraceState& s, const KParams& kp, 
     s.id = -1;
 }
 
-// One wavefront's share of the alignments of one query: hit indices below
-// `hi` taken from the workgroup counter `ctr`, at most `cap` in flight.  The
-// winning round of each hit is replayed with the block scorer of the scoring
-// pass (so every step picks the same placement) and alignment a is written
-// to alns[a], its ops to ops[ops_base + a * ops_stride ...].
+// Slot-based replay (a batch's hits): one wavefront's share of the
+// alignments of one query, hit indices below `hi` taken from the workgroup
+// counter `ctr`, at most `cap` in flight, one per lane.  The winning round of
+// each hit is replayed on the scoring pass's scheduler and block scorer (so
+// every step picks the same placement) and alignment a is written to
+// alns[a], its ops to ops[ops_base + a * ops_stride ...].
 template <int kCopies>
 __device__ __forceinline__ void wave_trace_slots(WaveLds& W, int32_t lane, int32_t cap,
-                                           const uint8_t* prof, int32_t ps, int32_t cpb,
-                                           int32_t bias, int32_t qlen, const KParams& kp,
-                                           const DbView& db, const DevHit* __restrict__ hits,
-                                           uint32_t hi, uint32_t* ctr, DevAln* __restrict__ alns,
-                                           uint32_t* __restrict__ ops, int64_t ops_base,
-                                           int64_t ops_stride) {
+                                                 const uint8_t* prof, int32_t ps, int32_t cpb,
+                                                 int32_t bias, int32_t qlen, const KParams& kp,
+                                                 const DbView& db, const DevHit* __restrict__ hits,
+                                                 uint32_t hi, uint32_t* ctr, DevAln* __restrict__ alns,
+                                                 uint32_t* __restrict__ ops, int64_t ops_base,
+                                                 int64_t ops_stride) {
     TraceState s;
     s.id = -1;
     s.stepping = false;
