@@ -512,6 +512,7 @@ struct hs_batch {
     int32_t waves = kWaves;             // wavefronts per workgroup (LDS permitting)
     // alignment pass: hits per work item, in flight per wavefront, workgroups
     int32_t tchunk = 0, tcap = 0, tgrid = 0, n_titems = 0;
+    bool trace_one = false;          // alignments one hit per wavefront
     // graph of one whole search
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -594,9 +595,14 @@ int upload_items(hs_batch* b, hipStream_t st) {
         }
     if ((int64_t)items.size() > b->max_items) return fail(HS_EINVAL, "too many work items");
     b->n_items = (int32_t)items.size();
-    // alignment items: each query's first n_aln ranks, in ranges of tchunk
+    // alignment items: each query's first n_aln ranks, in ranges of tchunk.
+    // A small batch, whose items of one hit per wavefront all fit on the
+    // device at once, replays one hit per wavefront; a large one keeps each
+    // query's hits in one item, several per wavefront (slot-based).
     std::vector<BatchItem> titems;
-    b->tchunk = std::max(b->n_aln, 1);
+    const int64_t one_items = (int64_t)b->nq * ((b->n_aln + b->waves - 1) / b->waves);
+    b->trace_one = b->n_aln > 0 && one_items <= std::min<int64_t>(b->max_titems, 2 * (int64_t)device_cus());
+    b->tchunk = b->trace_one ? b->waves : std::max(b->n_aln, 1);
     b->tcap = std::min(kLanes, (b->tchunk + b->waves - 1) / b->waves);
     for (int32_t q : order)
         for (int32_t lo = 0; lo < b->n_aln; lo += b->tchunk) {
@@ -707,7 +713,8 @@ void launch_trace_batch(const hs_batch* b, hipStream_t st) {
                        batch_lds(b, kCopies), st, b->db->view(), (const BatchQuery*)b->d_qs,
                        (const KMatrix*)b->d_mats, (const uint8_t*)b->d_qcodes,
                        (const BatchItem*)b->d_titems, b->n_titems, b->d_ctr + 1,
-                       (int32_t)batch_prof_bytes(b->cur_max_qlen, kCopies), b->tcap, b->k,
+                       (int32_t)batch_prof_bytes(b->cur_max_qlen, kCopies), b->tcap,
+                       (int32_t)b->trace_one, b->k,
                        (const DevHit*)b->d_hits, (const int32_t*)b->d_n_hits, b->n_aln,
                        b->d_alns, b->d_ops, b->ops_stride);
 }
@@ -996,7 +1003,8 @@ int hs_batch_create(const hs_db* db, int32_t max_nq, int32_t max_qlen, int64_t m
     b->ops_stride = 2 * (int64_t)max_qlen + 2;
     const int64_t chunks = (db->n_queue + min_chunk(db) - 1) / min_chunk(db);
     b->max_items = (int64_t)max_nq * std::max<int64_t>(chunks, 1);
-    b->max_titems = (int64_t)max_nq;
+    // one item per query, or for a small batch up to two per compute unit
+    b->max_titems = std::max<int64_t>((int64_t)max_nq, 2 * (int64_t)device_cus());
     const size_t nt = (size_t)std::max<int64_t>(db->n_targets, 1);
     const size_t nal = (size_t)max_nq * (size_t)std::max(n_aln, 1);
     // one device allocation, carved below

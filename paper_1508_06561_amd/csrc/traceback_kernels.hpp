@@ -420,16 +420,17 @@ __global__ __launch_bounds__(kThreads) void k_trace_sched(
 
 // Alignments of a batch, persistent: a workgroup takes work items (query q,
 // hit range [lo, hi)) from the counter, builds the query's profile and
-// recovers the item's hits below min(hi, n_hits[q]), up to `cap` per
-// wavefront in flight (slot-based replay: a wavefront's hits share each
-// phase's fixed cost).  Query q's hits start at
+// recovers the item's hits below min(hi, n_hits[q]): with `one`, one hit per
+// wavefront at a time (a small batch, whose items all run at once); else up
+// to `cap` per wavefront in flight (slot-based replay: a wavefront's hits
+// share each phase's fixed cost).  Query q's hits start at
 // hits[q * k], its alignments at alns[q * n_aln], and the ops of alignment
 // (q, a) at ops[(q * n_aln + a) * ops_stride].
 template <int kCopies>
 __global__ __launch_bounds__(kThreads) void k_trace_batch(
     DbView db, const BatchQuery* __restrict__ qs, const KMatrix* __restrict__ mats,
     const uint8_t* __restrict__ qcodes, const BatchItem* __restrict__ items, int32_t n_items,
-    uint32_t* item_ctr, int32_t prof_bytes, int32_t cap, int32_t k,
+    uint32_t* item_ctr, int32_t prof_bytes, int32_t cap, int32_t one, int32_t k,
     const DevHit* __restrict__ hits, const int32_t* __restrict__ n_hits, int32_t n_aln,
     DevAln* __restrict__ alns, uint32_t* __restrict__ ops, int64_t ops_stride) {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -456,9 +457,14 @@ __global__ __launch_bounds__(kThreads) void k_trace_batch(
             build_profile<kCopies>(lds, ps, qcodes + Q.qoff, Q.qlen, mats[q].m, Q.bias, lds + prof_bytes,
                                    threadIdx.x, blockDim.x);
             __syncthreads();
-            wave_trace_slots<kCopies>(W, lane, cap, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, db,
-                                hits + (int64_t)q * k, hi, &s_ctr, alns + (int64_t)q * n_aln, ops,
-                                (int64_t)q * n_aln * ops_stride, ops_stride);
+            if (one)
+                wave_trace_one<kCopies>(lane, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, db,
+                                        hits + (int64_t)q * k, hi, &s_ctr, alns + (int64_t)q * n_aln,
+                                        ops, (int64_t)q * n_aln * ops_stride, ops_stride);
+            else
+                wave_trace_slots<kCopies>(W, lane, cap, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, db,
+                                          hits + (int64_t)q * k, hi, &s_ctr, alns + (int64_t)q * n_aln,
+                                          ops, (int64_t)q * n_aln * ops_stride, ops_stride);
         }
         __syncthreads();   // the profile and the counter are rewritten for the next item
     }
