@@ -219,7 +219,8 @@ int hs_batch_set(hs_batch* b, int32_t nq, const char* residues, const int64_t* o
 /* Fixes the schedule of the scoring launch (results do not depend on it):
  *   copies   score-profile copies in LDS, 1 or 4 (4: aligned reads; needs
  *            more LDS), 0 = 4 whenever it fits
- *   cap      pairs in flight per wavefront, 1..64, 0 = 64
+ *   cap      pairs in flight per wavefront, 1..64, 0 = an item's positions
+ *            shared by the workgroup's wavefronts (at most 64)
  *   chunk    target positions per work item, a multiple of 64, 0 = sized
  *            so that every workgroup gets about four items
  * Applies to the current queries at once and to every later hs_batch_set. */

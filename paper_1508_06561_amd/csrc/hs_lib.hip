@@ -668,6 +668,10 @@ int choose_schedule(hs_batch* b, hipStream_t st) {
         b->chunk = (int32_t)std::min<int64_t>(round64(std::max<int64_t>(b->db->n_queue, 64)),
                                               std::max<int64_t>(round64(want), min_chunk(b->db)));
     }
+    // pairs in flight per wavefront: an item's positions shared by all the
+    // workgroup's wavefronts (with 64, the first wavefront would take a
+    // small item whole and leave the others idle)
+    if (!b->fix_cap) b->cap = std::min(kLanes, std::max(1, (b->chunk + b->waves - 1) / b->waves));
     return upload_items(b, st);
 }
 
