@@ -513,6 +513,7 @@ struct hs_batch {
     // alignment pass: hits per work item, in flight per wavefront, workgroups
     int32_t tchunk = 0, tcap = 0, tgrid = 0, n_titems = 0;
     bool trace_one = false;          // alignments one hit per wavefront
+    bool score_one = false;          // scoring one pair per wavefront
     // graph of one whole search
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -654,16 +655,29 @@ int choose_schedule(hs_batch* b, hipStream_t st) {
     int rc = prefer_ilp(batch_kernel(b->copies, false, false), batch_kernel(b->copies, false, true),
                         b->waves * kLanes, batch_lds(b, b->copies), &b->ilp);
     if (rc) return rc;
-    if (b->fix_chunk) {
-        b->chunk = std::max(b->fix_chunk, min_chunk(b->db));
-    } else {
-        int per_cu = 0;
+    int per_cu = 0;
+    {
         const void* fn = batch_kernel(b->copies, false, b->ilp);
         const size_t lds = batch_lds(b, b->copies);
         rc = set_lds_limit(fn, lds);
         if (rc) return rc;
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, b->waves * kLanes, lds));
-        const int64_t wgs = (int64_t)std::max(per_cu, 1) * device_cus();
+    }
+    const int64_t wgs = (int64_t)std::max(per_cu, 1) * device_cus();
+    // A batch whose items of one pair per wavefront all fit on the device at
+    // once is scored one pair per wavefront, all lanes on the pair: the
+    // chains of steps, not the lanes, set its time.
+    const int64_t one_items = (int64_t)b->nq * ((b->db->n_queue + b->waves - 1) / b->waves);
+    b->score_one = !b->fix_cap && !b->fix_chunk && b->db->n_queue > 0 &&
+                   one_items <= std::min<int64_t>(wgs, b->max_items);
+    if (b->score_one) {
+        b->chunk = b->waves;
+        b->cap = 1;
+        return upload_items(b, st);
+    }
+    if (b->fix_chunk) {
+        b->chunk = std::max(b->fix_chunk, min_chunk(b->db));
+    } else {
         const int64_t want = (int64_t)b->nq * b->db->n_queue / (4 * wgs);
         b->chunk = (int32_t)std::min<int64_t>(round64(std::max<int64_t>(b->db->n_queue, 64)),
                                               std::max<int64_t>(round64(want), min_chunk(b->db)));
@@ -683,6 +697,7 @@ void launch_batch_kernel(const hs_batch* b, hipStream_t st, uint64_t* d_cells) {
                        (const KMatrix*)b->d_mats, (const uint8_t*)b->d_qcodes,
                        (const BatchItem*)b->d_items, b->n_items, b->d_ctr,
                        (int32_t)batch_prof_bytes(b->cur_max_qlen, kCopies), b->cap,
+                       (int32_t)b->score_one,
                        (const PairRec*)db->d_recs, (const uint8_t*)db->d_letters,
                        (const uint64_t*)b->d_draws, b->d_scores, b->d_rounds,
                        (int64_t)db->n_targets, &b->d_st->max_score,
@@ -1006,7 +1021,10 @@ int hs_batch_create(const hs_db* db, int32_t max_nq, int32_t max_qlen, int64_t m
     b->n_aln = n_aln;
     b->ops_stride = 2 * (int64_t)max_qlen + 2;
     const int64_t chunks = (db->n_queue + min_chunk(db) - 1) / min_chunk(db);
-    b->max_items = (int64_t)max_nq * std::max<int64_t>(chunks, 1);
+    // items of min_chunk positions, or for a small batch one position per
+    // wavefront, up to two workgroups per compute unit
+    b->max_items = std::max<int64_t>((int64_t)max_nq * std::max<int64_t>(chunks, 1),
+                                     2 * (int64_t)device_cus());
     // one item per query, or for a small batch up to two per compute unit
     b->max_titems = std::max<int64_t>((int64_t)max_nq, 2 * (int64_t)device_cus());
     const size_t nt = (size_t)std::max<int64_t>(db->n_targets, 1);

@@ -820,6 +820,196 @@ __device__ __forceinline__ int32_t wave_max_i32(int32_t x) {
 }
 
 
+// Maximum over the wavefront (all 64 lanes active), in registers: DPP row
+// shifts give every row's maximum in its lane 15, row broadcasts carry it
+// to lane 63.  Lanes without a source contribute 0.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+    uint32_t y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false); x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false); x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false); x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false); x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false); x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false); x = x > y ? x : y;
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, kLanes - 1);
+}
+
+// Largest 64-bit key over the wavefront: the largest high word, then the
+// largest low word among the lanes holding it.
+__device__ __forceinline__ uint64_t wave_max_key(uint64_t key) {
+    const uint32_t h = (uint32_t)(key >> 32), l = (uint32_t)key;
+    const uint32_t hm = wave_max_u32(h);
+    const uint32_t lm = wave_max_u32(h == hm ? l : 0u);
+    return ((uint64_t)hm << 32) | lm;
+}
+
+// Sum over aligned groups of P = 1 << lg lanes (lg <= 4, so that a group
+// lies within a row of 16 lanes), valid in each group's last lane: DPP row
+// shifts by 1, 2, .. P / 2 (adds only), after which lane L holds lanes
+// L - P + 1 .. L.  (A subtraction with a DPP operand is avoided: folded into
+// a reversed subtract, it returned the negated difference here.)
+__device__ __forceinline__ uint32_t group_sum(uint32_t x, int32_t lg) {
+    if (lg > 0) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    if (lg > 1) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    if (lg > 2) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    if (lg > 3) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    return x;
+}
+
+// Best placement of one step, cell-parallel (the step's placements are
+// few, or short): P = 1 << lg lanes per placement, lane l summing cells
+// [(l % P) * per, ...) of placement d0 + l / P, 64 / P placements per round.
+// Cell (k, j) pairs large letter pL + k + j with small letter pS + j; its
+// biased score is the profile byte of the target letter's row at the query
+// letter's column.  Returns the lane's best key over the rounds (0 in lanes
+// that end no group).
+__device__ __forceinline__ uint64_t step_best_cells(const uint8_t* prof, int32_t ps, int32_t bias,
+                                                    const uint8_t* __restrict__ tletters,
+                                                    bool tl, int32_t pL, int32_t pS, int32_t ss,
+                                                    int32_t nk, int32_t lane, int32_t lg) {
+    const int32_t P = 1 << lg;
+    const int32_t per = (ss + P - 1) >> lg;
+    const int32_t j0 = (lane & (P - 1)) * per;
+    const int32_t j1 = j0 + per < ss ? j0 + per : ss;
+    const bool last = (lane & (P - 1)) == P - 1;
+    const int32_t off = bias * ss;
+    uint64_t best = 0;
+    for (int32_t d0 = 0; d0 < nk; d0 += kLanes >> lg) {
+        const int32_t k = d0 + (lane >> lg);
+        uint32_t sum = 0;
+        if (k < nk) {
+            // target letter at tpos + j, query column qcol + j (profile copy 0)
+            const int32_t tpos = tl ? pL + k : pS;
+            const int32_t qcol = (tl ? pS : pL + k) + kPad;
+#pragma unroll 4
+            for (int32_t j = j0; j < j1; ++j)
+                sum += prof[__umul24((uint32_t)tletters[tpos + j], (uint32_t)ps) + (uint32_t)(qcol + j)];
+        }
+        sum = group_sum(sum, lg);
+        if (last && k < nk) {
+            const uint64_t key = shift_key((int32_t)sum - off, k);
+            best = key > best ? key : best;
+        }
+    }
+    return best;
+}
+
+// One step of a pair followed by every lane of a wavefront (all 64 lanes
+// active): the wavefront's best placement key over the step's nk
+// placements.  Whichever scorer has the shorter serial loop: the step's
+// blocks of 8 diagonals side by side on the lanes (the scoring pass's block
+// scorer, high-ILP loop: a lone wavefront is bound by latency), or every
+// placement's cells spread over up to 16 lanes.
+template <int kCopies>
+__device__ __forceinline__ uint64_t wave_step_key(int32_t lane, const uint8_t* prof, int32_t ps,
+                                                  int32_t cpb, int32_t bias,
+                                                  const uint8_t* __restrict__ letters,
+                                                  int64_t tbase, bool tl, int32_t pL, int32_t pS,
+                                                  int32_t ss, int32_t nk) {
+    const int32_t nblk = (nk + kBlockDiags - 1) / kBlockDiags;
+    int32_t lg = 0;
+    while (lg < 4 && (nk << (lg + 1)) <= kLanes && (1 << (lg + 1)) <= ss) ++lg;
+    const int32_t cells_it = ((nk + (kLanes >> lg) - 1) / (kLanes >> lg)) * ((ss + (1 << lg) - 1) >> lg);
+    const int32_t block_it = ((nblk + kLanes - 1) / kLanes) * (ss + (tl ? 14 : 0));
+    uint64_t best = 0;       // below every placement's key
+    if (2 * cells_it <= block_it + 64) {
+        best = step_best_cells(prof, ps, bias, letters + tbase, tl, pL, pS, ss, nk, lane, lg);
+    } else {
+        SlotInfo si;
+        si.pL = pL;
+        si.pS = pS;
+        si.ss_tl = ss | (tl ? (int32_t)0x80000000 : 0);
+        si.nk = nk;
+        si.tbase = tbase;
+        si.key = 0;
+        for (int32_t b0 = 0; b0 < nblk; b0 += kLanes) {
+            const int32_t k0 = (b0 + lane) * kBlockDiags;
+            if (k0 < nk) {
+                BlockFetch f;
+                fetch_block(si, k0, letters, f);
+                const uint64_t key = score_block<kCopies, true>(prof, ps, cpb, bias, si, k0, f);
+                best = key > best ? key : best;
+            }
+        }
+    }
+    return wave_max_key(best);
+}
+
+// random() draws of one (target, round), computed one Philox block at a
+// time and cached.
+struct DrawCache {
+    int32_t blk;                     // Philox block held in w (-1: none)
+    uint64_t w[4];
+};
+__device__ __forceinline__ uint32_t cached_draw(DrawCache& c, uint64_t seed, int32_t id,
+                                                int32_t round, uint32_t d) {
+    const int32_t b = (int32_t)(d >> 4);
+    if (b != c.blk) {
+        philox_block(seed, (uint64_t)id, (uint32_t)round, (uint32_t)b, c.w);
+        c.blk = b;
+    }
+    const uint32_t wi = (d >> 2) & 3;
+    const uint64_t x = wi == 0 ? c.w[0] : wi == 1 ? c.w[1] : wi == 2 ? c.w[2] : c.w[3];
+    return (uint32_t)(x >> (16 * (d & 3))) & 0xFFFFu;
+}
+
+// One pair per wavefront at a time (for searches with no more pairs than
+// resident wavefronts, where each pair's chain of steps sets the time):
+// hand-out positions below `hi` from the counter `ctr`, every lane following
+// the pair, every round's steps by wave_step_key; the best round's score (the
+// first best) goes to scores[target], the round to rounds[target].  Same
+// arithmetic as wave_pairs, so the same scores.
+template <int kCopies, bool kCount>
+__device__ __forceinline__ void wave_score_one(int32_t lane, const uint8_t* prof, int32_t ps,
+                                               int32_t cpb, int32_t bias, int32_t qlen,
+                                               const KParams& kp, const PairRec* __restrict__ recs,
+                                               uint32_t hi, const uint8_t* __restrict__ letters,
+                                               uint32_t* ctr, int32_t* __restrict__ scores,
+                                               int32_t* __restrict__ rounds, uint64_t& cells,
+                                               int32_t& best_seen) {
+    const bool w = lane == 0;     // the lane that stores (and counts)
+    for (;;) {
+        uint32_t qi = 0;
+        if (w) qi = atomicAdd(ctr, 1u);
+        qi = (uint32_t)__builtin_amdgcn_readlane((int)qi, 0);
+        if (qi >= hi) return;
+        const PairRec r = recs[qi];
+        if (r.id < 0) continue;
+        const bool tl = r.len >= qlen;
+        const int32_t nl = tl ? r.len : qlen, ns = tl ? qlen : r.len;
+        int32_t best = INT32_MIN, best_round = 0;
+        for (int32_t round = 0; round < kp.rounds; ++round) {
+            DrawCache dc;
+            dc.blk = -1;
+            const uint32_t LF = round_factor(kp.lfactor, kp.minfactor, cached_draw(dc, kp.seed, r.id, round, 0));
+            const uint32_t SF = round_factor(kp.sfactor, kp.minfactor, cached_draw(dc, kp.seed, r.id, round, 1));
+            int32_t pL = 0, pS = 0, score = 0;
+            for (int32_t t = 0; pL < nl && pS < ns; ++t) {
+                const int32_t ls = window_large(nl - pL, LF);
+                const int32_t ss = window_small(ns - pS, SF, cached_draw(dc, kp.seed, r.id, round, 2u + (uint32_t)t), ls);
+                const int32_t nk = ls - ss + 1;
+                if (kCount && w) cells += (uint64_t)nk * (uint64_t)ss;
+                const uint64_t key = wave_step_key<kCopies>(lane, prof, ps, cpb, bias, letters, r.offset,
+                                                            tl, pL, pS, ss, nk);
+                const int32_t kb = key_shift(key);
+                score += key_score(key) - shift_penalty(kp, t, kb);
+                pL += kb + ss;
+                pS += ss;
+            }
+            score -= kp.pgp * ((nl - pL) + (ns - pS));
+            if (score > best) {
+                best = score;
+                best_round = round;
+            }
+        }
+        if (w) {
+            scores[r.id] = best;
+            if (rounds) rounds[r.id] = best_round;
+        }
+        best_seen = best > best_seen ? best : best_seen;
+    }
+}
+
 // The default scoring kernels ask for four wavefronts per SIMD (at most 128
 // VGPRs): below that occupancy the phases' latency is no longer hidden.  The
 // high-ILP variants run where LDS already limits residency, and take the
@@ -866,14 +1056,17 @@ void k_score_sched(
 // workgroup takes work items (query, range of hand-out positions) from a
 // global counter, longest queries first; for each it builds that query's
 // profile, then its wavefronts pull the item's pairs from a counter in LDS,
-// at most `cap` in flight per wavefront.  Query q's scores go to
+// at most `cap` in flight per wavefront -- or, with `one` (a batch with no
+// more pairs than resident wavefronts), one pair per wavefront at a time,
+// followed by all its lanes.  Query q's scores go to
 // scores[q * stride + target], its maximum score to max_score[q * ms_stride].
 template <int kCopies, bool kCount, bool kIlp>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kIlp ? 1 : 4)))
 void k_score_batch(
     const BatchQuery* __restrict__ qs, const KMatrix* __restrict__ mats,
     const uint8_t* __restrict__ qcodes, const BatchItem* __restrict__ items, int32_t n_items,
-    uint32_t* item_ctr, int32_t prof_bytes, int32_t cap, const PairRec* __restrict__ recs,
+    uint32_t* item_ctr, int32_t prof_bytes, int32_t cap, int32_t one,
+    const PairRec* __restrict__ recs,
     const uint8_t* __restrict__ letters, const uint64_t* __restrict__ draws,
     int32_t* __restrict__ scores, int32_t* __restrict__ rounds, int64_t stride,
     int32_t* max_score, int32_t ms_stride, unsigned long long* cells_total) {
@@ -900,12 +1093,18 @@ void k_score_batch(
                                threadIdx.x, blockDim.x);
         __syncthreads();
         int32_t best_seen = INT32_MIN;
-        wave_pairs<kCopies, kCount, true, kIlp>(W, lane, cap, 0u, lds, ps, cpb, Q.bias, Q.qlen,
-                                                Q.kp, recs, item.hi, letters,
-                                                Q.table ? draws : nullptr, &s_ctr,
-                                                scores + (int64_t)q * stride,
-                                                rounds ? rounds + (int64_t)q * stride : nullptr,
-                                                cells, best_seen);
+        if (one)
+            wave_score_one<kCopies, kCount>(lane, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, recs, item.hi,
+                                            letters, &s_ctr, scores + (int64_t)q * stride,
+                                            rounds ? rounds + (int64_t)q * stride : nullptr, cells,
+                                            best_seen);
+        else
+            wave_pairs<kCopies, kCount, true, kIlp>(W, lane, cap, 0u, lds, ps, cpb, Q.bias, Q.qlen,
+                                                    Q.kp, recs, item.hi, letters,
+                                                    Q.table ? draws : nullptr, &s_ctr,
+                                                    scores + (int64_t)q * stride,
+                                                    rounds ? rounds + (int64_t)q * stride : nullptr,
+                                                    cells, best_seen);
         best_seen = wave_max_i32(best_seen);
         if (lane == 0 && best_seen != INT32_MIN) atomicMax(max_score + (int64_t)q * ms_stride, best_seen);
         __syncthreads();   // the profile and the counter are rewritten for the next item

@@ -85,29 +85,6 @@ __device__ __forceinline__ void trace_emit(TraceState& s, uint32_t o, int32_t l,
     s.len = (uint32_t)l;
 }
 
-// Maximum over the wavefront (all 64 lanes active), in registers: DPP row
-// shifts give every row's maximum in its lane 15, row broadcasts carry it
-// to lane 63.  Lanes without a source contribute 0.
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
-    uint32_t y;
-    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false); x = x > y ? x : y;
-    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false); x = x > y ? x : y;
-    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false); x = x > y ? x : y;
-    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false); x = x > y ? x : y;
-    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false); x = x > y ? x : y;
-    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false); x = x > y ? x : y;
-    return (uint32_t)__builtin_amdgcn_readlane((int)x, kLanes - 1);
-}
-
-// Largest 64-bit key over the wavefront: the largest high word, then the
-// largest low word among the lanes holding it.
-__device__ __forceinline__ uint64_t wave_max_key(uint64_t key) {
-    const uint32_t h = (uint32_t)(key >> 32), l = (uint32_t)key;
-    const uint32_t hm = wave_max_u32(h);
-    const uint32_t lm = wave_max_u32(h == hm ? l : 0u);
-    return ((uint64_t)hm << 32) | lm;
-}
-
 // Draws the next step of the alignment or, after the last one, writes the
 // alignment: inside the chop-and-consume loop only the small sequence
 // receives gaps (Section III.B.3) -- the k* skipped letters of large are
@@ -230,57 +207,6 @@ __device__ __forceinline__ void wave_trace_slots(WaveLds& W, int32_t lane, int32
     }
 }
 
-// Sum over aligned groups of P = 1 << lg lanes (lg <= 4, so that a group
-// lies within a row of 16 lanes), valid in each group's last lane: DPP row
-// shifts by 1, 2, .. P / 2 (adds only), after which lane L holds lanes
-// L - P + 1 .. L.  (A subtraction with a DPP operand is avoided: folded into
-// a reversed subtract, it returned the negated difference here.)
-__device__ __forceinline__ uint32_t group_sum(uint32_t x, int32_t lg) {
-    if (lg > 0) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
-    if (lg > 1) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
-    if (lg > 2) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
-    if (lg > 3) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
-    return x;
-}
-
-// Best placement of one step, cell-parallel (the step's placements are
-// few, or short): P = 1 << lg lanes per placement, lane l summing cells
-// [(l % P) * per, ...) of placement d0 + l / P, 64 / P placements per round.
-// Cell (k, j) pairs large letter pL + k + j with small letter pS + j; its
-// biased score is the profile byte of the target letter's row at the query
-// letter's column.  Returns the lane's best key over the rounds (0 in lanes
-// that end no group).
-__device__ __forceinline__ uint64_t step_best_cells(const uint8_t* prof, int32_t ps, int32_t bias,
-                                                    const uint8_t* __restrict__ tletters,
-                                                    bool tl, int32_t pL, int32_t pS, int32_t ss,
-                                                    int32_t nk, int32_t lane, int32_t lg) {
-    const int32_t P = 1 << lg;
-    const int32_t per = (ss + P - 1) >> lg;
-    const int32_t j0 = (lane & (P - 1)) * per;
-    const int32_t j1 = j0 + per < ss ? j0 + per : ss;
-    const bool last = (lane & (P - 1)) == P - 1;
-    const int32_t off = bias * ss;
-    uint64_t best = 0;
-    for (int32_t d0 = 0; d0 < nk; d0 += kLanes >> lg) {
-        const int32_t k = d0 + (lane >> lg);
-        uint32_t sum = 0;
-        if (k < nk) {
-            // target letter at tpos + j, query column qcol + j (profile copy 0)
-            const int32_t tpos = tl ? pL + k : pS;
-            const int32_t qcol = (tl ? pS : pL + k) + kPad;
-#pragma unroll 4
-            for (int32_t j = j0; j < j1; ++j)
-                sum += prof[__umul24((uint32_t)tletters[tpos + j], (uint32_t)ps) + (uint32_t)(qcol + j)];
-        }
-        sum = group_sum(sum, lg);
-        if (last && k < nk) {
-            const uint64_t key = shift_key((int32_t)sum - off, k);
-            best = key > best ? key : best;
-        }
-    }
-    return best;
-}
-
 // One wavefront's share of the alignments of one query: hit indices below
 // `hi`, taken one at a time from the workgroup counter `ctr`; alignment a is
 // written to alns[a], its ops to ops[ops_base + a * ops_stride ...].
@@ -330,38 +256,8 @@ __device__ __forceinline__ void wave_trace_one(int32_t lane, const uint8_t* prof
             const int32_t ss =
                 window_small(s.ns - s.pS, s.SF, trace_draw(s, kp.seed, 2u + (uint32_t)s.t), ls);
             const int32_t nk = ls - ss + 1;
-            const int32_t nblk = (nk + kBlockDiags - 1) / kBlockDiags;
-            SlotInfo si;
-            si.pL = s.pL;
-            si.pS = s.pS;
-            si.ss_tl = ss | (s.tl ? (int32_t)0x80000000 : 0);
-            si.nk = nk;
-            si.tbase = s.tbase;
-            si.key = 0;
-            // cells per placement-parallel lane (up to 16 lanes per
-            // placement) against letters per block lane (ramps included):
-            // whichever step scorer has the shorter serial loop
-            int32_t lg = 0;
-            while (lg < 4 && (nk << (lg + 1)) <= kLanes && (1 << (lg + 1)) <= ss) ++lg;
-            const int32_t cells_it = ((nk + (kLanes >> lg) - 1) / (kLanes >> lg)) * ((ss + (1 << lg) - 1) >> lg);
-            const int32_t block_it = ((nblk + kLanes - 1) / kLanes) * (ss + (s.tl ? 14 : 0));
-            uint64_t best = 0;       // below every placement's key
-            if (2 * cells_it <= block_it + 64) {
-                best = step_best_cells(prof, ps, bias, db.letters + s.tbase, s.tl, s.pL, s.pS, ss, nk,
-                                       lane, lg);
-            } else {
-                for (int32_t b0 = 0; b0 < nblk; b0 += kLanes) {
-                    const int32_t k0 = (b0 + lane) * kBlockDiags;
-                    if (k0 < nk) {
-                        BlockFetch f;
-                        fetch_block(si, k0, db.letters, f);
-                        // a lone wavefront is bound by latency: the high-ILP loop
-                        const uint64_t key = score_block<kCopies, true>(prof, ps, cpb, bias, si, k0, f);
-                        best = key > best ? key : best;
-                    }
-                }
-            }
-            best = wave_max_key(best);
+            const uint64_t best = wave_step_key<kCopies>(lane, prof, ps, cpb, bias, db.letters, s.tbase,
+                                                         s.tl, s.pL, s.pS, ss, nk);
             const int32_t kb = key_shift(best);
             s.score += key_score(best) - shift_penalty(kp, s.t, kb);
             trace_emit(s, s.tl ? kOpD : kOpI, kb, w);
