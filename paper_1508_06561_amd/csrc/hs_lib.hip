@@ -481,6 +481,20 @@ struct hs_batch {
     int32_t max_nq = 0, max_qlen = 0, k = 0, n_aln = 0;
     int64_t max_res = 0, ops_stride = 0, max_items = 0, max_titems = 0;
     char* d_mem = nullptr;
+    // pinned host mirrors, laid out as the device regions they are copied
+    // to or from: the uploads (codes .. alignment items) and the results
+    // (hits, hit counts, alignments; packing offsets after them)
+    char* h_up = nullptr;
+    char* h_down = nullptr;
+    uint8_t* h_qcodes = nullptr;
+    BatchQuery* h_qs = nullptr;
+    KMatrix* h_mats = nullptr;
+    BatchItem* h_items = nullptr;
+    BatchItem* h_titems = nullptr;
+    DevHit* h_hits = nullptr;
+    int32_t* h_nh = nullptr;
+    DevAln* h_alns = nullptr;
+    int64_t* h_pos = nullptr;
     uint8_t* d_qcodes = nullptr;
     BatchQuery* d_qs = nullptr;
     KMatrix* d_mats = nullptr;
@@ -541,6 +555,8 @@ void free_batch(hs_batch* b) {
     drop_graph(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     (void)hipFree(b->d_mem);
+    if (b->h_up) (void)hipHostFree(b->h_up);
+    if (b->h_down) (void)hipHostFree(b->h_down);
     delete b;
 }
 
@@ -616,12 +632,12 @@ int upload_items(hs_batch* b, hipStream_t st) {
         }
     if ((int64_t)titems.size() > b->max_titems) return fail(HS_EINVAL, "too many alignment items");
     b->n_titems = (int32_t)titems.size();
-    if (!items.empty())
-        HIP_TRY(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(BatchItem),
-                               hipMemcpyHostToDevice, st));
-    if (!titems.empty())
-        HIP_TRY(hipMemcpyAsync(b->d_titems, titems.data(), titems.size() * sizeof(BatchItem),
-                               hipMemcpyHostToDevice, st));
+    // both item lists in one copy from the pinned mirror (their device
+    // regions lie back to back), then wait for every upload of the batch
+    if (!items.empty()) std::memcpy(b->h_items, items.data(), items.size() * sizeof(BatchItem));
+    if (!titems.empty()) std::memcpy(b->h_titems, titems.data(), titems.size() * sizeof(BatchItem));
+    const size_t span = (size_t)((const char*)(b->h_titems + titems.size()) - (const char*)b->h_items);
+    HIP_TRY(hipMemcpyAsync(b->d_items, b->h_items, span, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     const void* fn = batch_kernel(b->copies, false, b->ilp);
     const size_t lds = batch_lds(b, b->copies);
@@ -1076,6 +1092,22 @@ int hs_batch_create(const hs_db* db, int32_t max_nq, int32_t max_qlen, int64_t m
     b->d_ops = (uint32_t*)p; p += sz[i++];
     b->d_pos = (int64_t*)p;
     b->d_packed = (uint32_t*)(p + align_up(sizeof(int64_t) * (nal + 1)));
+    const size_t up = sz[0] + sz[1] + sz[2] + sz[3] + sz[4];
+    const size_t down = sz[12] + sz[13] + sz[14] + align_up(sizeof(int64_t) * (nal + 1));
+    if (hipHostMalloc((void**)&b->h_up, up, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_down, down, hipHostMallocDefault) != hipSuccess) {
+        free_batch(b);
+        return fail(HS_ENOMEM, "pinned host allocation for the batch failed");
+    }
+    b->h_qcodes = (uint8_t*)b->h_up;
+    b->h_qs = (BatchQuery*)(b->h_up + sz[0]);
+    b->h_mats = (KMatrix*)(b->h_up + sz[0] + sz[1]);
+    b->h_items = (BatchItem*)(b->h_up + sz[0] + sz[1] + sz[2]);
+    b->h_titems = (BatchItem*)(b->h_up + sz[0] + sz[1] + sz[2] + sz[3]);
+    b->h_hits = (DevHit*)b->h_down;
+    b->h_nh = (int32_t*)(b->h_down + sz[12]);
+    b->h_alns = (DevAln*)(b->h_down + sz[12] + sz[13]);
+    b->h_pos = (int64_t*)(b->h_down + sz[12] + sz[13] + sz[14]);
     *out = b;
     return HS_OK;
 }
@@ -1107,15 +1139,17 @@ int hs_batch_set(hs_batch* b, int32_t nq, const char* residues, const int64_t* o
         int rc = check_params(params + i);
         if (rc) return rc;
     }
-    std::vector<uint8_t> codes((size_t)total);
+    // the pinned mirror is free: every earlier upload completed before its
+    // hs_batch_set (or hs_batch_schedule) returned
+    uint8_t* codes = b->h_qcodes;
     {
-        int rc = hs_encode(residues + offsets[0], total, codes.data());
+        int rc = hs_encode(residues + offsets[0], total, codes);
         if (rc) return rc;
     }
     const uint64_t seed0 = params[0].seed;
     const bool new_table = !b->table_valid || b->table_seed != seed0;
-    std::vector<BatchQuery> qs((size_t)nq);
-    std::vector<KMatrix> mats((size_t)nq);
+    BatchQuery* qs = b->h_qs;
+    KMatrix* mats = b->h_mats;
     for (int32_t q = 0; q < nq; ++q) {
         const hs_params* p = params + (n_params == 1 ? 0 : q);
         BatchQuery& Q = qs[(size_t)q];
@@ -1129,9 +1163,11 @@ int hs_batch_set(hs_batch* b, int32_t nq, const char* residues, const int64_t* o
     }
     b->nq = 0;      // not usable until the upload below completes
     drop_graph(b);
-    HIP_TRY(hipMemcpyAsync(b->d_qcodes, codes.data(), codes.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(b->d_qs, qs.data(), qs.size() * sizeof(BatchQuery), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(b->d_mats, mats.data(), mats.size() * sizeof(KMatrix), hipMemcpyHostToDevice, st));
+    // codes, queries and matrices in one copy (their device regions lie
+    // back to back, like the mirror's); the work items follow in
+    // upload_items, which waits for both
+    const size_t span = (size_t)((const char*)(mats + nq) - b->h_up);
+    HIP_TRY(hipMemcpyAsync(b->d_qcodes, b->h_up, span, hipMemcpyHostToDevice, st));
     if (new_table && b->db->n_queue > 0) {
         const int32_t nqueue = (int32_t)b->db->n_queue;
         hipLaunchKernelGGL(k_draws, dim3((2 * (int64_t)nqueue + 255) / 256), dim3(256), 0, st,
@@ -1139,14 +1175,16 @@ int hs_batch_set(hs_batch* b, int32_t nq, const char* residues, const int64_t* o
                            TopkWs{}, 0, 0);
         HIP_TRY(hipGetLastError());
     }
-    HIP_TRY(hipStreamSynchronize(st));
     b->table_valid = true;
     b->table_seed = seed0;
     b->nq = nq;
     b->qlens = qlens;
     b->cur_max_qlen = mx;
     int rc = choose_schedule(b, st);
-    if (rc) b->nq = 0;
+    if (rc) {
+        b->nq = 0;
+        (void)hipStreamSynchronize(st);     // the mirror may be rewritten after return
+    }
     return rc;
 }
 
@@ -1302,10 +1340,12 @@ int hs_batch_results(hs_batch* b, void* stream, hs_hit* hits, int32_t* n_hits, h
         return fail(HS_EINVAL, "NULL output pointer");
     hipStream_t st = (hipStream_t)stream;
     const int32_t nq = b->nq, k = b->k, na = b->n_aln;
-    std::vector<DevHit> h_hits((size_t)nq * k);
-    std::vector<int32_t> h_nh((size_t)nq);
-    std::vector<DevAln> h_alns((size_t)nq * std::max(na, 1));
-    std::vector<int64_t> h_pos((size_t)nq * std::max(na, 1) + 1, 0);
+    // pinned mirrors of the result regions (hits, counts and alignments lie
+    // back to back on the device, as in the mirror)
+    const DevHit* h_hits = b->h_hits;
+    const int32_t* h_nh = b->h_nh;
+    const DevAln* h_alns = b->h_alns;
+    const int64_t* h_pos = b->h_pos;
     if (na > 0) {
         hipLaunchKernelGGL(k_ops_scan, dim3(1), dim3(1024), 0, st, (const DevAln*)b->d_alns,
                            (const int32_t*)b->d_n_hits, nq, na, b->d_pos);
@@ -1314,14 +1354,12 @@ int hs_batch_results(hs_batch* b, void* stream, hs_hit* hits, int32_t* n_hits, h
                            (const int64_t*)b->d_pos, b->d_packed);
         HIP_TRY(hipGetLastError());
     }
-    HIP_TRY(hipMemcpyAsync(h_hits.data(), b->d_hits, sizeof(DevHit) * h_hits.size(), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(h_nh.data(), b->d_n_hits, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st));
-    if (na > 0) {
-        HIP_TRY(hipMemcpyAsync(h_alns.data(), b->d_alns, sizeof(DevAln) * (size_t)nq * na,
+    const size_t span = na > 0 ? (size_t)((const char*)(h_alns + (size_t)nq * na) - (const char*)h_hits)
+                               : (size_t)((const char*)(h_nh + nq) - (const char*)h_hits);
+    HIP_TRY(hipMemcpyAsync(b->h_hits, b->d_hits, span, hipMemcpyDeviceToHost, st));
+    if (na > 0)
+        HIP_TRY(hipMemcpyAsync(b->h_pos, b->d_pos, sizeof(int64_t) * ((size_t)nq * na + 1),
                                hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(h_pos.data(), b->d_pos, sizeof(int64_t) * ((size_t)nq * na + 1),
-                               hipMemcpyDeviceToHost, st));
-    }
     HIP_TRY(hipStreamSynchronize(st));
     if (na > 0) {
         const int64_t need = h_pos[(size_t)nq * na];
@@ -1334,7 +1372,7 @@ int hs_batch_results(hs_batch* b, void* stream, hs_hit* hits, int32_t* n_hits, h
     }
     for (int32_t q = 0; q < nq; ++q) {
         const int32_t nh = h_nh[(size_t)q];
-        std::memcpy(hits + (size_t)q * k, h_hits.data() + (size_t)q * k, sizeof(DevHit) * (size_t)nh);
+        std::memcpy(hits + (size_t)q * k, h_hits + (size_t)q * k, sizeof(DevHit) * (size_t)nh);
         n_hits[q] = nh;
         if (na > 0) {
             const int32_t m = std::min(na, nh);
