@@ -495,6 +495,8 @@ struct hs_batch {
     int32_t* h_nh = nullptr;
     DevAln* h_alns = nullptr;
     int64_t* h_pos = nullptr;
+    uint32_t* h_packed = nullptr;        // the first ops_prefix bytes of the packed ops
+    size_t ops_prefix = 0;
     uint8_t* d_qcodes = nullptr;
     BatchQuery* d_qs = nullptr;
     KMatrix* d_mats = nullptr;
@@ -1093,7 +1095,10 @@ int hs_batch_create(const hs_db* db, int32_t max_nq, int32_t max_qlen, int64_t m
     b->d_pos = (int64_t*)p;
     b->d_packed = (uint32_t*)(p + align_up(sizeof(int64_t) * (nal + 1)));
     const size_t up = sz[0] + sz[1] + sz[2] + sz[3] + sz[4];
-    const size_t down = sz[12] + sz[13] + sz[14] + align_up(sizeof(int64_t) * (nal + 1));
+    // the packing offsets and, right after them as on the device, up to
+    // 64 KB of packed ops: results that small come back in one copy
+    b->ops_prefix = std::min<size_t>(sizeof(uint32_t) * nal * (size_t)b->ops_stride, 64 * 1024);
+    const size_t down = sz[12] + sz[13] + sz[14] + align_up(sizeof(int64_t) * (nal + 1)) + b->ops_prefix;
     if (hipHostMalloc((void**)&b->h_up, up, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&b->h_down, down, hipHostMallocDefault) != hipSuccess) {
         free_batch(b);
@@ -1108,6 +1113,7 @@ int hs_batch_create(const hs_db* db, int32_t max_nq, int32_t max_qlen, int64_t m
     b->h_nh = (int32_t*)(b->h_down + sz[12]);
     b->h_alns = (DevAln*)(b->h_down + sz[12] + sz[13]);
     b->h_pos = (int64_t*)(b->h_down + sz[12] + sz[13] + sz[14]);
+    b->h_packed = (uint32_t*)((char*)b->h_pos + align_up(sizeof(int64_t) * (nal + 1)));
     *out = b;
     return HS_OK;
 }
@@ -1357,15 +1363,18 @@ int hs_batch_results(hs_batch* b, void* stream, hs_hit* hits, int32_t* n_hits, h
     const size_t span = na > 0 ? (size_t)((const char*)(h_alns + (size_t)nq * na) - (const char*)h_hits)
                                : (size_t)((const char*)(h_nh + nq) - (const char*)h_hits);
     HIP_TRY(hipMemcpyAsync(b->h_hits, b->d_hits, span, hipMemcpyDeviceToHost, st));
-    if (na > 0)
-        HIP_TRY(hipMemcpyAsync(b->h_pos, b->d_pos, sizeof(int64_t) * ((size_t)nq * na + 1),
+    if (na > 0)   // packing offsets and the packed ops' first ops_prefix bytes
+        HIP_TRY(hipMemcpyAsync(b->h_pos, b->d_pos,
+                               (size_t)((const char*)b->h_packed - (const char*)b->h_pos) + b->ops_prefix,
                                hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (na > 0) {
         const int64_t need = h_pos[(size_t)nq * na];
         *ops_used = need;
         if (need > ops_cap) return fail(HS_ENOSPC, "ops buffer too small");
-        if (need > 0) {
+        if (need > 0 && (size_t)need * sizeof(uint32_t) <= b->ops_prefix) {
+            std::memcpy(ops, b->h_packed, sizeof(uint32_t) * (size_t)need);
+        } else if (need > 0) {
             HIP_TRY(hipMemcpyAsync(ops, b->d_packed, sizeof(uint32_t) * need, hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
         }
