@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -260,9 +261,62 @@ int check_search_args(const hs_db* db, int32_t qlen, const hs_params* p, int32_t
     return check_params(p);
 }
 
+// Kernels' LDS limits and occupancies are functions of (device, kernel,
+// threads, LDS bytes) only; a batch asks the same questions for every query
+// set, so the answers are kept (for every thread of the process).
+struct LdsLimit {
+    int dev;
+    const void* fn;
+    size_t bytes;
+};
+struct Occupancy {
+    int dev;
+    const void* fn;
+    int threads;
+    size_t lds;
+    int per_cu;
+};
+std::mutex g_kernel_info_mu;
+std::vector<LdsLimit> g_lds_limits;
+std::vector<Occupancy> g_occupancies;
+
+int current_device() {
+    int dev = 0;
+    return hipGetDevice(&dev) == hipSuccess ? dev : -1;
+}
+
 int set_lds_limit(const void* fn, size_t bytes) {
-    if (bytes > 64 * 1024)
-        HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    if (bytes <= 64 * 1024) return HS_OK;
+    const int dev = current_device();
+    std::lock_guard<std::mutex> lock(g_kernel_info_mu);
+    for (const LdsLimit& l : g_lds_limits)
+        if (l.dev == dev && l.fn == fn && l.bytes >= bytes) return HS_OK;
+    HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    for (LdsLimit& l : g_lds_limits)
+        if (l.dev == dev && l.fn == fn) {
+            l.bytes = bytes;
+            return HS_OK;
+        }
+    g_lds_limits.push_back(LdsLimit{dev, fn, bytes});
+    return HS_OK;
+}
+
+// Workgroups of fn resident per compute unit (the LDS limit already set).
+int occupancy(const void* fn, int threads, size_t lds, int* per_cu) {
+    const int dev = current_device();
+    {
+        std::lock_guard<std::mutex> lock(g_kernel_info_mu);
+        for (const Occupancy& o : g_occupancies)
+            if (o.dev == dev && o.fn == fn && o.threads == threads && o.lds == lds) {
+                *per_cu = o.per_cu;
+                return HS_OK;
+            }
+    }
+    int v = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, fn, threads, lds));
+    std::lock_guard<std::mutex> lock(g_kernel_info_mu);
+    g_occupancies.push_back(Occupancy{dev, fn, threads, lds, v});
+    *per_cu = v;
     return HS_OK;
 }
 
@@ -323,7 +377,7 @@ int resident_wgs(const void* fn, int threads, size_t lds, int* per_cu) {
     *per_cu = 0;
     int rc = set_lds_limit(fn, lds);
     if (rc) return rc;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, threads, lds));
+    if (int rc_o = occupancy(fn, threads, lds, per_cu)) return rc_o;
     return HS_OK;
 }
 
@@ -350,7 +404,7 @@ int launch_sched(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParam
     int rc = set_lds_limit(fn, L.lds);
     if (rc) return rc;
     int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, L.lds));
+    if (int rc_o = occupancy(fn, threads, L.lds, &per_cu)) return rc_o;
     if (per_cu < 1) return fail(HS_ENOMEM, "scoring kernel does not fit on a compute unit");
     // Spread the pairs over every wavefront that can be resident: cap pairs
     // in flight per wavefront, taken cap at a time, 64 for large databases.
@@ -648,13 +702,13 @@ int upload_items(hs_batch* b, hipStream_t st) {
     if (!rc) rc = set_lds_limit(batch_kernel(b->copies, true, b->ilp), lds);
     if (rc) return rc;
     int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds));
+    if (int rc_o = occupancy(fn, threads, lds, &per_cu)) return rc_o;
     if (per_cu < 1) return fail(HS_ENOMEM, "batch scoring kernel does not fit on a compute unit");
     b->grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * device_cus(), b->n_items));
     const void* tfn = b->copies == 4 ? (const void*)k_trace_batch<4> : (const void*)k_trace_batch<1>;
     if ((rc = set_lds_limit(tfn, lds))) return rc;
     per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tfn, threads, lds));
+    if (int rc_o = occupancy(tfn, threads, lds, &per_cu)) return rc_o;
     if (per_cu < 1) return fail(HS_ENOMEM, "batch alignment kernel does not fit on a compute unit");
     b->tgrid = (int32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * device_cus(), b->n_titems));
     drop_graph(b);
@@ -679,7 +733,7 @@ int choose_schedule(hs_batch* b, hipStream_t st) {
         const size_t lds = batch_lds(b, b->copies);
         rc = set_lds_limit(fn, lds);
         if (rc) return rc;
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, b->waves * kLanes, lds));
+        if (int rc_o = occupancy(fn, b->waves * kLanes, lds, &per_cu)) return rc_o;
     }
     const int64_t wgs = (int64_t)std::max(per_cu, 1) * device_cus();
     // A batch whose items of one pair per wavefront all fit on the device at
