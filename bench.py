@@ -279,6 +279,14 @@ def bench_serving(args):
         for t in srv.poll(timeout_ms=100):
             srv.result(t)
             got += 1
+    # and queries one at a time, so that one-query batches' paths run too
+    for i, q in enumerate(w0.queries[:8]):
+        srv.submit(bytes(q), tag=(1 << 41) + i)
+        done = False
+        while not done:
+            for t in srv.poll(timeout_ms=100):
+                srv.result(t)
+                done = True
     rows = []
     for ri, rate in enumerate(args.rates):
         w = synth.config_serving(rate, duration_s=args.serve_s)

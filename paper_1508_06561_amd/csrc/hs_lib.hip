@@ -487,12 +487,17 @@ int launch_trace(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParam
                  int32_t n_aln, DevAln* d_alns, uint32_t* d_ops, int64_t ops_stride,
                  const QueryLayout& L) {
     const int32_t per_wg = L.waves;
-    const size_t lds = (size_t)trace_lds_bytes(profile_region_bytes(qlen, kCopies));
+    // a target buffer per wavefront when the LDS allows it (not beside the
+    // longest queries' profiles)
+    const int32_t pb = profile_region_bytes(qlen, kCopies);
+    const bool staged = (size_t)trace_lds_bytes(pb, L.waves) + 16 <= device_lds_limit();
+    const size_t lds = staged ? (size_t)trace_lds_bytes(pb, L.waves) : (size_t)trace_stage_offset(pb);
     int rc = set_lds_limit((const void*)k_trace_sched<kCopies>, lds);
     if (rc) return rc;
     hipLaunchKernelGGL((k_trace_sched<kCopies>), dim3((n_aln + per_wg - 1) / per_wg),
                        dim3(L.waves * kLanes), lds, st, db->view(), d_q, qlen, kp, km,
-                       matrix_bias(km), d_hits, d_n_hits, n_aln, per_wg, d_alns, d_ops, ops_stride);
+                       matrix_bias(km), d_hits, d_n_hits, n_aln, per_wg, d_alns, d_ops, ops_stride,
+                       staged ? (int32_t)sizeof(WaveLds) : 0);
     HIP_TRY(hipGetLastError());
     return HS_OK;
 }
@@ -700,6 +705,11 @@ int upload_items(hs_batch* b, hipStream_t st) {
     const int threads = b->waves * kLanes;
     int rc = set_lds_limit(fn, lds);
     if (!rc) rc = set_lds_limit(batch_kernel(b->copies, true, b->ilp), lds);
+    if (!rc && b->score_one)
+        rc = b->copies == 4 ? set_lds_limit((const void*)k_score_one<4, false>, lds) ||
+                                  set_lds_limit((const void*)k_score_one<4, true>, lds)
+                            : set_lds_limit((const void*)k_score_one<1, false>, lds) ||
+                                  set_lds_limit((const void*)k_score_one<1, true>, lds);
     if (rc) return rc;
     int per_cu = 0;
     if (int rc_o = occupancy(fn, threads, lds, &per_cu)) return rc_o;
@@ -764,12 +774,23 @@ int choose_schedule(hs_batch* b, hipStream_t st) {
 template <int kCopies, bool kCount, bool kIlp>
 void launch_batch_kernel(const hs_batch* b, hipStream_t st, uint64_t* d_cells) {
     const hs_db* db = b->db;
+    if (b->score_one) {
+        hipLaunchKernelGGL((k_score_one<kCopies, kCount>), dim3(b->grid), dim3(b->waves * kLanes),
+                           batch_lds(b, kCopies), st, (const BatchQuery*)b->d_qs,
+                           (const KMatrix*)b->d_mats, (const uint8_t*)b->d_qcodes,
+                           (const BatchItem*)b->d_items, b->n_items, b->d_ctr,
+                           (int32_t)batch_prof_bytes(b->cur_max_qlen, kCopies),
+                           (const PairRec*)db->d_recs, (const uint8_t*)db->d_letters,
+                           (const uint64_t*)b->d_draws, b->d_scores, b->d_rounds,
+                           (int64_t)db->n_targets, &b->d_st->max_score,
+                           (int32_t)(sizeof(TopkState) / sizeof(int32_t)), (unsigned long long*)d_cells);
+        return;
+    }
     hipLaunchKernelGGL((k_score_batch<kCopies, kCount, kIlp>), dim3(b->grid), dim3(b->waves * kLanes),
                        batch_lds(b, kCopies), st, (const BatchQuery*)b->d_qs,
                        (const KMatrix*)b->d_mats, (const uint8_t*)b->d_qcodes,
                        (const BatchItem*)b->d_items, b->n_items, b->d_ctr,
                        (int32_t)batch_prof_bytes(b->cur_max_qlen, kCopies), b->cap,
-                       (int32_t)b->score_one,
                        (const PairRec*)db->d_recs, (const uint8_t*)db->d_letters,
                        (const uint64_t*)b->d_draws, b->d_scores, b->d_rounds,
                        (int64_t)db->n_targets, &b->d_st->max_score,
@@ -1168,6 +1189,17 @@ int hs_batch_create(const hs_db* db, int32_t max_nq, int32_t max_qlen, int64_t m
     b->h_alns = (DevAln*)(b->h_down + sz[12] + sz[13]);
     b->h_pos = (int64_t*)(b->h_down + sz[12] + sz[13] + sz[14]);
     b->h_packed = (uint32_t*)((char*)b->h_pos + align_up(sizeof(int64_t) * (nal + 1)));
+    // resolve every kernel a search of the batch may launch now, rather than
+    // on the first search that needs it
+    const void* fns[] = {
+        (const void*)k_score_batch<4, false, false>, (const void*)k_score_batch<4, false, true>,
+        (const void*)k_score_batch<1, false, false>, (const void*)k_score_batch<1, false, true>,
+        (const void*)k_score_one<4, false>, (const void*)k_score_one<1, false>,
+        (const void*)k_trace_batch<4>, (const void*)k_trace_batch<1>};
+    for (const void* fn : fns) {
+        hipFuncAttributes attr;
+        (void)hipFuncGetAttributes(&attr, fn);
+    }
     *out = b;
     return HS_OK;
 }

@@ -864,7 +864,7 @@ __device__ __forceinline__ uint32_t group_sum(uint32_t x, int32_t lg) {
 // letter's column.  Returns the lane's best key over the rounds (0 in lanes
 // that end no group).
 __device__ __forceinline__ uint64_t step_best_cells(const uint8_t* prof, int32_t ps, int32_t bias,
-                                                    const uint8_t* __restrict__ tletters,
+                                                    const uint8_t* tletters,
                                                     bool tl, int32_t pL, int32_t pS, int32_t ss,
                                                     int32_t nk, int32_t lane, int32_t lg) {
     const int32_t P = 1 << lg;
@@ -903,7 +903,7 @@ __device__ __forceinline__ uint64_t step_best_cells(const uint8_t* prof, int32_t
 template <int kCopies>
 __device__ __forceinline__ uint64_t wave_step_key(int32_t lane, const uint8_t* prof, int32_t ps,
                                                   int32_t cpb, int32_t bias,
-                                                  const uint8_t* __restrict__ letters,
+                                                  const uint8_t* letters,
                                                   int64_t tbase, bool tl, int32_t pL, int32_t pS,
                                                   int32_t ss, int32_t nk) {
     const int32_t nblk = (nk + kBlockDiags - 1) / kBlockDiags;
@@ -933,6 +933,41 @@ __device__ __forceinline__ uint64_t wave_step_key(int32_t lane, const uint8_t* p
         }
     }
     return wave_max_key(best);
+}
+
+// Copies a target's tlen letters from memory into the wavefront's LDS
+// buffer `stage` (all 64 lanes, reading exactly the target's letters) and
+// pads them with the zero-row code up to kLetterPad readable bytes past the
+// end, as the database is; returns false, copying nothing, when they do not
+// fit in stage_bytes.  The copy is complete when it returns true.  A lone
+// wavefront then reads its letters from LDS instead of waiting on memory
+// at every step.
+__device__ __forceinline__ bool stage_target(int32_t lane, const uint8_t* __restrict__ src,
+                                             int32_t tlen, uint8_t* stage, int32_t stage_bytes) {
+    const int32_t nbytes = (tlen + kLetterPad + 15) & ~15;
+    if (stage == nullptr || nbytes > stage_bytes) return false;
+    for (int32_t i = lane * 16; i < nbytes; i += kLanes * 16) {
+        uint4 v;
+        if (i + 16 <= tlen) {
+            v = load16(src + i);
+        } else {
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                w[q] = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int32_t j = i + 4 * q + b;
+                    w[q] |= (j < tlen ? (uint32_t)src[j] : (uint32_t)kZeroRow) << (8 * b);
+                }
+            }
+            v = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        *(uint4*)(stage + i) = v;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    wave_sync();
+    return true;
 }
 
 // random() draws of one (target, round), computed one Philox block at a
@@ -966,7 +1001,8 @@ __device__ __forceinline__ void wave_score_one(int32_t lane, const uint8_t* prof
                                                uint32_t hi, const uint8_t* __restrict__ letters,
                                                uint32_t* ctr, int32_t* __restrict__ scores,
                                                int32_t* __restrict__ rounds, uint64_t& cells,
-                                               int32_t& best_seen) {
+                                               int32_t& best_seen, uint8_t* stage,
+                                               int32_t stage_bytes) {
     const bool w = lane == 0;     // the lane that stores (and counts)
     for (;;) {
         uint32_t qi = 0;
@@ -977,6 +1013,10 @@ __device__ __forceinline__ void wave_score_one(int32_t lane, const uint8_t* prof
         if (r.id < 0) continue;
         const bool tl = r.len >= qlen;
         const int32_t nl = tl ? r.len : qlen, ns = tl ? qlen : r.len;
+        // the target's letters from LDS when they fit in the stage
+        const bool staged = stage_target(lane, letters + r.offset, r.len, stage, stage_bytes);
+        const uint8_t* base = staged ? (const uint8_t*)stage : letters;
+        const int64_t tbase = staged ? 0 : r.offset;
         int32_t best = INT32_MIN, best_round = 0;
         for (int32_t round = 0; round < kp.rounds; ++round) {
             DrawCache dc;
@@ -989,7 +1029,7 @@ __device__ __forceinline__ void wave_score_one(int32_t lane, const uint8_t* prof
                 const int32_t ss = window_small(ns - pS, SF, cached_draw(dc, kp.seed, r.id, round, 2u + (uint32_t)t), ls);
                 const int32_t nk = ls - ss + 1;
                 if (kCount && w) cells += (uint64_t)nk * (uint64_t)ss;
-                const uint64_t key = wave_step_key<kCopies>(lane, prof, ps, cpb, bias, letters, r.offset,
+                const uint64_t key = wave_step_key<kCopies>(lane, prof, ps, cpb, bias, base, tbase,
                                                             tl, pL, pS, ss, nk);
                 const int32_t kb = key_shift(key);
                 score += key_score(key) - shift_penalty(kp, t, kb);
@@ -1056,17 +1096,14 @@ void k_score_sched(
 // workgroup takes work items (query, range of hand-out positions) from a
 // global counter, longest queries first; for each it builds that query's
 // profile, then its wavefronts pull the item's pairs from a counter in LDS,
-// at most `cap` in flight per wavefront -- or, with `one` (a batch with no
-// more pairs than resident wavefronts), one pair per wavefront at a time,
-// followed by all its lanes.  Query q's scores go to
+// at most `cap` in flight per wavefront.  Query q's scores go to
 // scores[q * stride + target], its maximum score to max_score[q * ms_stride].
 template <int kCopies, bool kCount, bool kIlp>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kIlp ? 1 : 4)))
 void k_score_batch(
     const BatchQuery* __restrict__ qs, const KMatrix* __restrict__ mats,
     const uint8_t* __restrict__ qcodes, const BatchItem* __restrict__ items, int32_t n_items,
-    uint32_t* item_ctr, int32_t prof_bytes, int32_t cap, int32_t one,
-    const PairRec* __restrict__ recs,
+    uint32_t* item_ctr, int32_t prof_bytes, int32_t cap, const PairRec* __restrict__ recs,
     const uint8_t* __restrict__ letters, const uint64_t* __restrict__ draws,
     int32_t* __restrict__ scores, int32_t* __restrict__ rounds, int64_t stride,
     int32_t* max_score, int32_t ms_stride, unsigned long long* cells_total) {
@@ -1093,18 +1130,64 @@ void k_score_batch(
                                threadIdx.x, blockDim.x);
         __syncthreads();
         int32_t best_seen = INT32_MIN;
-        if (one)
-            wave_score_one<kCopies, kCount>(lane, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, recs, item.hi,
-                                            letters, &s_ctr, scores + (int64_t)q * stride,
-                                            rounds ? rounds + (int64_t)q * stride : nullptr, cells,
-                                            best_seen);
-        else
-            wave_pairs<kCopies, kCount, true, kIlp>(W, lane, cap, 0u, lds, ps, cpb, Q.bias, Q.qlen,
-                                                    Q.kp, recs, item.hi, letters,
-                                                    Q.table ? draws : nullptr, &s_ctr,
-                                                    scores + (int64_t)q * stride,
-                                                    rounds ? rounds + (int64_t)q * stride : nullptr,
-                                                    cells, best_seen);
+        wave_pairs<kCopies, kCount, true, kIlp>(W, lane, cap, 0u, lds, ps, cpb, Q.bias, Q.qlen,
+                                                Q.kp, recs, item.hi, letters,
+                                                Q.table ? draws : nullptr, &s_ctr,
+                                                scores + (int64_t)q * stride,
+                                                rounds ? rounds + (int64_t)q * stride : nullptr,
+                                                cells, best_seen);
+        best_seen = wave_max_i32(best_seen);
+        if (lane == 0 && best_seen != INT32_MIN) atomicMax(max_score + (int64_t)q * ms_stride, best_seen);
+        __syncthreads();   // the profile and the counter are rewritten for the next item
+    }
+    if (kCount) {
+        for (int o = kLanes / 2; o > 0; o >>= 1) cells += __shfl_xor(cells, o, kLanes);
+        if (lane == 0) atomicAdd(cells_total, (unsigned long long)cells);
+    }
+}
+
+// A batch with no more pairs than resident wavefronts: as k_score_batch, but
+// each wavefront takes the item's pairs one at a time and all its lanes
+// follow the pair (wave_score_one), its record serving as the pair's target
+// buffer.  A kernel of its own, so that its registers do not weigh on
+// k_score_batch.  Query q's scores go to
+// scores[q * stride + target], its maximum score to max_score[q * ms_stride].
+template <int kCopies, bool kCount>
+__global__ __launch_bounds__(kThreads) void k_score_one(
+    const BatchQuery* __restrict__ qs, const KMatrix* __restrict__ mats,
+    const uint8_t* __restrict__ qcodes, const BatchItem* __restrict__ items, int32_t n_items,
+    uint32_t* item_ctr, int32_t prof_bytes, const PairRec* __restrict__ recs,
+    const uint8_t* __restrict__ letters, const uint64_t* __restrict__ draws,
+    int32_t* __restrict__ scores, int32_t* __restrict__ rounds, int64_t stride,
+    int32_t* max_score, int32_t ms_stride, unsigned long long* cells_total) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ uint32_t s_item, s_ctr;
+    const int32_t lane = threadIdx.x & (kLanes - 1);
+    WaveLds& W = ((WaveLds*)(lds + prof_bytes))[threadIdx.x / kLanes];
+    uint64_t cells = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint32_t it = atomicAdd(item_ctr, 1u);
+            s_item = it;
+            if (it < (uint32_t)n_items) s_ctr = items[it].lo;
+        }
+        __syncthreads();
+        const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it >= (uint32_t)n_items) break;
+        const BatchItem item = items[it];
+        const int32_t q = item.q;
+        const BatchQuery Q = qs[q];
+        const int32_t ps = profile_stride(Q.qlen);
+        const int32_t cpb = profile_copy_bytes(ps);
+        build_profile<kCopies>(lds, ps, qcodes + Q.qoff, Q.qlen, mats[q].m, Q.bias, lds + prof_bytes,
+                               threadIdx.x, blockDim.x);
+        __syncthreads();
+        int32_t best_seen = INT32_MIN;
+        // the wavefront's record is unused here: it stages the targets
+        wave_score_one<kCopies, kCount>(lane, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, recs, item.hi,
+                                        letters, &s_ctr, scores + (int64_t)q * stride,
+                                        rounds ? rounds + (int64_t)q * stride : nullptr, cells,
+                                        best_seen, (uint8_t*)&W, (int32_t)sizeof(WaveLds));
         best_seen = wave_max_i32(best_seen);
         if (lane == 0 && best_seen != INT32_MIN) atomicMax(max_score + (int64_t)q * ms_stride, best_seen);
         __syncthreads();   // the profile and the counter are rewritten for the next item

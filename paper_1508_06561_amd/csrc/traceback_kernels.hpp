@@ -225,7 +225,7 @@ __device__ __forceinline__ void wave_trace_one(int32_t lane, const uint8_t* prof
                                            const DevHit* __restrict__ hits, uint32_t hi,
                                            uint32_t* ctr, DevAln* __restrict__ alns,
                                            uint32_t* __restrict__ ops, int64_t ops_base,
-                                           int64_t ops_stride) {
+                                           int64_t ops_stride, uint8_t* stage, int32_t stage_bytes) {
     const bool w = lane == 0;     // the lane that stores
     for (;;) {
         uint32_t a = 0;
@@ -242,6 +242,10 @@ __device__ __forceinline__ void wave_trace_one(int32_t lane, const uint8_t* prof
         s.nl = s.tl ? tlen : qlen;
         s.ns = s.tl ? qlen : tlen;
         s.tbase = db.offsets[id];
+        // the target's letters from LDS when they fit in the stage
+        const bool staged = stage_target(lane, db.letters + s.tbase, tlen, stage, stage_bytes);
+        const uint8_t* base = staged ? (const uint8_t*)stage : db.letters;
+        if (staged) s.tbase = 0;
         s.round = h.round;
         s.dblk = -1;
         s.LF = round_factor(kp.lfactor, kp.minfactor, trace_draw(s, kp.seed, 0));
@@ -256,7 +260,7 @@ __device__ __forceinline__ void wave_trace_one(int32_t lane, const uint8_t* prof
             const int32_t ss =
                 window_small(s.ns - s.pS, s.SF, trace_draw(s, kp.seed, 2u + (uint32_t)s.t), ls);
             const int32_t nk = ls - ss + 1;
-            const uint64_t best = wave_step_key<kCopies>(lane, prof, ps, cpb, bias, db.letters, s.tbase,
+            const uint64_t best = wave_step_key<kCopies>(lane, prof, ps, cpb, bias, base, s.tbase,
                                                          s.tl, s.pL, s.pS, ss, nk);
             const int32_t kb = key_shift(best);
             s.score += key_score(best) - shift_penalty(kp, s.t, kb);
@@ -284,20 +288,25 @@ __device__ __forceinline__ void wave_trace_one(int32_t lane, const uint8_t* prof
     }
 }
 
-// LDS of a replay workgroup: the profile region, then the substitution rows
-// staged by build_profile.
-__host__ __device__ inline int32_t trace_lds_bytes(int32_t prof_bytes) {
+// LDS of a one-query replay workgroup of `waves` wavefronts: the profile
+// region, the substitution rows staged by build_profile, then (when it fits)
+// one target buffer of a wavefront record's size per wavefront.
+__host__ __device__ inline int32_t trace_stage_offset(int32_t prof_bytes) {
     return prof_bytes + ((kProfRows * kNsym + 15) & ~15);
+}
+__host__ __device__ inline int32_t trace_lds_bytes(int32_t prof_bytes, int32_t waves) {
+    return trace_stage_offset(prof_bytes) + waves * (int32_t)sizeof(WaveLds);
 }
 
 // Alignments of one query: workgroup g recovers hits [g * per_wg, (g + 1) *
-// per_wg) below min(n_aln, n_hits), one per wavefront at a time.
+// per_wg) below min(n_aln, n_hits), one per wavefront at a time; with
+// stage_bytes > 0 each wavefront has a target buffer of that size.
 template <int kCopies>
 __global__ __launch_bounds__(kThreads) void k_trace_sched(
     DbView db, const uint8_t* __restrict__ qcodes, int32_t qlen, KParams kp, KMatrix km,
     int32_t bias, const DevHit* __restrict__ hits, const int32_t* __restrict__ n_hits,
     int32_t n_aln, int32_t per_wg, DevAln* __restrict__ alns, uint32_t* __restrict__ ops,
-    int64_t ops_stride) {
+    int64_t ops_stride, int32_t stage_bytes) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t s_ctr;
     const int32_t nh = *n_hits < n_aln ? *n_hits : n_aln;
@@ -310,8 +319,11 @@ __global__ __launch_bounds__(kThreads) void k_trace_sched(
                            threadIdx.x, blockDim.x);
     if (threadIdx.x == 0) s_ctr = (uint32_t)lo;
     __syncthreads();
+    uint8_t* stage = stage_bytes > 0 ? lds + trace_stage_offset(profile_region_bytes(qlen, kCopies)) +
+                                           (threadIdx.x / kLanes) * stage_bytes
+                                     : nullptr;
     wave_trace_one<kCopies>(threadIdx.x & (kLanes - 1), lds, ps, cpb, bias, qlen, kp, db, hits,
-                        (uint32_t)hi, &s_ctr, alns, ops, 0, ops_stride);
+                            (uint32_t)hi, &s_ctr, alns, ops, 0, ops_stride, stage, stage_bytes);
 }
 
 // Alignments of a batch, persistent: a workgroup takes work items (query q,
@@ -354,9 +366,11 @@ __global__ __launch_bounds__(kThreads) void k_trace_batch(
                                    threadIdx.x, blockDim.x);
             __syncthreads();
             if (one)
+                // the wavefront's record is unused here: it stages the targets
                 wave_trace_one<kCopies>(lane, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, db,
                                         hits + (int64_t)q * k, hi, &s_ctr, alns + (int64_t)q * n_aln,
-                                        ops, (int64_t)q * n_aln * ops_stride, ops_stride);
+                                        ops, (int64_t)q * n_aln * ops_stride, ops_stride, (uint8_t*)&W,
+                                        (int32_t)sizeof(WaveLds));
             else
                 wave_trace_slots<kCopies>(W, lane, cap, lds, ps, cpb, Q.bias, Q.qlen, Q.kp, db,
                                           hits + (int64_t)q * k, hi, &s_ctr, alns + (int64_t)q * n_aln,
