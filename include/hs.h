@@ -223,6 +223,9 @@ int hs_batch_set(hs_batch* b, int32_t nq, const char* residues, const int64_t* o
  *            shared by the workgroup's wavefronts (at most 64)
  *   chunk    target positions per work item, a multiple of 64, 0 = sized
  *            so that every workgroup gets about four items
+ * With cap and chunk both 0, a batch whose pairs each get a resident
+ * wavefront is instead scored one pair per wavefront (reported as cap 1,
+ * chunk = wavefronts per workgroup).
  * Applies to the current queries at once and to every later hs_batch_set. */
 int hs_batch_schedule(hs_batch* b, int32_t copies, int32_t cap, int32_t chunk, void* stream);
 
