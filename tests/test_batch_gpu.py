@@ -262,3 +262,33 @@ def test_handle_reuse_and_errors(small):
             same_result(got[i], O.search(codes, off, O.encode(q), to_oparams(P), k=10, n_aln=4),
                         f"set {rep}, query {i}")
     b.close()
+
+
+def test_one_pair_paths_equal_oracle_and_slots(small):
+    """A one-query batch on a small database is scored one pair per
+    wavefront (k_score_one) and aligned one hit per wavefront; with every
+    parameter family it equals the oracle, and a fixed schedule (the slot
+    paths) gives the same results."""
+    q0, res, off, codes, db = small
+    rng = np.random.default_rng(21)
+    P = H().Params
+    m = O.blosum62().astype(np.int16)
+    m2 = np.clip(m + rng.integers(-1, 2, size=m.shape), -4, 11).astype(np.int8)
+    m2 = ((m2.astype(np.int16) + m2.T) // 2).astype(np.int8)
+    plist = [P(), P(rounds=3, seed=9), P(pgp=2, gop=3, gep=1), P(matrix=m2), P(min_score=30)]
+    queries = [bytes(q0), bytes(synth.mutate(rng, q0, 0.5)), bytes(synth.random_protein(rng, 250))]
+    for qi, q in enumerate(queries):
+        for p in plist:
+            b = H().Batch(db, 1, 400, 400, k=30, n_aln=15)
+            b.set([q], p)
+            sched = b.get_schedule()
+            assert sched["cap"] == 1, f"one-pair mode not chosen: {sched}"
+            b.run()
+            got = b.results()[0]
+            ref = O.search(codes, off, O.encode(q), to_oparams(p), k=30, n_aln=15,
+                           min_score=p.min_score, matrix=p.matrix)
+            same_result(got, ref, f"query {qi} with {p}")
+            b.schedule(4, 64, 64)
+            b.run()
+            same_results(b.results()[0], got, f"query {qi} with {p}, slot paths")
+            b.close()
