@@ -705,11 +705,11 @@ int upload_items(hs_batch* b, hipStream_t st) {
     const int threads = b->waves * kLanes;
     int rc = set_lds_limit(fn, lds);
     if (!rc) rc = set_lds_limit(batch_kernel(b->copies, true, b->ilp), lds);
-    if (!rc && b->score_one)
-        rc = b->copies == 4 ? set_lds_limit((const void*)k_score_one<4, false>, lds) ||
-                                  set_lds_limit((const void*)k_score_one<4, true>, lds)
-                            : set_lds_limit((const void*)k_score_one<1, false>, lds) ||
-                                  set_lds_limit((const void*)k_score_one<1, true>, lds);
+    if (!rc && b->score_one) {
+        const bool four = b->copies == 4;
+        rc = set_lds_limit(four ? (const void*)k_score_one<4, false> : (const void*)k_score_one<1, false>, lds);
+        if (!rc) rc = set_lds_limit(four ? (const void*)k_score_one<4, true> : (const void*)k_score_one<1, true>, lds);
+    }
     if (rc) return rc;
     int per_cu = 0;
     if (int rc_o = occupancy(fn, threads, lds, &per_cu)) return rc_o;
