@@ -106,6 +106,7 @@ struct hs_db {
     int32_t* d_order = nullptr;     // longest first
     PairRec* d_recs = nullptr;      // (index, length, offset) in hand-out order
     int64_t n_queue = 0;            // hand-out positions (targets plus padding)
+    int32_t median_len = 0;         // median target length (0 for an empty database)
     int64_t device_bytes = 0;
 
     DbView view() const {
@@ -394,6 +395,10 @@ int prefer_ilp(const void* fn_default, const void* fn_ilp, int threads, size_t l
     return HS_OK;
 }
 
+// Target letters a wavefront of the one-query search keeps in flight: 64
+// pairs of targets up to 384 letters, one pair of a target over 12,288.
+constexpr int64_t kLettersInFlight = 64 * 384;
+
 template <int kCopies, bool kCount, bool kIlp>
 int launch_sched(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParams& kp,
                  const KMatrix& km, int32_t bias, hipStream_t st, const QueryWs& w,
@@ -407,9 +412,17 @@ int launch_sched(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParam
     if (int rc_o = occupancy(fn, threads, L.lds, &per_cu)) return rc_o;
     if (per_cu < 1) return fail(HS_ENOMEM, "scoring kernel does not fit on a compute unit");
     // Spread the pairs over every wavefront that can be resident: cap pairs
-    // in flight per wavefront, taken cap at a time, 64 for large databases.
+    // in flight per wavefront, taken cap at a time.  The cap is the smallest
+    // of 64, the share that puts every pair in flight at once, and the share
+    // that keeps about kLettersInFlight target letters (median length) in
+    // flight: one pair of a long target already fills the wavefront's lanes
+    // with blocks, and pairs left in the queue balance the wavefronts' loads
+    // (32 queries of 2,000-5,000 letters against targets of median 17,000
+    // letters ran 1.9 times faster at cap 1 than with every pair in flight).
     const int64_t slots = (int64_t)per_cu * device_cus() * L.waves;
-    const int32_t cap = (int32_t)std::min<int64_t>(kLanes, std::max<int64_t>(1, (db->n_targets + slots - 1) / slots));
+    const int64_t by_len = std::max<int64_t>(1, kLettersInFlight / std::max<int32_t>(db->median_len, 1));
+    const int32_t cap = (int32_t)std::min<int64_t>(
+        std::min<int64_t>(kLanes, by_len), std::max<int64_t>(1, (db->n_targets + slots - 1) / slots));
     const int64_t want = (db->n_targets + (int64_t)cap * L.waves - 1) / ((int64_t)cap * L.waves);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * device_cus(), want));
     hipLaunchKernelGGL((k_score_sched<kCopies, kCount, kIlp>), dim3(grid), dim3(threads), L.lds, st,
@@ -915,6 +928,7 @@ int hs_db_load(const char* residues, const int64_t* offsets, int64_t n_targets, 
     hs_db* db = new hs_db();
     db->n_targets = n_targets;
     db->n_residues = total;
+    db->median_len = n_targets ? len[(size_t)order[(size_t)(n_targets / 2)]] : 0;
     int rc = HS_OK;
     int32_t* d_err = nullptr;
     auto cleanup = [&](int code) {
