@@ -220,7 +220,8 @@ int hs_batch_set(hs_batch* b, int32_t nq, const char* residues, const int64_t* o
  *   copies   score-profile copies in LDS, 1 or 4 (4: aligned reads; needs
  *            more LDS), 0 = 4 whenever it fits
  *   cap      pairs in flight per wavefront, 1..64, 0 = an item's positions
- *            shared by the workgroup's wavefronts (at most 64)
+ *            shared by the workgroup's wavefronts (at most 64), and at most
+ *            24,576 letters / the database's median target length (at least 1)
  *   chunk    target positions per work item, a multiple of 64, 0 = sized
  *            so that every workgroup gets about four items
  * With cap and chunk both 0, a batch whose pairs each get a resident

@@ -779,8 +779,16 @@ int choose_schedule(hs_batch* b, hipStream_t st) {
     }
     // pairs in flight per wavefront: an item's positions shared by all the
     // workgroup's wavefronts (with 64, the first wavefront would take a
-    // small item whole and leave the others idle)
-    if (!b->fix_cap) b->cap = std::min(kLanes, std::max(1, (b->chunk + b->waves - 1) / b->waves));
+    // small item whole and leave the others idle), and no more than keep
+    // about kLettersInFlight target letters in flight (median length), as in
+    // the one-query kernel: on long targets the queue then still holds pairs
+    // that balance the wavefronts (32 queries of 2,000-5,000 letters against
+    // targets of median 17,000 letters took 169 ms at 32 pairs in flight)
+    if (!b->fix_cap) {
+        const int32_t by_len = (int32_t)std::max<int64_t>(
+            1, kLettersInFlight / std::max<int32_t>(b->db->median_len, 1));
+        b->cap = std::min(std::min(kLanes, by_len), std::max(1, (b->chunk + b->waves - 1) / b->waves));
+    }
     return upload_items(b, st);
 }
 
