@@ -182,6 +182,36 @@ int hs_score_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const h
                  uint64_t* d_cells);
 
 /* ---------------------------------------------------------------------------
+ * Smith-Waterman baseline.  The exact optimum that the paper measures its
+ * heuristic against (Sections I and IV compare the two for speed and
+ * sensitivity): Smith & Waterman (1981) local alignment with Gotoh's (1982)
+ * affine gaps, a gap run of g columns costing gop + (g - 1) * gep, the
+ * convention of Section III.B.1.  Scores only, no alignments.
+ * ------------------------------------------------------------------------- */
+
+/* Device workspace bytes hs_sw_scores_dev needs for `db`: 8 bytes per
+ * database letter (a boundary row of H and gap values per target letter,
+ * written by one pass over 16 query rows and read by the next).  Returns
+ * HS_EINVAL for a NULL db. */
+int64_t hs_sw_workspace_bytes(const hs_db* db);
+
+/* Optimal local alignment score of one query against every target of `db`,
+ * queued on `stream`:
+ *   d_qcodes, qlen   device query codes from hs_encode (each < HS_NSYM),
+ *                    1..HS_MAX_QUERY of them; the query profile lives in LDS
+ *   params           gop, gep and matrix are used (checked as for hs_search);
+ *                    the heuristic's factors, rounds and seed are ignored
+ *   d_ws, ws_bytes   device workspace, at least hs_sw_workspace_bytes(db);
+ *                    contents on entry are ignored, on return unspecified
+ *   d_scores         device int32[n_targets] in target index order; 0 when no
+ *                    positive-scoring local alignment exists
+ * Errors: HS_EINVAL (NULL pointer, qlen out of range, bad params), HS_ENOSPC
+ * (workspace too small), HS_EDEVICE (launch failed).  All buffers stay owned
+ * by the caller and must stay valid until the stream has run the launch. */
+int hs_sw_scores_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const hs_params* params,
+                     void* stream, void* d_ws, size_t ws_bytes, int32_t* d_scores);
+
+/* ---------------------------------------------------------------------------
  * Batches.  The query-against-database comparison of Section II, done for
  * many queries at once: every (query, target) pair is scored by the same
  * search-mode heuristic (Fig. 1 with Section III.B.3) and every query is

@@ -16,6 +16,7 @@
 #include "score_kernels.hpp"
 #include "topk_kernels.hpp"
 #include "traceback_kernels.hpp"
+#include "sw_kernels.hpp"
 
 using namespace hs;
 
@@ -1113,6 +1114,32 @@ int hs_score_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const h
     QueryWs w = carve(d_ws, db->n_targets, db->n_queue);
     return launch_score(db, d_qcodes, qlen, params, (hipStream_t)stream, w, d_scores, d_rounds,
                         d_cells, nullptr);
+}
+
+int64_t hs_sw_workspace_bytes(const hs_db* db) {
+    if (!db) return fail(HS_EINVAL, "db is NULL");
+    return (int64_t)align_up(sizeof(int2) * (size_t)std::max<int64_t>(db->n_residues, 1));
+}
+
+int hs_sw_scores_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const hs_params* params,
+                     void* stream, void* d_ws, size_t ws_bytes, int32_t* d_scores) {
+    if (!db) return fail(HS_EINVAL, "db is NULL");
+    if (qlen < 1 || qlen > HS_MAX_QUERY) return fail(HS_EINVAL, "qlen must lie in [1, HS_MAX_QUERY]");
+    int rc = check_params(params);
+    if (rc) return rc;
+    if (!d_qcodes || !d_scores || !d_ws) return fail(HS_EINVAL, "NULL device pointer");
+    if ((int64_t)ws_bytes < hs_sw_workspace_bytes(db)) return fail(HS_ENOSPC, "workspace too small");
+    if (db->n_targets < 1) return HS_OK;
+    const int32_t qp = sw_profile_stride(qlen);
+    const size_t lds = (size_t)kNsym * (size_t)qp;
+    const void* fn = (const void*)k_sw_scores;
+    if ((rc = set_lds_limit(fn, lds))) return rc;
+    const int64_t grid = (db->n_targets + kSwThreads - 1) / kSwThreads;
+    hipLaunchKernelGGL(k_sw_scores, dim3((unsigned)grid), dim3(kSwThreads), lds, (hipStream_t)stream,
+                       db->view(), d_qcodes, qlen, qp, kmatrix(params), params->gop, params->gep,
+                       (int2*)d_ws, d_scores);
+    HIP_TRY(hipGetLastError());
+    return HS_OK;
 }
 
 int hs_batch_create(const hs_db* db, int32_t max_nq, int32_t max_qlen, int64_t max_residues,

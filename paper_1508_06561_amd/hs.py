@@ -91,6 +91,9 @@ def lib():
         L.hs_score_dev.argtypes = [vp, vp, ctypes.c_int32, P(_CParams), vp, vp, ctypes.c_size_t,
                                    vp, vp, vp]
         i32, i64, pi32 = ctypes.c_int32, ctypes.c_int64, P(ctypes.c_int32)
+        L.hs_sw_workspace_bytes.argtypes = [vp]
+        L.hs_sw_workspace_bytes.restype = ctypes.c_int64
+        L.hs_sw_scores_dev.argtypes = [vp, vp, ctypes.c_int32, P(_CParams), vp, vp, ctypes.c_size_t, vp]
         L.hs_batch_create.argtypes = [vp, i32, i32, i64, i32, i32, P(vp)]
         L.hs_batch_free.argtypes = [vp]
         L.hs_batch_set.argtypes = [vp, i32, vp, P(ctypes.c_int64), P(_CParams), i32, vp]
@@ -260,6 +263,30 @@ class Database:
                                   d_ws.numel() * d_ws.element_size(), d_scores.data_ptr(),
                                   d_rounds.data_ptr() if d_rounds is not None else None,
                                   d_cells.data_ptr() if d_cells is not None else None))
+
+    def sw_workspace_bytes(self):
+        """Device workspace bytes of sw_scores_dev (hs_sw_workspace_bytes)."""
+        n = lib().hs_sw_workspace_bytes(self._h)
+        if n < 0:
+            _check(int(n))
+        return int(n)
+
+    def sw_scores_dev(self, d_qcodes, qlen, params, d_ws, d_scores, stream=None):
+        """Queues hs_sw_scores_dev: every target's Smith-Waterman-Gotoh local
+        score into d_scores (int32 torch CUDA tensor of n_targets)."""
+        p = params.c()
+        _check(lib().hs_sw_scores_dev(self._h, d_qcodes.data_ptr(), qlen, ctypes.byref(p),
+                                      _stream(stream), d_ws.data_ptr(),
+                                      d_ws.numel() * d_ws.element_size(), d_scores.data_ptr()))
+
+    def sw_scores(self, query, params=None):
+        """Every target's Smith-Waterman-Gotoh local score (host int32 array)."""
+        import torch
+        codes = torch.from_numpy(encode(query)).cuda()
+        out = torch.empty(max(self.n_targets, 1), dtype=torch.int32, device="cuda")
+        ws = torch.empty(self.sw_workspace_bytes(), dtype=torch.uint8, device="cuda")
+        self.sw_scores_dev(codes, len(codes), params or Params(), ws, out)
+        return out.cpu().numpy()[:self.n_targets]
 
     def scores(self, query, params=None):
         """(scores, rounds, cells): every target's pair score and winning
