@@ -8,7 +8,11 @@ a time; `--workload long` does the same for 32 queries of U[2000, 5000]
 residues against that database plus 5,064 targets of 10,000-35,000 residues.
 `--workload serving` replays Poisson query arrivals at 50, 200 and 500 queries/s
 (lengths log-normal, median 250) into the serving loop over the 2,020-target
-database and reports p50/p99 latency and the sustained rate.
+database and reports p50/p99 latency and the sustained rate.  `--workload sw`
+times the Smith-Waterman-Gotoh scores of the full workload's query against
+every target beside the heuristic's search of the same query (its roofline
+counts 11 32-bit integer ops per cell against 256 CUs x 64 lanes x 2.4 GHz =
+39.3 TOP/s).
 
 Prints one JSON line.  `value` is query*database residues per second with the
 database and the query resident in device memory when timing starts.  The
@@ -345,6 +349,110 @@ def bench_serving(args):
     print(json.dumps(out), flush=True)
 
 
+SW_OPS_PER_CELL = 11     # Gotoh cell: 4 subtractions, 1 addition, 6 maxima (with the running best)
+SW_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit integer ops: 64 lanes per CU per clock
+
+
+def cpu_baseline_sw(w, q, budget_s):
+    """Oracle Gotoh checker (plain single-threaded C) on targets in index
+    order until about budget_s seconds have passed."""
+    import numpy as np
+    import oracle as O
+    codes = O.encode_db(w.residues, w.offsets)
+    qc = O.encode(bytes(q))
+    res = 0
+    n = 0
+    t = time.perf_counter()
+    while n < w.n_targets and time.perf_counter() - t < budget_s:
+        O.sw_score(qc, codes[w.offsets[n]:w.offsets[n + 1]])
+        res += int(w.offsets[n + 1] - w.offsets[n])
+        n += 1
+    dt = time.perf_counter() - t
+    return {"value": len(q) * res / dt, "unit": "query*residues/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} of {w.n_targets} targets ({res} residues), one query of "
+                      f"{len(q)}, single thread, {dt:.1f} s"}
+
+
+def bench_sw(args):
+    """Smith-Waterman-Gotoh scores of the full workload's query against every
+    target (hs_sw_scores_dev), beside the heuristic's whole search of the
+    same query: the speed and sensitivity comparison of Sections I and IV."""
+    import numpy as np
+    import torch
+
+    import paper_1508_06561_amd as H
+    import synth
+
+    w = synth.config_full()
+    q = w.queries[0]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    db = H.Database(w.residues, w.offsets)
+    p = H.Params()
+    ds = H.DeviceSearch(db, len(q), w.k, w.n_aln)
+    ds.set_query(bytes(q))
+    scores = torch.empty(w.n_targets, dtype=torch.int32, device="cuda")
+    ws = torch.empty(db.sw_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        db.sw_scores_dev(ds.q, ds.qlen, p, ws, scores)
+        ds.run(p)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        db.sw_scores_dev(ds.q, ds.qlen, p, ws, scores)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    ev0.record(stream)
+    for _ in range(args.steps):
+        ds.run(p)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    h_ms = ev0.elapsed_time(ev1) / args.steps
+    res = ds.fetch()
+    log(f"sw scores: {ms:.3f} ms; heuristic search: {h_ms:.3f} ms")
+    sw = scores.cpu().numpy()
+    ids = np.arange(w.n_targets)
+    top_sw = ids[np.lexsort((ids, -sw.astype(np.int64)))][:w.k]
+    planted = set(int(x) for x in w.planted)
+    recall_sw = len(planted & set(int(x) for x in top_sw)) / len(planted)
+    recall_h = len(planted & set(int(x) for x in res.hits["target_id"])) / len(planted)
+    cells = len(q) * w.db_residues
+    achieved = cells * SW_OPS_PER_CELL / (ms * 1e-3) / 1e12
+    out = {
+        "metric": "query*DB residues/sec on 1 GPU (one query, Smith-Waterman-Gotoh scores)",
+        "value": cells / (ms * 1e-3),
+        "unit": "query*residues/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded; log-normal lengths, background residue composition)",
+        "config": {"workload": "one 300-residue query vs 500,200 targets (log-normal lengths, "
+                               "median 300, sigma 0.6, clip 10-35,000; 200 planted homologs); "
+                               "every target's optimal local score",
+                   "db_residues": w.db_residues, "params": "GOP 10, GEP 5, BLOSUM62"},
+        "roofline": {"bound": "alu", "kernel": "k_sw_scores", "achieved": achieved,
+                     "peak": SW_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / SW_PEAK_TOPS,
+                     "traffic": None, "ops_per_cell": SW_OPS_PER_CELL, "cells_per_launch": cells,
+                     "kernel_ms": ms, "cells_per_s": cells / (ms * 1e-3)},
+        "heuristic": {"ms_per_search": h_ms, "sw_over_heuristic_time": ms / h_ms},
+        "homolog_recall": {"k": w.k, "planted": len(planted), "sw": recall_sw,
+                           "heuristic": recall_h,
+                           "note": "planted homologs ranked in the top k (information only)"},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_sw(w, q, args.cpu_budget)
+        log(f"cpu baseline: {out['cpu_baseline']}")
+    db.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -352,7 +460,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["full", "batched", "long", "serving"], default="full")
+    ap.add_argument("--workload", choices=["full", "batched", "long", "serving", "sw"], default="full")
     ap.add_argument("--rates", type=float, nargs="+", default=[50, 200, 500])
     ap.add_argument("--schedule", type=int, nargs=3, metavar=("COPIES", "CAP", "CHUNK"),
                     help="batch workloads: fixed schedule instead of the autotuner")
@@ -379,6 +487,8 @@ def main():
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "sw":
+        return bench_sw(args)
 
     import numpy as np
     import torch

@@ -108,6 +108,7 @@ struct hs_db {
     PairRec* d_recs = nullptr;      // (index, length, offset) in hand-out order
     int64_t n_queue = 0;            // hand-out positions (targets plus padding)
     int32_t median_len = 0;         // median target length (0 for an empty database)
+    std::vector<int32_t> lens_desc; // target lengths, longest first (host copy)
     int64_t device_bytes = 0;
 
     DbView view() const {
@@ -938,6 +939,8 @@ int hs_db_load(const char* residues, const int64_t* offsets, int64_t n_targets, 
     db->n_targets = n_targets;
     db->n_residues = total;
     db->median_len = n_targets ? len[(size_t)order[(size_t)(n_targets / 2)]] : 0;
+    db->lens_desc.resize((size_t)n_targets);
+    for (int64_t i = 0; i < n_targets; ++i) db->lens_desc[(size_t)i] = len[(size_t)order[(size_t)i]];
     int rc = HS_OK;
     int32_t* d_err = nullptr;
     auto cleanup = [&](int code) {
@@ -1134,10 +1137,20 @@ int hs_sw_scores_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, con
     const size_t lds = (size_t)kNsym * (size_t)qp;
     const void* fn = (const void*)k_sw_scores;
     if ((rc = set_lds_limit(fn, lds))) return rc;
-    const int64_t grid = (db->n_targets + kSwThreads - 1) / kSwThreads;
+    // Targets whose one-lane sweep (a step per letter and 16-row pass) would
+    // outlast the wavefront sweep of the longest target (a step per letter,
+    // plus 63, and 1,024-row pass) take a wavefront each.
+    const int64_t lane_passes = (qlen + kSwRows - 1) / kSwRows;
+    const int64_t wave_passes = (qlen + kSwWaveRows - 1) / kSwWaveRows;
+    const int64_t thr = wave_passes * ((int64_t)db->lens_desc[0] + kLanes - 1) / lane_passes;
+    const int32_t n_long = (int32_t)(std::partition_point(db->lens_desc.begin(), db->lens_desc.end(),
+                                                          [&](int32_t L) { return L > thr; }) -
+                                     db->lens_desc.begin());
+    const int64_t wave_blocks = (n_long + kSwThreads / kLanes - 1) / (kSwThreads / kLanes);
+    const int64_t grid = wave_blocks + (db->n_targets - n_long + kSwThreads - 1) / kSwThreads;
     hipLaunchKernelGGL(k_sw_scores, dim3((unsigned)grid), dim3(kSwThreads), lds, (hipStream_t)stream,
-                       db->view(), d_qcodes, qlen, qp, kmatrix(params), params->gop, params->gep,
-                       (int2*)d_ws, d_scores);
+                       db->view(), n_long, d_qcodes, qlen, qp, kmatrix(params), params->gop,
+                       params->gep, (int2*)d_ws, d_scores);
     HIP_TRY(hipGetLastError());
     return HS_OK;
 }

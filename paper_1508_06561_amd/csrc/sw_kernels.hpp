@@ -23,6 +23,7 @@ namespace hs {
 
 constexpr int kSwRows = 16;          // query rows per pass: one 16-byte profile read
 constexpr int kSwThreads = 256;
+constexpr int kSwWaveRows = kSwRows * kLanes;    // query rows per pass of the wavefront role
 constexpr int32_t kSwNeg = -(1 << 29);   // minus infinity; one subtraction stays in range
 
 // Query profile bytes in LDS for a query of qlen letters.
@@ -34,27 +35,38 @@ __device__ __forceinline__ int32_t sw_byte(uint32_t w, int k) {
     return (int32_t)(int8_t)(uint8_t)(w >> (8 * k));
 }
 
-// scores[t] = optimal local score of the query against target t (index
-// order).  col: workspace of one int2 per database letter (index as the
-// letters).  LDS: kNsym * qp bytes.
-__global__ __launch_bounds__(kSwThreads) void k_sw_scores(
-    DbView db, const uint8_t* __restrict__ q, int32_t qlen, int32_t qp, KMatrix km, int32_t gop,
-    int32_t gep, int2* __restrict__ col, int32_t* __restrict__ scores) {
-    extern __shared__ __align__(16) uint8_t sw_prof[];
-    for (int32_t w = threadIdx.x; w < kNsym * qp; w += blockDim.x) {
-        const int32_t c = w / qp, i = w - c * qp;
-        // codes outside the alphabet read row kNsym - 1 (never outside the matrix)
-        const int32_t qc = i < qlen ? min((int32_t)q[i], kNsym - 1) : 0;
-        sw_prof[w] = i < qlen ? (uint8_t)km.m[qc * kNsym + c] : (uint8_t)0;
+// One column of kSwRows rows: sv holds the rows' substitution scores, H and
+// Fr the rows' values at the previous column, top_prev H[i0-1][j-1]; up and
+// v enter as H[i0-1][j] and the vertical gap into row i0 and leave as the
+// bottom row's.  Rows r >= valid are outside the query and not counted in
+// best.
+__device__ __forceinline__ void sw_column(const uint4& sv, int32_t (&H)[kSwRows],
+                                          int32_t (&Fr)[kSwRows], int32_t& top_prev, int32_t& up,
+                                          int32_t& v, int32_t& best, int32_t valid, int32_t gop,
+                                          int32_t gep) {
+    int32_t diag = top_prev;
+    top_prev = up;
+#pragma unroll
+    for (int r = 0; r < kSwRows; ++r) {
+        const uint32_t word = r < 4 ? sv.x : r < 8 ? sv.y : r < 12 ? sv.z : sv.w;
+        const int32_t s = sw_byte(word, r & 3);
+        v = max(up - gop, v - gep);                        // gap in the target, down column j
+        const int32_t f = max(H[r] - gop, Fr[r] - gep);    // gap in the query, along row i
+        Fr[r] = f;
+        const int32_t h = max(max(diag + s, v), max(f, 0));
+        diag = H[r];
+        H[r] = h;
+        up = h;
+        if (r < valid) best = max(best, h);
     }
-    __syncthreads();
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= db.n) return;
-    const int32_t tgt = db.order[g];
-    const int32_t tlen = db.lens[tgt];
-    const int64_t off = db.offsets[tgt];
-    const uint8_t* __restrict__ t = db.letters + off;
-    int2* __restrict__ cb = col + off;
+}
+
+// Lane role: the whole target on one lane, in passes of kSwRows query rows;
+// the bottom row of a pass goes to cb (one int2 per target letter) for the
+// next.  Returns the best cell.
+__device__ __forceinline__ int32_t sw_lane(const uint8_t* __restrict__ t, int32_t tlen,
+                                           int2* __restrict__ cb, const uint8_t* prof,
+                                           int32_t qlen, int32_t qp, int32_t gop, int32_t gep) {
     int32_t best = 0;
     for (int32_t i0 = 0; i0 < qlen; i0 += kSwRows) {
         const bool first = i0 == 0;
@@ -77,26 +89,106 @@ __global__ __launch_bounds__(kSwThreads) void k_sw_scores(
                 c_next = t[j + 1];
                 if (!first) b_next = cb[j + 1];
             }
-            const uint4 sv = *(const uint4*)(sw_prof + c * qp + i0);
-            int32_t diag = top_prev;
-            top_prev = up;
-#pragma unroll
-            for (int r = 0; r < kSwRows; ++r) {
-                const uint32_t word = r < 4 ? sv.x : r < 8 ? sv.y : r < 12 ? sv.z : sv.w;
-                const int32_t s = sw_byte(word, r & 3);
-                v = max(up - gop, v - gep);                 // gap in the target, down column j
-                const int32_t f = max(H[r] - gop, Fr[r] - gep);   // gap in the query, along row i
-                Fr[r] = f;
-                const int32_t h = max(max(diag + s, v), max(f, 0));
-                diag = H[r];
-                H[r] = h;
-                up = h;
-                if (r < valid) best = max(best, h);
-            }
+            const uint4 sv = *(const uint4*)(prof + c * qp + i0);
+            sw_column(sv, H, Fr, top_prev, up, v, best, valid, gop, gep);
             if (!last) cb[j] = make_int2(up, v);
         }
     }
-    scores[tgt] = best;
+    return best;
+}
+
+// Wavefront role: the whole target on one wavefront, in passes of
+// kSwWaveRows query rows.  Lane l holds rows [p0 + 16 l, p0 + 16 l + 16) and
+// works one column behind lane l - 1, whose bottom row it takes by a one-lane
+// shift at each step, so that a pass takes tlen + 63 steps.  Lane 0 reads the
+// previous pass's bottom row from cb, lane 63 writes its own there.  Returns
+// the best cell of the whole matrix on every lane.
+__device__ __forceinline__ int32_t sw_wave(int32_t lane, const uint8_t* __restrict__ t,
+                                           int32_t tlen, int2* __restrict__ cb,
+                                           const uint8_t* prof, int32_t qlen, int32_t qp,
+                                           int32_t gop, int32_t gep) {
+    int32_t best = 0;
+    for (int32_t p0 = 0; p0 < qlen; p0 += kSwWaveRows) {
+        const bool first = p0 == 0;
+        const bool last = p0 + kSwWaveRows >= qlen;
+        const int32_t i0 = p0 + lane * kSwRows;
+        const int32_t valid = qlen - i0;          // rows r < valid are query rows
+        const bool has_rows = valid > 0;          // lanes past the query skip the work
+        const int32_t i0c = has_rows ? i0 : 0;
+        int32_t H[kSwRows], Fr[kSwRows];
+#pragma unroll
+        for (int r = 0; r < kSwRows; ++r) {
+            H[r] = 0;
+            Fr[r] = kSwNeg;
+        }
+        int32_t top_prev = 0;
+        int32_t out_h = 0, out_v = kSwNeg;        // this lane's bottom row at its last column
+        int32_t c_next = lane == 0 ? t[0] : 0;    // step 0 works on column -lane
+        int2 b_next = (lane == 0 && !first) ? cb[0] : make_int2(0, kSwNeg);
+        const int32_t steps = tlen + kLanes - 1;
+        for (int32_t st = 0; st < steps; ++st) {
+            const int32_t j = st - lane;
+            int32_t up = __shfl_up(out_h, 1);
+            int32_t v = __shfl_up(out_v, 1);
+            if (lane == 0) {
+                up = b_next.x;
+                v = b_next.y;
+            }
+            const int32_t c = c_next;
+            const int32_t jn = j + 1;
+            if (jn >= 0 && jn < tlen) {
+                c_next = t[jn];
+                if (lane == 0 && !first) b_next = cb[jn];
+            }
+            if (j >= 0 && j < tlen && has_rows) {
+                const uint4 sv = *(const uint4*)(prof + c * qp + i0c);
+                sw_column(sv, H, Fr, top_prev, up, v, best, valid, gop, gep);
+                out_h = up;
+                out_v = v;
+                if (lane == kLanes - 1 && !last) cb[j] = make_int2(up, v);
+            }
+        }
+        __threadfence_block();   // lane 63's boundary stores land before lane 0 reads them
+    }
+    for (int o = kLanes / 2; o >= 1; o >>= 1) best = max(best, __shfl_xor(best, o));
+    return best;
+}
+
+// scores[t] = optimal local score of the query against target t (index
+// order).  The n_long longest targets (order[0 .. n_long - 1]) take the
+// wavefront role, one per wavefront, in the first ceil(n_long / 4)
+// workgroups; the others take the lane role, one per lane.  col: workspace
+// of one int2 per database letter (index as the letters).  LDS: kNsym * qp
+// bytes.
+__global__ __launch_bounds__(kSwThreads) void k_sw_scores(
+    DbView db, int32_t n_long, const uint8_t* __restrict__ q, int32_t qlen, int32_t qp, KMatrix km,
+    int32_t gop, int32_t gep, int2* __restrict__ col, int32_t* __restrict__ scores) {
+    extern __shared__ __align__(16) uint8_t sw_prof[];
+    for (int32_t w = threadIdx.x; w < kNsym * qp; w += blockDim.x) {
+        const int32_t c = w / qp, i = w - c * qp;
+        // codes outside the alphabet read row kNsym - 1 (never outside the matrix)
+        const int32_t qc = i < qlen ? min((int32_t)q[i], kNsym - 1) : 0;
+        sw_prof[w] = i < qlen ? (uint8_t)km.m[qc * kNsym + c] : (uint8_t)0;
+    }
+    __syncthreads();
+    constexpr int kWavesPerBlock = kSwThreads / kLanes;
+    const int32_t wave_blocks = (n_long + kWavesPerBlock - 1) / kWavesPerBlock;
+    if ((int32_t)blockIdx.x < wave_blocks) {
+        const int32_t w = (int32_t)blockIdx.x * kWavesPerBlock + (int32_t)(threadIdx.x / kLanes);
+        if (w >= n_long) return;                  // uniform over the wavefront
+        const int32_t lane = threadIdx.x & (kLanes - 1);
+        const int32_t tgt = db.order[w];
+        const int64_t off = db.offsets[tgt];
+        const int32_t best = sw_wave(lane, db.letters + off, db.lens[tgt], col + off, sw_prof, qlen,
+                                     qp, gop, gep);
+        if (lane == 0) scores[tgt] = best;
+        return;
+    }
+    const int64_t g = (int64_t)(blockIdx.x - wave_blocks) * blockDim.x + threadIdx.x + n_long;
+    if (g >= db.n) return;
+    const int32_t tgt = db.order[g];
+    const int64_t off = db.offsets[tgt];
+    scores[tgt] = sw_lane(db.letters + off, db.lens[tgt], col + off, sw_prof, qlen, qp, gop, gep);
 }
 
 }  // namespace hs
