@@ -1138,11 +1138,13 @@ int hs_sw_scores_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, con
     const void* fn = (const void*)k_sw_scores;
     if ((rc = set_lds_limit(fn, lds))) return rc;
     // Targets whose one-lane sweep (a step per letter and 16-row pass) would
-    // outlast the wavefront sweep of the longest target (a step per letter,
-    // plus 63, and 1,024-row pass) take a wavefront each.
+    // outlast half the wavefront sweep of the longest target (a step per
+    // letter, plus 63, and 1,024-row pass) take a wavefront each: the lanes
+    // near the threshold share their SIMDs with other wavefronts, and at half
+    // the full search ran in 62 ms instead of 72 (a quarter gained nothing).
     const int64_t lane_passes = (qlen + kSwRows - 1) / kSwRows;
     const int64_t wave_passes = (qlen + kSwWaveRows - 1) / kSwWaveRows;
-    const int64_t thr = wave_passes * ((int64_t)db->lens_desc[0] + kLanes - 1) / lane_passes;
+    const int64_t thr = wave_passes * ((int64_t)db->lens_desc[0] + kLanes - 1) / (2 * lane_passes);
     const int32_t n_long = (int32_t)(std::partition_point(db->lens_desc.begin(), db->lens_desc.end(),
                                                           [&](int32_t L) { return L > thr; }) -
                                      db->lens_desc.begin());
