@@ -5,11 +5,12 @@
 // Gotoh's (1982) three-state recurrence; a gap run of g columns costs
 // GOP + (g - 1) * GEP, the gap convention of Section III.B.1.
 //
-// Layout: one lane per target, lanes taking the targets longest first (the
-// database's order array) so that the 64 targets of a wavefront have
-// similar lengths.  A lane sweeps its target in passes of kSwRows query
-// rows; the rows' H and horizontal-gap values live in registers and move
-// along the target one column per iteration.  The substitution scores of a
+// Layout: most targets take one lane each, longest first (the database's
+// order array), so that the 64 targets of a wavefront have similar lengths;
+// the longest targets take a whole wavefront each (sw_wave below), so that
+// no single lane sets the launch's critical path.  A lane sweeps its target
+// in passes of kSwRows query rows; the rows' H and horizontal-gap values
+// live in registers and move along the target one column per iteration.  The substitution scores of a
 // column for all kSwRows rows are one 16-byte LDS read from the query
 // profile (kNsym rows of qp bytes: score of query position i against code
 // c at c * qp + i).  Between passes the bottom row's H and vertical-gap
