@@ -14,6 +14,12 @@ every target beside the heuristic's search of the same query (its roofline
 counts 11 32-bit integer ops per cell against 256 CUs x 64 lanes x 2.4 GHz =
 39.3 TOP/s).
 
+The default run also measures the rest of the metric in the same line: a
+`batched` object (the 256-query batch against the same queries searched one
+at a time, with the batch scoring kernel's roofline) and a `serving` object
+(p50/p99 latency and the sustained rate at 50, 200 and 500 queries/s, plus a
+saturating 5,000 queries/s for information).
+
 Prints one JSON line.  `value` is query*database residues per second with the
 database and the query resident in device memory when timing starts.  The
 roofline object covers the dominant kernel (pair scoring): algorithmic integer
@@ -67,6 +73,25 @@ def traffic_from_profile():
     return d.get("hbm_bytes_per_launch")
 
 
+def host_facts():
+    """Host CPU facts for the CPU baseline: logical CPUs (nproc), the CPUs
+    this process may run on, and the model name."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
+
+
 def cpu_baseline(w, q, budget_s):
     """Oracle (plain single-threaded C) on every m-th target, m chosen so the
     sample takes about budget_s seconds."""
@@ -87,7 +112,7 @@ def cpu_baseline(w, q, budget_s):
     res = int(np.diff(w.offsets)[ids].sum())
     return {"value": len(q) * res / dt, "unit": "query*residues/s", "cores": 1, "kind": "oracle",
             "sample": f"every {m}th target ({len(ids)} of {w.n_targets}, {res} residues), "
-                      f"one query of {len(q)}, single thread, {dt:.1f} s"}
+                      f"one query of {len(q)}, single thread, {dt:.1f} s", **host_facts()}
 
 
 def cpu_baseline_batched(w, budget_s, stride=1):
@@ -110,7 +135,7 @@ def cpu_baseline_batched(w, budget_s, stride=1):
         f"all {w.n_targets} targets"
     return {"value": res / dt, "unit": "query*residues/s", "cores": 1, "kind": "oracle",
             "sample": f"first {m} of {len(w.queries)} queries against {which}, "
-                      f"single thread, {dt:.1f} s"}
+                      f"single thread, {dt:.1f} s", **host_facts()}
 
 
 BATCH_WORKLOADS = {
@@ -130,17 +155,22 @@ BATCH_WORKLOADS = {
 
 
 def bench_batched(args):
+    out = measure_batched(args, args.workload)
+    print(json.dumps(out), flush=True)
+
+
+def measure_batched(args, workload, cpu=True):
     import numpy as np
     import torch
 
     import paper_1508_06561_amd as H
     import synth
 
-    spec = BATCH_WORKLOADS[args.workload]
+    spec = BATCH_WORKLOADS[workload]
     w = getattr(synth, spec["gen"])()
     qs = [bytes(q) for q in w.queries]
     nres = sum(map(len, qs))
-    log(f"{args.workload} workload: {len(qs)} queries ({nres} residues) vs {w.n_targets} targets, "
+    log(f"{workload} workload: {len(qs)} queries ({nres} residues) vs {w.n_targets} targets, "
         f"{w.db_residues} residues")
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
@@ -154,7 +184,7 @@ def bench_batched(args):
         sched = b.get_schedule()
         log(f"fixed schedule {sched}")
     else:
-        tuned_ms = b.tune(reps=3 if args.workload == "batched" else 1)
+        tuned_ms = b.tune(reps=3 if workload == "batched" else 1)
         sched = b.get_schedule()
         log(f"tuned schedule {sched}: scoring {tuned_ms:.3f} ms")
     for _ in range(args.warmup):
@@ -214,7 +244,26 @@ def bench_batched(args):
     log(f"one at a time: {ms_single:.3f} ms for {len(qs)} queries")
 
     recall = None
-    if args.workload == "long":
+    # Setting a batch builds its round-0 draw table (one Philox pass over the
+    # database) when the seed differs from the cached table's; the replays
+    # above reuse the cached table, while each one-at-a-time search runs its
+    # own draw kernel.  Timed here with a fresh seed on every set (host
+    # encode, upload and table), for a like-for-like ratio.
+    reps_set = max(1, args.steps // 4)
+    t_set = 0.0
+    for i in range(reps_set):
+        pf = H.Params(seed=1000 + i)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        b.set(qs, pf)
+        b.run(graph=False)
+        torch.cuda.synchronize()
+        t_set += time.perf_counter() - t
+    ms_set_run = t_set * 1e3 / reps_set
+    b.set(qs, p)
+    log(f"set (fresh seed) + run: {ms_set_run:.3f} ms per batch")
+
+    if workload == "long":
         # two planted homologs per query, in query order
         hits = b.results()
         per = len(w.planted) // len(qs)
@@ -245,6 +294,11 @@ def bench_batched(args):
         "ms_direct_launch": ms_eager,
         "one_at_a_time": {"ms": ms_single, "value": qres / (ms_single * 1e-3),
                           "batch_speedup": ms_single / ms},
+        "draw_table": {"note": "hs_batch_set caches the round-0 random-draw table per "
+                               "(database, seed); graph replays reuse it, each one-at-a-time "
+                               "search runs its own draw kernel",
+                       "ms_set_fresh_seed_and_run": ms_set_run,
+                       "batch_speedup_incl_set": ms_single / ms_set_run},
         "roofline": {"bound": "alu", "kernel": "k_score_batch", "achieved": achieved,
                      "peak": ALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS,
                      "traffic": None, "ops_per_cell": OPS_PER_CELL,
@@ -253,15 +307,44 @@ def bench_batched(args):
     }
     if recall is not None:
         out["homolog_recall"] = recall
-    if not args.no_cpu:
+    if cpu and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_batched(w, args.cpu_budget, spec["cpu_stride"])
         log(f"cpu baseline: {out['cpu_baseline']}")
     b.close()
     db.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_serving(args):
+    rows = measure_serving(args, args.rates)
+    top = rows[-1]
+    out = {
+        "metric": f"p99 query latency (serving, Poisson {top['rate']} queries/s)",
+        "value": top["p99_ms"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": sum(r["queries"] for r in rows),
+        "warmup": 16,
+        "ms_per_step": top["mean_ms"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded; Poisson arrivals, log-normal query lengths)",
+        "config": {"workload": SERVING_DESC.format(rates=", ".join(f"{r:g}" for r in args.rates),
+                                                   secs=args.serve_s)},
+        "serving": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
+SERVING_DESC = ("Poisson arrivals at {rates} queries/s for {secs} s each, |Q| log-normal (median "
+                "250, sigma 0.6, clip 20-2,000), vs 2,020 targets U[50,500]; top 500 hits and "
+                "top 50 alignments per query; continuous batching (at most 64 queries per "
+                "batch, two batches in flight)")
+
+
+def measure_serving(args, rates):
     import threading
 
     import numpy as np
@@ -292,7 +375,7 @@ def bench_serving(args):
                 srv.result(t)
                 done = True
     rows = []
-    for ri, rate in enumerate(args.rates):
+    for ri, rate in enumerate(rates):
         w = synth.config_serving(rate, duration_s=args.serve_s)
         qs = [bytes(q) for q in w.queries]
         base = (ri + 1) << 32
@@ -314,39 +397,24 @@ def bench_serving(args):
                 timings.append(tm)
         th.join()
         lat = np.array([t["total_ms"] for t in timings])
+        qms = np.array([t["queue_ms"] for t in timings])
+        bms = np.array([t["batch_ms"] for t in timings])
         start = min(t["submit_ms"] for t in timings)
         end = max(t["submit_ms"] + t["total_ms"] for t in timings)
         row = {"rate": rate, "queries": len(qs), "p50_ms": float(np.percentile(lat, 50)),
-               "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+               "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
+               "mean_ms": float(lat.mean()),
+               "p99_queue_ms": float(np.percentile(qms, 99)),
+               "p99_batch_ms": float(np.percentile(bms, 99)),
                "sustained_qps": len(qs) / ((end - start) * 1e-3),
                "mean_batch": float(np.mean([t["batch_size"] for t in timings])),
-               "mean_batch_ms": float(np.mean([t["batch_ms"] for t in timings]))}
+               "max_batch": int(max(t["batch_size"] for t in timings)),
+               "mean_batch_ms": float(bms.mean())}
         log(f"rate {rate}/s: {row}")
         rows.append(row)
     srv.close()
     db.close()
-    top = rows[-1]
-    out = {
-        "metric": f"p99 query latency (serving, Poisson {top['rate']} queries/s)",
-        "value": top["p99_ms"],
-        "unit": "ms",
-        "n_gpus": 1,
-        "steps": sum(r["queries"] for r in rows),
-        "warmup": 16,
-        "ms_per_step": top["mean_ms"],
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic (seeded; Poisson arrivals, log-normal query lengths)",
-        "config": {"workload": "Poisson arrivals at 50, 200 and 500 queries/s for "
-                               f"{args.serve_s} s each, |Q| log-normal (median 250, sigma 0.6, "
-                               "clip 20-2,000), vs 2,020 targets U[50,500]; top 500 hits and "
-                               "top 50 alignments per query; continuous batching (at most 64 "
-                               "queries per batch, two batches in flight)"},
-        "serving": rows,
-    }
-    print(json.dumps(out), flush=True)
+    return rows
 
 
 SW_OPS_PER_CELL = 11     # Gotoh cell: 4 subtractions, 1 addition, 6 maxima (with the running best)
@@ -370,7 +438,7 @@ def cpu_baseline_sw(w, q, budget_s):
     dt = time.perf_counter() - t
     return {"value": len(q) * res / dt, "unit": "query*residues/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n} of {w.n_targets} targets ({res} residues), one query of "
-                      f"{len(q)}, single thread, {dt:.1f} s"}
+                      f"{len(q)}, single thread, {dt:.1f} s", **host_facts()}
 
 
 def bench_sw(args):
@@ -465,6 +533,12 @@ def main():
     ap.add_argument("--schedule", type=int, nargs=3, metavar=("COPIES", "CAP", "CHUNK"),
                     help="batch workloads: fixed schedule instead of the autotuner")
     ap.add_argument("--serve-s", type=float, default=2.0, help="seconds of arrivals per rate")
+    ap.add_argument("--saturate", type=float, default=5000.0,
+                    help="default run: an extra serving rate beyond the three of the workload "
+                         "(0: none)")
+    ap.add_argument("--full-only", action="store_true",
+                    help="default run: the one-query line alone, without the batched and "
+                         "serving objects")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device (counter calibration)")
     args = ap.parse_args()
@@ -544,7 +618,7 @@ def main():
 
     qres = len(q) * w.db_residues
     out = {
-        "metric": "query*DB residues/sec on 1 GPU (one query)",
+        "metric": "query*DB residues/sec on 1 GPU, batched vs one-query; p50/p99 query latency",
         "value": qres / (ms * 1e-3),
         "unit": "query*residues/s",
         "n_gpus": 1,
@@ -574,6 +648,23 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, q, args.cpu_budget)
         log(f"cpu baseline: {out['cpu_baseline']}")
     db.close()
+    del ds, scores, cells_t
+    if not args.full_only:
+        # the rest of the metric: the batched search against the one-query
+        # kernel, and serving latency, as objects of the same line
+        bt = measure_batched(args, "batched", cpu=False)
+        out["batched"] = {"workload": bt["config"]["workload"], "value": bt["value"],
+                          "unit": bt["unit"], "ms_per_batch": bt["ms_per_step"],
+                          "ms_direct_launch": bt["ms_direct_launch"],
+                          "one_at_a_time": bt["one_at_a_time"], "draw_table": bt["draw_table"],
+                          "schedule": bt["config"]["schedule"], "roofline": bt["roofline"]}
+        rates = list(args.rates) + ([args.saturate] if args.saturate else [])
+        rows = measure_serving(args, rates)
+        out["serving"] = {"workload": SERVING_DESC.format(rates=", ".join(f"{r:g}" for r in rates),
+                                                          secs=args.serve_s),
+                          "rows": rows,
+                          "note": f"{args.saturate:g} q/s is a saturating rate, information only"
+                                  if args.saturate else ""}
     print(json.dumps(out), flush=True)
 
 

@@ -341,7 +341,9 @@ typedef struct hs_server_timing {
 
 /* Creates a server with two workers on the current device for searches
  * returning k ranks and n_aln alignments per query (limits as in
- * hs_batch_create).  The database must outlive the server. */
+ * hs_batch_create, and max_residues >= max_qlen so that every acceptable
+ * query can be admitted: HS_EINVAL otherwise).  The database must outlive
+ * the server. */
 int hs_server_create(const hs_db* db, int32_t max_batch, int32_t max_qlen, int64_t max_residues,
                      int32_t k, int32_t n_aln, hs_server** out);
 

@@ -195,6 +195,10 @@ int hs_server_create_workers(const hs_db* db, int32_t max_batch, int32_t max_qle
     if (!out) return sfail(HS_EINVAL, "out is NULL");
     if (n_workers < 1 || n_workers > HS_MAX_SERVER_WORKERS)
         return sfail(HS_EINVAL, "n_workers must lie in [1, HS_MAX_SERVER_WORKERS]");
+    // a query longer than max_residues could never be admitted: it would stay
+    // at the head of the queue and block every query behind it
+    if (max_qlen > 0 && max_residues < max_qlen)
+        return sfail(HS_EINVAL, "max_residues must be at least max_qlen");
     hs_server* s = new hs_server();
     s->workers.resize((size_t)n_workers);
     int rc = HS_OK;
@@ -254,7 +258,8 @@ int hs_server_submit(hs_server* s, const char* query, int32_t qlen, const hs_par
                      uint64_t tag) {
     if (!s) return sfail(HS_EINVAL, "server is NULL");
     if (!query || !params) return sfail(HS_EINVAL, "NULL query or params");
-    if (qlen < 1 || qlen > s->max_qlen) return sfail(HS_EINVAL, "qlen must lie in [1, max_qlen]");
+    if (qlen < 1 || qlen > s->max_qlen || qlen > s->max_residues)
+        return sfail(HS_EINVAL, "qlen must lie in [1, max_qlen] and fit max_residues");
     if (int rc = hs_params_check(params)) return rc;
     std::vector<uint8_t> codes((size_t)qlen);
     if (hs_encode(query, qlen, codes.data())) return HS_EINVAL;

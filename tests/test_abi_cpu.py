@@ -138,3 +138,16 @@ def test_server_argument_errors_before_device_use():
     assert L.hs_params_check(ctypes.byref(p)) == 0
     assert L.hs_params_check(ctypes.byref(H.Params(gep=-1).c())) == E
     assert L.hs_params_check(ctypes.byref(H.Params(rounds=0).c())) == E
+
+
+def test_server_rejects_a_footprint_that_cannot_admit_its_longest_query():
+    """A query longer than max_residues could never be admitted and would
+    block the queue behind it, so such a server is refused at creation
+    (checked before any device work)."""
+    import paper_1508_06561_amd as H
+    L = H.lib()
+    h = ctypes.c_void_p()
+    rc = L.hs_server_create_workers(ctypes.c_void_p(1), 4, 100, 99, 10, 5, 2, ctypes.byref(h))
+    assert rc == H.hs.HS_EINVAL and b"max_residues" in L.hs_last_error()
+    rc = L.hs_server_create(ctypes.c_void_p(1), 4, 100, 50, 10, 5, ctypes.byref(h))
+    assert rc == H.hs.HS_EINVAL

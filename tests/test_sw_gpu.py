@@ -3,9 +3,11 @@ score against the oracle's Gotoh checker (itself pinned by exhaustive
 enumeration of alignments on tiny inputs), bit for bit, on the tiny database
 over ragged query lengths and gap parameters, an asymmetric matrix, the
 longest query against long targets (sampled), and the full 500,200-target
-database (sampled, plus the bound that no heuristic pair score exceeds the
-optimum, for every target)."""
+database (every score against the oracle's stored score vector, plus the
+bound that no heuristic pair score exceeds the optimum, for every target)."""
 import concurrent.futures as cf
+import hashlib
+import json
 import os
 import sys
 
@@ -18,6 +20,7 @@ import synth
 pytestmark = pytest.mark.gpu
 
 ALPHA = b"ARNDCQEGHILKMFPSTWYVBZX*"
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def H():
@@ -120,18 +123,28 @@ def test_longest_query_long_targets():
         db.close()
 
 
-def test_full_size_sampled_and_bound():
-    """The full 500,200-target database with the 300-residue query: sampled
-    scores against the oracle (the longest targets, the planted homologs and
-    a random sample), and for every target the bound that the heuristic's
-    pair score never exceeds the local optimum (its alignment, with end gaps
-    removed, is one of the alignments the optimum ranges over)."""
+def test_full_size_every_score_and_bound():
+    """The full 500,200-target database with the 300-residue query: every
+    one of the 500,200 scores against the oracle's (stored by
+    tests/golden/make_golden.py sw_full: SHA-256 of the whole score vector,
+    its sum and the 500 best), a sample rescored by the oracle here, and for
+    every target the bound that the heuristic's pair score never exceeds the
+    local optimum (its alignment, with end gaps removed, is one of the
+    alignments the optimum ranges over)."""
+    gold = json.load(open(os.path.join(GOLDEN, "sw_full_oracle.json")))
     w = synth.config_full()
+    assert w.n_targets == gold["n_targets"]
     db = H().Database(w.residues, w.offsets)
     try:
         q = bytes(w.queries[0])
         sw = db.sw_scores(q)
         say("gpu sw scores done")
+        top = O.rank(sw, len(gold["top_ids"]))
+        assert [int(i) for i in top] == gold["top_ids"]
+        assert [int(sw[i]) for i in top] == gold["top_scores"]
+        assert int(sw.astype(np.int64).sum()) == gold["score_sum"]
+        assert hashlib.sha256(np.ascontiguousarray(sw, dtype="<i4").tobytes()).hexdigest() == \
+            gold["scores_sha256"], "the score vector differs from the oracle's"
         heur, _, _ = db.scores(q)
         assert (sw >= heur).all(), f"{(sw < heur).sum()} targets above the optimum"
         assert (sw >= 0).all()
@@ -140,7 +153,7 @@ def test_full_size_sampled_and_bound():
         rng = np.random.default_rng(11)
         ids = np.unique(np.concatenate([np.argsort(-lens, kind="stable")[:8],
                                         np.asarray(w.planted[:40]),
-                                        rng.choice(w.n_targets, 300, replace=False)]))
+                                        rng.choice(w.n_targets, 100, replace=False)]))
         ref = sw_ref(codes, w.offsets, O.encode(q), ids)
         say("oracle sample done")
         assert (sw[ids] == ref).all(), f"{(sw[ids] != ref).sum()} sampled scores differ"
