@@ -168,6 +168,29 @@ int hs_search_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const 
                   hs_hit* d_hits, int32_t* d_n_hits, hs_aln* d_alns, uint32_t* d_ops,
                   int64_t ops_stride);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): hs_search_dev
+ * without the workspace argument.  The workspace is a static device array of
+ * HS_NOALLOC_SCRATCH_BYTES that comes with the library's code object; each
+ * device holds its own copy from the library's first kernel launch there until
+ * the process ends.  The call allocates nothing (no hipMalloc, hipFree or
+ * other allocating routine); the caller still passes the query and the
+ * outputs, with the meaning, layout and ownership of hs_search_dev.
+ *   HS_ENOMEM   the database needs more workspace than the scratch holds:
+ *               hs_workspace_bytes(db, 1, qlen, k, n_aln) above
+ *               HS_NOALLOC_SCRATCH_BYTES (about 72 bytes per target, so
+ *               databases of up to roughly 900,000 targets fit)
+ *   HS_EINVAL   as hs_search_dev
+ * Every call on one device shares that device's scratch and keeps the last
+ * call's contents there (each search resets what it needs): calls that
+ * overlap on one device -- queued on different streams, or from different
+ * threads, without ordering -- race and give undefined results. */
+#define HS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int hs_search_dev_noalloc(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen,
+                          const hs_params* params, int32_t k, int32_t n_aln, void* stream,
+                          hs_hit* d_hits, int32_t* d_n_hits, hs_aln* d_alns, uint32_t* d_ops,
+                          int64_t ops_stride);
+
 /* Pair scores only: the search-mode heuristic score of the query against
  * every target (Fig. 1 with Section III.B.3), written by target index into
  * d_scores (int32) and the winning round into d_rounds (int32; may be NULL),

@@ -279,9 +279,22 @@ struct Occupancy {
     size_t lds;
     int per_cu;
 };
+// Fixed capacity, so that asking allocates nothing (hs_search_dev_noalloc
+// relies on it); once full, answers are asked of the runtime again instead
+// of kept.
+template <class T, int N>
+struct FixedCache {
+    T v[N];
+    int n = 0;
+    T* begin() { return v; }
+    T* end() { return v + n; }
+    void push_back(const T& x) {
+        if (n < N) v[n++] = x;
+    }
+};
 std::mutex g_kernel_info_mu;
-std::vector<LdsLimit> g_lds_limits;
-std::vector<Occupancy> g_occupancies;
+FixedCache<LdsLimit, 256> g_lds_limits;
+FixedCache<Occupancy, 512> g_occupancies;
 
 int current_device() {
     int dev = 0;
@@ -1037,6 +1050,60 @@ int hs_search_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const 
         return fail(HS_ENOSPC, "workspace too small");
     if (n_aln > 0 && ops_stride < 2 * (int64_t)qlen + 2) return fail(HS_EINVAL, "ops_stride too small");
     return launch_search(db, d_qcodes, qlen, params, k, n_aln, (hipStream_t)stream, d_ws,
+                         (DevHit*)d_hits, d_n_hits, (DevAln*)d_alns, d_ops, ops_stride);
+}
+
+// Workspace of hs_search_dev_noalloc: device memory that comes with the code
+// object, so that the call allocates nothing.  Each device the library runs
+// on holds its own copy until the process ends.  Host code never passes this
+// name to a kernel or a copy (on the host it is only a stand-in for the
+// symbol): it uses the device address taken below.
+static __device__ __align__(256) uint8_t scratch[HS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];   // device address of `scratch`, per device
+
+// Device address of the current device's scratch array, taken once per
+// device with that device current.
+int scratch_address(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(HS_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(HS_EDEVICE, "no device address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HS_OK;
+}
+}  // namespace
+
+int hs_search_dev_noalloc(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen,
+                          const hs_params* params, int32_t k, int32_t n_aln, void* stream,
+                          hs_hit* d_hits, int32_t* d_n_hits, hs_aln* d_alns, uint32_t* d_ops,
+                          int64_t ops_stride) {
+    int rc = check_search_args(db, qlen, params, k, n_aln);
+    if (rc) return rc;
+    if (!d_qcodes || !d_hits || !d_n_hits || (n_aln > 0 && (!d_alns || !d_ops)))
+        return fail(HS_EINVAL, "NULL device pointer");
+    if (n_aln > 0 && ops_stride < 2 * (int64_t)qlen + 2) return fail(HS_EINVAL, "ops_stride too small");
+    const size_t need = hs_workspace_bytes(db, 1, qlen, k, n_aln);
+    if (need > (size_t)HS_NOALLOC_SCRATCH_BYTES)
+        return fail(HS_ENOMEM, "database needs a workspace of " + std::to_string(need) +
+                                   " bytes, above the static scratch of " +
+                                   std::to_string((size_t)HS_NOALLOC_SCRATCH_BYTES) +
+                                   " (use hs_search_dev with a workspace)");
+    void* ws = nullptr;
+    if ((rc = scratch_address(&ws))) return rc;
+    // every piece of state the search needs zeroed (queue counter, ranking
+    // state) is reset by its own kernels, so the previous call's contents do
+    // no harm
+    return launch_search(db, d_qcodes, qlen, params, k, n_aln, (hipStream_t)stream, ws,
                          (DevHit*)d_hits, d_n_hits, (DevAln*)d_alns, d_ops, ops_stride);
 }
 

@@ -88,6 +88,8 @@ def lib():
         L.hs_search_dev.argtypes = [vp, vp, ctypes.c_int32, P(_CParams), ctypes.c_int32,
                                     ctypes.c_int32, vp, vp, ctypes.c_size_t, vp, vp, vp, vp,
                                     ctypes.c_int64]
+        L.hs_search_dev_noalloc.argtypes = [vp, vp, ctypes.c_int32, P(_CParams), ctypes.c_int32,
+                                            ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_int64]
         L.hs_score_dev.argtypes = [vp, vp, ctypes.c_int32, P(_CParams), vp, vp, ctypes.c_size_t,
                                    vp, vp, vp]
         i32, i64, pi32 = ctypes.c_int32, ctypes.c_int64, P(ctypes.c_int32)
@@ -251,6 +253,17 @@ class Database:
                                    d_alns.data_ptr() if d_alns is not None else None,
                                    d_ops.data_ptr() if d_ops is not None else None, ops_stride))
 
+    def search_dev_noalloc(self, d_qcodes, qlen, params, k, n_aln, d_hits, d_n_hits, d_alns,
+                           d_ops, ops_stride, stream=None):
+        """hs_search_dev_noalloc: search_dev with the library's static device
+        scratch as its workspace (allocates nothing)."""
+        p = params.c()
+        _check(lib().hs_search_dev_noalloc(self._h, d_qcodes.data_ptr(), qlen, ctypes.byref(p), k,
+                                           n_aln, _stream(stream), d_hits.data_ptr(),
+                                           d_n_hits.data_ptr(),
+                                           d_alns.data_ptr() if d_alns is not None else None,
+                                           d_ops.data_ptr() if d_ops is not None else None,
+                                           ops_stride))
 
     def score_dev(self, d_qcodes, qlen, params, d_ws, d_scores, d_rounds=None, d_cells=None,
                   stream=None):
@@ -324,9 +337,14 @@ class DeviceSearch:
         self.qlen = len(codes)
         self.q[:self.qlen].copy_(torch.from_numpy(codes))
 
-    def run(self, params, stream=None):
-        self.db.search_dev(self.q, self.qlen, params, self.k, self.n_aln, self.ws, self.hits,
-                           self.n_hits, self.alns, self.ops, self.stride, stream)
+    def run(self, params, stream=None, noalloc=False):
+        """Queues the search; noalloc: through hs_search_dev_noalloc."""
+        if noalloc:
+            self.db.search_dev_noalloc(self.q, self.qlen, params, self.k, self.n_aln, self.hits,
+                                       self.n_hits, self.alns, self.ops, self.stride, stream)
+        else:
+            self.db.search_dev(self.q, self.qlen, params, self.k, self.n_aln, self.ws, self.hits,
+                               self.n_hits, self.alns, self.ops, self.stride, stream)
 
     def fetch(self):
         """Copies the last results to the host (synchronises)."""
