@@ -205,6 +205,48 @@ int hs_score_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const h
                  uint64_t* d_cells);
 
 /* ---------------------------------------------------------------------------
+ * Threshold reporting.  Section IV reports the database sequences whose
+ * score reaches a threshold, ranked.  These calls return every target
+ * scoring at least params->min_score, in rank order (score descending,
+ * target index ascending), with no cap on the count (hs_search keeps at most
+ * HS_MAX_K ranks), and alignments for the first n_aln of them.  The ranking
+ * is a stable radix sort on the device; scores are those of hs_search.
+ * ------------------------------------------------------------------------- */
+
+/* Device workspace bytes of hs_search_threshold_dev for `db` (0 for NULL):
+ * the search's workspace plus 16 bytes per target and a histogram. */
+size_t hs_threshold_workspace_bytes(const hs_db* db);
+
+/* Device form, queued on `stream`:
+ *   d_qcodes, qlen   device query codes (hs_encode), 1..HS_MAX_QUERY
+ *   cap              ranks the caller has room for (>= 0)
+ *   n_aln            alignments wanted, 0..min(cap, HS_MAX_K)
+ *   d_ws, ws_bytes   device workspace of at least hs_threshold_workspace_bytes
+ *   d_hits           device array of cap hits: the first min(n, cap) ranks
+ *   d_n              one device int64: n, the number of targets at or above
+ *                    the threshold (written also when n > cap)
+ *   d_alns, d_ops    as hs_search_dev: alignment i (i < min(n_aln, n)) belongs
+ *                    to rank i, its ops at d_ops + i * ops_stride
+ * Errors: HS_EINVAL (arguments), HS_ENOSPC (workspace too small), HS_EDEVICE. */
+int hs_search_threshold_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen,
+                            const hs_params* params, int64_t cap, int32_t n_aln, void* stream,
+                            void* d_ws, size_t ws_bytes, hs_hit* d_hits, int64_t* d_n,
+                            hs_aln* d_alns, uint32_t* d_ops, int64_t ops_stride);
+
+/* Host form (host query in, host results out; returns when they are there):
+ *   hits, cap        host array of cap entries; *n_hits receives n.  When
+ *                    n > cap the call returns HS_ENOSPC with *n_hits set and
+ *                    writes nothing else, so that the caller can retry with
+ *                    cap >= *n_hits
+ *   n_aln, alns, n_alns, ops, ops_cap, ops_used
+ *                    as hs_search, for the first min(n_aln, n) ranks
+ * Device memory is allocated per call. */
+int hs_search_threshold(const hs_db* db, const char* query, int32_t qlen, const hs_params* params,
+                        int64_t cap, int32_t n_aln, void* stream, hs_hit* hits, int64_t* n_hits,
+                        hs_aln* alns, int32_t* n_alns, uint32_t* ops, int64_t ops_cap,
+                        int64_t* ops_used);
+
+/* ---------------------------------------------------------------------------
  * Smith-Waterman baseline.  The exact optimum that the paper measures its
  * heuristic against (Sections I and IV compare the two for speed and
  * sensitivity): Smith & Waterman (1981) local alignment with Gotoh's (1982)

@@ -17,6 +17,7 @@
 #include "topk_kernels.hpp"
 #include "traceback_kernels.hpp"
 #include "sw_kernels.hpp"
+#include "threshold_kernels.hpp"
 
 using namespace hs;
 
@@ -261,6 +262,15 @@ int check_search_args(const hs_db* db, int32_t qlen, const hs_params* p, int32_t
     if (qlen < 1 || qlen > HS_MAX_QUERY) return fail(HS_EINVAL, "qlen must lie in [1, HS_MAX_QUERY]");
     if (k < 1 || k > HS_MAX_K) return fail(HS_EINVAL, "k must lie in [1, HS_MAX_K]");
     if (n_aln < 0 || n_aln > k) return fail(HS_EINVAL, "n_aln must lie in [0, k]");
+    return check_params(p);
+}
+
+int check_threshold_args(const hs_db* db, int32_t qlen, const hs_params* p, int64_t cap,
+                         int32_t n_aln) {
+    if (!db) return fail(HS_EINVAL, "db is NULL");
+    if (qlen < 1 || qlen > HS_MAX_QUERY) return fail(HS_EINVAL, "qlen must lie in [1, HS_MAX_QUERY]");
+    if (cap < 0) return fail(HS_EINVAL, "cap must be >= 0");
+    if (n_aln < 0 || n_aln > HS_MAX_K) return fail(HS_EINVAL, "n_aln must lie in [0, HS_MAX_K]");
     return check_params(p);
 }
 
@@ -553,6 +563,77 @@ int launch_search(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_pa
                                    ops_stride, L)
                  : launch_trace<1>(db, d_q, qlen, kp, km, st, d_hits, d_n_hits, n_aln, d_alns, d_ops,
                                    ops_stride, L);
+        if (rc) return rc;
+    }
+    return HS_OK;
+}
+
+// Threshold workspace: the search's own workspace, then the radix sort's
+// state, histogram and two key buffers.
+size_t threshold_ws_bytes(const hs_db* db) {
+    const size_t n = (size_t)std::max<int64_t>(db->n_targets, 1);
+    const size_t tiles = (size_t)std::max<int64_t>(rs_tiles(db->n_targets), 1);
+    return query_ws_bytes(db->n_targets, db->n_queue, 1) + align_up(sizeof(RsState)) +
+           align_up(sizeof(uint32_t) * kRsBins * tiles) + 4 * align_up(sizeof(uint32_t) * n);
+}
+
+RsWs carve_rs(void* ws, const hs_db* db) {
+    const size_t n = (size_t)std::max<int64_t>(db->n_targets, 1);
+    const size_t tiles = (size_t)std::max<int64_t>(rs_tiles(db->n_targets), 1);
+    char* p = (char*)ws + query_ws_bytes(db->n_targets, db->n_queue, 1);
+    RsWs r;
+    r.st = (RsState*)p;
+    p += align_up(sizeof(RsState));
+    r.hist = (uint32_t*)p;
+    p += align_up(sizeof(uint32_t) * kRsBins * tiles);
+    r.v[0] = (uint32_t*)p;
+    p += align_up(sizeof(uint32_t) * n);
+    r.v[1] = (uint32_t*)p;
+    p += align_up(sizeof(uint32_t) * n);
+    r.id[0] = (int32_t*)p;
+    p += align_up(sizeof(uint32_t) * n);
+    r.id[1] = (int32_t*)p;
+    return r;
+}
+
+// Queues a threshold search: scoring, the radix passes, the ranked hits
+// and the alignments of the first n_aln ranks.  All pointers are device
+// pointers.
+int launch_threshold(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_params* p,
+                     int64_t cap, int32_t n_aln, hipStream_t st, void* d_ws, DevHit* d_hits,
+                     int64_t* d_n, DevAln* d_alns, uint32_t* d_ops, int64_t ops_stride) {
+    QueryWs w = carve(d_ws, db->n_targets, db->n_queue);
+    RsWs r = carve_rs(d_ws, db);
+    hipLaunchKernelGGL(k_rs_reset, dim3(1), dim3(64), 0, st, r.st);
+    if (db->n_targets == 0)   // no draw kernel runs: reset the ranking state here
+        hipLaunchKernelGGL(k_topk_reset, dim3(1, 1), dim3(256), 0, st, w.tw(), p->min_score,
+                           (const BatchQuery*)nullptr, (uint32_t*)nullptr);
+    int rc = launch_score(db, d_q, qlen, p, st, w, w.scores, w.rounds, nullptr, &w.topk->max_score,
+                          true);
+    if (rc) return rc;
+    const int32_t n = (int32_t)db->n_targets;
+    const int32_t tiles = (int32_t)std::max<int64_t>(rs_tiles(n), 1);
+    for (int pass = 0; pass < 4; ++pass) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(tiles), dim3(kRsThreads), 0, st, pass,
+                           (const int32_t*)w.scores, n, (const TopkState*)w.topk, r, tiles);
+        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(kRsScanThreads), 0, st, pass, r, tiles);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(tiles), dim3(kRsThreads), 0, st, pass,
+                           (const int32_t*)w.scores, n, (const TopkState*)w.topk, r, tiles);
+    }
+    const int64_t out_blocks = std::max<int64_t>(1, std::min<int64_t>((std::min<int64_t>(cap, n) + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_rs_out, dim3((unsigned)out_blocks), dim3(256), 0, st,
+                       (const TopkState*)w.topk, r, (const int32_t*)w.rounds, cap, d_hits, d_n);
+    HIP_TRY(hipGetLastError());
+    if (n_aln > 0) {
+        const KParams kp = kparams(p);
+        const KMatrix km = kmatrix(p);
+        QueryLayout L;
+        if ((rc = query_layout(qlen, &L))) return rc;
+        rc = L.copies == 4
+                 ? launch_trace<4>(db, d_q, qlen, kp, km, st, d_hits, &r.st->n_out, n_aln, d_alns,
+                                   d_ops, ops_stride, L)
+                 : launch_trace<1>(db, d_q, qlen, kp, km, st, d_hits, &r.st->n_out, n_aln, d_alns,
+                                   d_ops, ops_stride, L);
         if (rc) return rc;
     }
     return HS_OK;
@@ -891,6 +972,36 @@ int check_batch_ready(const hs_batch* b) {
 
 }  // namespace
 
+// Workspace of hs_search_dev_noalloc: device memory that comes with the code
+// object, so that the call allocates nothing.  Each device the library runs
+// on holds its own copy until the process ends.  Host code never passes this
+// name to a kernel or a copy (on the host it is only a stand-in for the
+// symbol): it uses the device address taken below.
+static __device__ __align__(256) uint8_t scratch[HS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];   // device address of `scratch`, per device
+
+// Device address of the current device's scratch array, taken once per
+// device with that device current.
+int scratch_address(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(HS_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(HS_EDEVICE, "no device address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HS_OK;
+}
+}  // namespace
+
 // --------------------------------------------------------------------------
 // C ABI
 // --------------------------------------------------------------------------
@@ -1053,36 +1164,6 @@ int hs_search_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const 
                          (DevHit*)d_hits, d_n_hits, (DevAln*)d_alns, d_ops, ops_stride);
 }
 
-// Workspace of hs_search_dev_noalloc: device memory that comes with the code
-// object, so that the call allocates nothing.  Each device the library runs
-// on holds its own copy until the process ends.  Host code never passes this
-// name to a kernel or a copy (on the host it is only a stand-in for the
-// symbol): it uses the device address taken below.
-static __device__ __align__(256) uint8_t scratch[HS_NOALLOC_SCRATCH_BYTES];
-
-namespace {
-constexpr int kMaxDevices = 64;
-std::mutex g_scratch_mu;
-void* g_scratch_ptr[kMaxDevices];   // device address of `scratch`, per device
-
-// Device address of the current device's scratch array, taken once per
-// device with that device current.
-int scratch_address(void** out) {
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    if (dev < 0 || dev >= kMaxDevices) return fail(HS_EDEVICE, "device index beyond the scratch table");
-    std::lock_guard<std::mutex> lock(g_scratch_mu);
-    if (!g_scratch_ptr[dev]) {
-        void* ptr = nullptr;
-        HIP_TRY(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)));
-        if (!ptr) return fail(HS_EDEVICE, "no device address for the scratch array");
-        g_scratch_ptr[dev] = ptr;
-    }
-    *out = g_scratch_ptr[dev];
-    return HS_OK;
-}
-}  // namespace
-
 int hs_search_dev_noalloc(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen,
                           const hs_params* params, int32_t k, int32_t n_aln, void* stream,
                           hs_hit* d_hits, int32_t* d_n_hits, hs_aln* d_alns, uint32_t* d_ops,
@@ -1184,6 +1265,99 @@ int hs_score_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, const h
     QueryWs w = carve(d_ws, db->n_targets, db->n_queue);
     return launch_score(db, d_qcodes, qlen, params, (hipStream_t)stream, w, d_scores, d_rounds,
                         d_cells, nullptr);
+}
+
+size_t hs_threshold_workspace_bytes(const hs_db* db) {
+    if (!db) return 0;
+    return threshold_ws_bytes(db);
+}
+
+int hs_search_threshold_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen,
+                            const hs_params* params, int64_t cap, int32_t n_aln, void* stream,
+                            void* d_ws, size_t ws_bytes, hs_hit* d_hits, int64_t* d_n,
+                            hs_aln* d_alns, uint32_t* d_ops, int64_t ops_stride) {
+    int rc = check_threshold_args(db, qlen, params, cap, n_aln);
+    if (rc) return rc;
+    if (!d_qcodes || !d_ws || !d_n || (cap > 0 && !d_hits) || (n_aln > 0 && (!d_alns || !d_ops)))
+        return fail(HS_EINVAL, "NULL device pointer");
+    if (n_aln > cap) return fail(HS_EINVAL, "n_aln must not exceed cap");
+    if (ws_bytes < threshold_ws_bytes(db)) return fail(HS_ENOSPC, "workspace too small");
+    if (n_aln > 0 && ops_stride < 2 * (int64_t)qlen + 2) return fail(HS_EINVAL, "ops_stride too small");
+    return launch_threshold(db, d_qcodes, qlen, params, cap, n_aln, (hipStream_t)stream, d_ws,
+                            (DevHit*)d_hits, d_n, (DevAln*)d_alns, d_ops, ops_stride);
+}
+
+int hs_search_threshold(const hs_db* db, const char* query, int32_t qlen, const hs_params* params,
+                        int64_t cap, int32_t n_aln, void* stream, hs_hit* hits, int64_t* n_hits,
+                        hs_aln* alns, int32_t* n_alns, uint32_t* ops, int64_t ops_cap,
+                        int64_t* ops_used) {
+    int rc = check_threshold_args(db, qlen, params, cap, n_aln);
+    if (rc) return rc;
+    if (!query || !n_hits || (cap > 0 && !hits) || (n_aln > 0 && (!alns || !n_alns || !ops_used)))
+        return fail(HS_EINVAL, "NULL output pointer");
+    std::vector<uint8_t> qc((size_t)qlen);
+    if ((rc = hs_encode(query, qlen, qc.data()))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t stride = 2 * (int64_t)qlen + 2;
+    // the device keeps at most all targets' ranks, whatever the caller's cap
+    const int64_t dcap = std::min<int64_t>(cap, db->n_targets);
+    const int32_t na = (int32_t)std::min<int64_t>(n_aln, dcap);
+    const size_t ws = threshold_ws_bytes(db);
+    const size_t o_q = 0, o_n = align_up((size_t)qlen), o_hits = o_n + kAlign,
+                 o_alns = o_hits + align_up(sizeof(DevHit) * (size_t)std::max<int64_t>(dcap, 1)),
+                 o_ops = o_alns + align_up(sizeof(DevAln) * std::max(na, 1)),
+                 o_ws = o_ops + align_up(sizeof(uint32_t) * (size_t)stride * std::max(na, 1)),
+                 total = o_ws + ws;
+    char* d = nullptr;
+    if (hipMallocAsync((void**)&d, total, st) != hipSuccess)
+        return fail(HS_ENOMEM, "device workspace allocation failed");
+    int64_t n = 0;
+    rc = HS_OK;
+    if (hipMemcpyAsync(d + o_q, qc.data(), (size_t)qlen, hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = fail(HS_EDEVICE, "query copy failed");
+    if (!rc)
+        rc = launch_threshold(db, (const uint8_t*)(d + o_q), qlen, params, dcap, na, st, d + o_ws,
+                              (DevHit*)(d + o_hits), (int64_t*)(d + o_n), (DevAln*)(d + o_alns),
+                              (uint32_t*)(d + o_ops), stride);
+    if (!rc && (hipMemcpyAsync(&n, d + o_n, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess))
+        rc = fail(HS_EDEVICE, "threshold search failed on the device");
+    const int64_t n_out = std::min<int64_t>(n, dcap);
+    const int32_t n_a = (int32_t)std::min<int64_t>(na, n_out);
+    std::vector<DevAln> h_alns((size_t)std::max(n_a, 1));
+    std::vector<uint32_t> h_ops((size_t)stride * std::max(n_a, 1));
+    if (!rc && n <= cap) {
+        if ((n_out > 0 && hipMemcpyAsync(hits, d + o_hits, sizeof(DevHit) * (size_t)n_out,
+                                         hipMemcpyDeviceToHost, st) != hipSuccess) ||
+            (n_a > 0 && hipMemcpyAsync(h_alns.data(), d + o_alns, sizeof(DevAln) * n_a,
+                                       hipMemcpyDeviceToHost, st) != hipSuccess) ||
+            (n_a > 0 && hipMemcpyAsync(h_ops.data(), d + o_ops, sizeof(uint32_t) * stride * n_a,
+                                       hipMemcpyDeviceToHost, st) != hipSuccess) ||
+            hipStreamSynchronize(st) != hipSuccess)
+            rc = fail(HS_EDEVICE, "threshold results copy failed");
+    }
+    (void)hipFreeAsync(d, st);
+    if (rc) return rc;
+    *n_hits = n;
+    if (n > cap) return fail(HS_ENOSPC, "more targets reach the threshold than cap");
+    if (n_aln > 0) {
+        int64_t need = 0;
+        for (int32_t i = 0; i < n_a; ++i) need += h_alns[(size_t)i].n_ops;
+        *ops_used = need;
+        if (need > ops_cap) return fail(HS_ENOSPC, "ops buffer too small");
+        int64_t off = 0;
+        for (int32_t i = 0; i < n_a; ++i) {
+            const DevAln& a = h_alns[(size_t)i];
+            std::memcpy(ops + off, h_ops.data() + a.ops_off, sizeof(uint32_t) * a.n_ops);
+            alns[i].target_id = a.target_id;
+            alns[i].score = a.score;
+            alns[i].n_ops = a.n_ops;
+            alns[i].ops_off = off;
+            off += a.n_ops;
+        }
+        *n_alns = n_a;
+    }
+    return HS_OK;
 }
 
 int64_t hs_sw_workspace_bytes(const hs_db* db) {

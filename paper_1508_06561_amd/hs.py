@@ -92,6 +92,15 @@ def lib():
                                             ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_int64]
         L.hs_score_dev.argtypes = [vp, vp, ctypes.c_int32, P(_CParams), vp, vp, ctypes.c_size_t,
                                    vp, vp, vp]
+        L.hs_threshold_workspace_bytes.argtypes = [vp]
+        L.hs_threshold_workspace_bytes.restype = ctypes.c_size_t
+        L.hs_search_threshold_dev.argtypes = [vp, vp, ctypes.c_int32, P(_CParams), ctypes.c_int64,
+                                              ctypes.c_int32, vp, vp, ctypes.c_size_t, vp, vp, vp,
+                                              vp, ctypes.c_int64]
+        L.hs_search_threshold.argtypes = [vp, ctypes.c_char_p, ctypes.c_int32, P(_CParams),
+                                          ctypes.c_int64, ctypes.c_int32, vp, vp,
+                                          P(ctypes.c_int64), vp, P(ctypes.c_int32), vp,
+                                          ctypes.c_int64, P(ctypes.c_int64)]
         i32, i64, pi32 = ctypes.c_int32, ctypes.c_int64, P(ctypes.c_int32)
         L.hs_sw_workspace_bytes.argtypes = [vp]
         L.hs_sw_workspace_bytes.restype = ctypes.c_int64
@@ -238,6 +247,39 @@ class Database:
                                ctypes.byref(na), ops.ctypes.data, cap, ctypes.byref(used)))
         n_a = na.value if n_aln > 0 else 0
         return Result(hits[:nh.value].copy(), alns[:n_a].copy(), ops[:used.value].copy())
+
+    def search_threshold(self, query, params=None, cap=None, n_aln=0, stream=None):
+        """hs_search_threshold: every target scoring at least params.min_score,
+        ranked (no cap on the count), with alignments for the first n_aln.
+        cap defaults to the number of targets, which always suffices."""
+        p = (params or Params()).c()
+        q = query.encode() if isinstance(query, str) else bytes(query)
+        cap = self.n_targets if cap is None else cap
+        hits = np.zeros(max(cap, 1), dtype=HIT_DTYPE)
+        alns = np.zeros(max(n_aln, 1), dtype=ALN_DTYPE)
+        ocap = max(1, n_aln * (2 * len(q) + 2))
+        ops = np.zeros(ocap, dtype=np.uint32)
+        n, na, used = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().hs_search_threshold(self._h, q, len(q), ctypes.byref(p), cap, n_aln,
+                                         _stream(stream), hits.ctypes.data, ctypes.byref(n),
+                                         alns.ctypes.data, ctypes.byref(na), ops.ctypes.data,
+                                         ocap, ctypes.byref(used)))
+        n_a = na.value if n_aln > 0 else 0
+        return Result(hits[:n.value].copy(), alns[:n_a].copy(), ops[:used.value].copy())
+
+    def threshold_workspace_bytes(self):
+        return int(lib().hs_threshold_workspace_bytes(self._h))
+
+    def search_threshold_dev(self, d_qcodes, qlen, params, cap, n_aln, d_ws, d_hits, d_n,
+                             d_alns=None, d_ops=None, ops_stride=0, stream=None):
+        """Queues hs_search_threshold_dev; buffers are torch CUDA tensors."""
+        p = params.c()
+        _check(lib().hs_search_threshold_dev(
+            self._h, d_qcodes.data_ptr(), qlen, ctypes.byref(p), cap, n_aln, _stream(stream),
+            d_ws.data_ptr(), d_ws.numel() * d_ws.element_size(),
+            d_hits.data_ptr() if d_hits is not None else None, d_n.data_ptr(),
+            d_alns.data_ptr() if d_alns is not None else None,
+            d_ops.data_ptr() if d_ops is not None else None, ops_stride))
 
     # ---- device-resident form (hs_search_dev) ----
     def workspace_bytes(self, nq, max_qlen, k, n_aln):
