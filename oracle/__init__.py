@@ -47,7 +47,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("gop", ctypes.c_int32), ("gep", ctypes.c_int32), ("pgp", ctypes.c_int32),
                 ("lfactor_q16", ctypes.c_int32), ("sfactor_q16", ctypes.c_int32),
                 ("minfactor_q16", ctypes.c_int32), ("rounds", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("full_slide", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class _Step(ctypes.Structure):
@@ -59,7 +59,9 @@ class _Step(ctypes.Structure):
 class Params:
     """Parameters of Section III.B.1; defaults are the search setting of
     Section IV (PGP 0, GOP 10, GEP 5, LFactor 0.5, SFactor 1, MinFactor 0.5)
-    with Rounds = 1 (Section III.B.3).  Factors are Q16 (65536 = 1.0)."""
+    with Rounds = 1 (Section III.B.3).  Factors are Q16 (65536 = 1.0).
+    full_slide selects the pairwise mode of Fig. 1 (every overlapping
+    placement) instead of the search mode's contained shifts."""
     gop: int = 10
     gep: int = 5
     pgp: int = 0
@@ -68,10 +70,12 @@ class Params:
     minfactor_q16: int = 32768
     rounds: int = 1
     seed: int = 0
+    full_slide: bool = False
 
     def c(self):
         return _Params(self.gop, self.gep, self.pgp, self.lfactor_q16, self.sfactor_q16,
-                       self.minfactor_q16, self.rounds, 0, self.seed & (2**64 - 1))
+                       self.minfactor_q16, self.rounds, 1 if self.full_slide else 0,
+                       self.seed & (2**64 - 1))
 
 
 def alphabet():

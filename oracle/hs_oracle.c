@@ -9,9 +9,13 @@
  * the product library never links or calls it, and it shares no code,
  * header or table with the HIP path.
  *
- * Structure follows Fig. 1 of the paper, with the search-mode changes of
- * Section III.B.3 (Rounds = 1 by default, contained shifts only):
- *   align_sequences           -> ALGORITHM AlignSequences
+ * Structure follows Fig. 1 of the paper.  Two slides are implemented: the
+ * search mode of Section III.B.3 (contained shifts only; the database search
+ * runs it with Rounds = 1) and the pairwise mode of Fig. 1 as written (the
+ * small window slides across the large one from end to end, every placement
+ * overlapping at least one letter; the paper's alignment tests used
+ * Rounds = 20, Section V).
+ *   orc_align_pair            -> ALGORITHM AlignSequences
  *   align_round               -> PROCEDURE Align
  *   best_subsequence_alignment-> PROCEDURE getBestSubsequenceAlignment
  *   virtual_alignment_score   -> getVirtualAlignmentScore (Section III.B.2)
@@ -25,7 +29,13 @@
  *     (Section III.B.1 names the factors; Fig. 1 draws lf, sf).
  *   - All fractions are Q16 fixed point (1.0 = 65536); lengths are floored.
  *   - ls = max(1, floor(len(large) * LF)); ss = max(1, floor(len(small) *
- *     SF * u)), then ss = min(ss, ls) so that a contained shift exists.
+ *     SF * u)); in the search mode also ss = min(ss, ls), so that a
+ *     contained shift exists.
+ *   - A placement uses all ss letters of the small window (Fig. 1 removes
+ *     them from small whatever the shift) and, of the large window, its
+ *     letters up to the last one facing a small letter; the rest of the large
+ *     window goes back to large (Section III.B.2).  Small letters hanging
+ *     over either end of the large window face gaps (pairwise mode only).
  *   - random() is a 16-bit fraction taken from Philox4x64-10 (Salmon et al.,
  *     SC'11) keyed by (seed, 0) with counter (target_id, round, d/16, 0);
  *     draw d uses 16-bit chunk d%4 of output word (d/4)%4.  Draw 0 is lf,
@@ -157,7 +167,8 @@ typedef struct {
     int32_t gop, gep, pgp;                          /* Section III.B.1 */
     int32_t lfactor_q16, sfactor_q16, minfactor_q16; /* Q16, in [0, 65536] */
     int32_t rounds;                                 /* >= 1 */
-    int32_t pad_;
+    int32_t full_slide;     /* 0: search mode (Section III.B.3); 1: pairwise
+                               mode, every overlapping placement (Fig. 1) */
     uint64_t seed;
 } orc_params;
 
@@ -191,14 +202,17 @@ static int64_t virtual_alignment_score(orc_ctx* cx, const uint8_t* large, int32_
     return s;
 }
 
-/* getBestSubsequenceAlignment with the search-mode slide of Section III.B.3:
- * start = length(small) - 1, end = length(large) - 1, shift k = i -
- * length(small) + 1, so only placements with small wholly inside large are
- * graded.  The first shift reaching the best score is kept. */
+/* getBestSubsequenceAlignment: placement i puts small at shift
+ * k = i - length(small) + 1 of large.  Pairwise mode grades every placement
+ * with some overlap, i = 0 .. length(small) + length(large) - 2 (Fig. 1);
+ * the search mode of Section III.B.3 grades only i = length(small) - 1 ..
+ * length(large) - 1, where small lies wholly inside large.  The first
+ * placement reaching the best score is kept. */
 static void best_subsequence_alignment(orc_ctx* cx, const uint8_t* large, int32_t nl,
                                        const uint8_t* small, int32_t ns,
                                        int32_t* kbest, int64_t* sbest) {
-    int32_t start = ns - 1, end = nl - 1;
+    int32_t start = cx->p->full_slide ? 0 : ns - 1;
+    int32_t end = cx->p->full_slide ? ns + nl - 2 : nl - 1;
     int64_t best = INT64_MIN;
     int32_t bk = 0;
     for (int32_t i = start; i <= end; ++i) {
@@ -242,49 +256,58 @@ static int64_t score_columns(const int8_t* B, const uint8_t* aL, const uint8_t* 
     return s;
 }
 
-/* PROCEDURE Align(large, small, LF, SF): chop both sequences into windows,
- * place the small window at its best contained shift, consume what was used,
- * repeat until one sequence is exhausted, append the rest against gaps and
- * score the aligned rows.  aL / aS receive the aligned rows (capacity nl+ns). */
+/* PROCEDURE Align (Fig. 1): one round with factors LF and SF.  Each step
+ * takes a window from the front of each sequence, finds the best placement
+ * of the small window on the large one, moves the letters that placement
+ * used into the aligned rows and leaves the rest; when one sequence runs out,
+ * the other's remaining letters are set against gaps and the rows are scored
+ * with SCORE.  aL / aS receive the aligned rows (capacity nl + ns). */
 static int64_t align_round(orc_ctx* cx, const uint8_t* large, int32_t nl, const uint8_t* small,
                            int32_t ns, uint32_t round, uint32_t LF, uint32_t SF,
                            uint8_t* aL, uint8_t* aS, int32_t* alen,
                            orc_step* trace, int32_t trace_cap, int32_t* n_steps) {
     const orc_params* p = cx->p;
     int32_t len = 0, t = 0;
-    int32_t usedL = 0, usedS = 0;
+    int32_t doneL = 0, doneS = 0;
     while (nl > 0 && ns > 0) {
-        /* ls = length(large) * LF */
+        /* window sizes: the fraction LF of what is left of large, and the
+         * fraction SF times this step's random draw of what is left of
+         * small, both floored and at least one letter */
         int64_t ls = (int64_t)(((uint64_t)nl * LF) >> 16);
         if (ls < 1) ls = 1;
-        /* ss = length(small) * SF * random() */
         uint32_t u = orc_draw(p->seed, cx->target_id, round, 2u + (uint32_t)t);
         int64_t ss = (int64_t)(((uint64_t)ns * SF * u) >> 32);
         if (ss < 1) ss = 1;
-        if (ss > ls) ss = ls;
+        if (!p->full_slide && ss > ls) ss = ls;   /* search mode: a contained shift exists */
 
         int32_t kstar;
         int64_t dbest;
         best_subsequence_alignment(cx, large, (int32_t)ls, small, (int32_t)ss, &kstar, &dbest);
 
         if (trace && t < trace_cap) {
-            trace[t].pL = usedL; trace[t].pS = usedS;
+            trace[t].pL = doneL; trace[t].pS = doneS;
             trace[t].ls = (int32_t)ls; trace[t].ss = (int32_t)ss;
             trace[t].kstar = kstar; trace[t].dscore = (int32_t)dbest;
         }
-        /* delete from large the used-up subsequence and append it to
-         * alignedLarge; small is placed after kstar gaps */
-        int32_t used = kstar + (int32_t)ss;
-        for (int32_t i = 0; i < used; ++i) aL[len + i] = large[i];
-        for (int32_t i = 0; i < kstar; ++i) aS[len + i] = ORC_GAP;
-        /* delete from small the first ss letters and append them */
-        for (int32_t i = 0; i < (int32_t)ss; ++i) aS[len + kstar + i] = small[i];
-        len += used;
-        large += used; nl -= used; usedL += used;
-        small += ss;   ns -= (int32_t)ss; usedS += (int32_t)ss;
+        /* columns of the step, left to right: large letters skipped before a
+         * positive shift face gaps; then every small letter of the window,
+         * facing the large letter at its place or, hanging over an end of the
+         * large window, a gap */
+        for (int32_t i = 0; i < kstar; ++i) { aL[len] = large[i]; aS[len] = ORC_GAP; ++len; }
+        for (int32_t j = 0; j < (int32_t)ss; ++j) {
+            int32_t i = kstar + j;
+            aL[len] = (i >= 0 && i < (int32_t)ls) ? large[i] : ORC_GAP;
+            aS[len] = small[j];
+            ++len;
+        }
+        /* large gives up its window up to the last letter facing small; small
+         * gives up the whole window */
+        int32_t takeL = kstar + (int32_t)ss < (int32_t)ls ? kstar + (int32_t)ss : (int32_t)ls;
+        large += takeL; nl -= takeL; doneL += takeL;
+        small += ss;    ns -= (int32_t)ss; doneS += (int32_t)ss;
         ++t;
     }
-    /* append the remaining letters against dashes */
+    /* whichever sequence is left over faces gaps */
     for (int32_t i = 0; i < nl; ++i) { aL[len] = large[i]; aS[len] = ORC_GAP; ++len; }
     for (int32_t i = 0; i < ns; ++i) { aL[len] = ORC_GAP; aS[len] = small[i]; ++len; }
     *alen = len;
@@ -292,9 +315,9 @@ static int64_t align_round(orc_ctx* cx, const uint8_t* large, int32_t nl, const 
     return score_columns(cx->B, aL, aS, len, p);
 }
 
-/* ALGORITHM AlignSequences(large, small): Rounds independent runs, each with
- * lf = MAX(minFactor, random()) and sf = MAX(minFactor, random()); the first
- * round with the highest score is kept.
+/* ALGORITHM AlignSequences (Fig. 1): Rounds independent runs of Align, each
+ * with two fresh random fractions raised to at least MinFactor (and scaled
+ * by LFactor and SFactor); the first round with the highest score is kept.
  *
  * Roles: the longer of query and target is "large" (the target on a tie).
  * The aligned rows of the best round are returned oriented as (query row,

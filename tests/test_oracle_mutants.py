@@ -23,7 +23,9 @@ MUTANTS = [
     ("transposed_operands", "s += cx->B[large[i] * ORC_NSYM + small[j]];",
      "s += cx->B[small[j] * ORC_NSYM + large[i] + 1 - 1 + 0 * ORC_NSYM] + (large[i] != small[j] ? (large[i] < small[j]) : 0);"),
     ("role_tie", "int target_is_large = tlen >= qlen;", "int target_is_large = tlen > qlen;"),
-    ("consume_no_shift", "int32_t used = kstar + (int32_t)ss;", "int32_t used = (int32_t)ss;"),
+    ("consume_no_shift",
+     "int32_t takeL = kstar + (int32_t)ss < (int32_t)ls ? kstar + (int32_t)ss : (int32_t)ls;",
+     "int32_t takeL = (int32_t)ss < (int32_t)ls ? (int32_t)ss : (int32_t)ls;"),
     ("ls_scale", "int64_t ls = (int64_t)(((uint64_t)nl * LF) >> 16);",
      "int64_t ls = (int64_t)(((uint64_t)nl * LF) >> 17);"),
     ("draw_chunk", "return (uint32_t)((word >> (16 * (d & 3))) & 0xFFFFu);",
@@ -35,7 +37,18 @@ MUTANTS = [
      "if (s >= best) {\n            best = s; best_round = r;"),
     ("step_draw_index", "orc_draw(p->seed, cx->target_id, round, 2u + (uint32_t)t);",
      "orc_draw(p->seed, cx->target_id, round, 1u + (uint32_t)t);"),
-    ("ss_no_clamp", "if (ss > ls) ss = ls;", "if (ss > ls + 1) ss = ls;"),
+    ("ss_no_clamp", "if (!p->full_slide && ss > ls) ss = ls;",
+     "if (!p->full_slide && ss > ls + 1) ss = ls;"),
+    ("full_slide_clamped", "if (!p->full_slide && ss > ls) ss = ls;", "if (ss > ls) ss = ls;"),
+    ("full_start", "int32_t start = cx->p->full_slide ? 0 : ns - 1;",
+     "int32_t start = cx->p->full_slide ? 1 : ns - 1;"),
+    ("full_end", "int32_t end = cx->p->full_slide ? ns + nl - 2 : nl - 1;",
+     "int32_t end = cx->p->full_slide ? ns + nl - 3 : nl - 1;"),
+    ("overhang_takes_window",
+     "int32_t takeL = kstar + (int32_t)ss < (int32_t)ls ? kstar + (int32_t)ss : (int32_t)ls;",
+     "int32_t takeL = kstar + (int32_t)ss < (int32_t)ls ? kstar + (int32_t)ss : (int32_t)ls - (kstar < 0);"),
+    ("hang_front_kept", "aL[len] = (i >= 0 && i < (int32_t)ls) ? large[i] : ORC_GAP;",
+     "aL[len] = (i > 0 && i < (int32_t)ls) ? large[i] : ORC_GAP;"),
     ("tail_dropped", "for (int32_t i = 0; i < ns; ++i) { aL[len] = ORC_GAP; aS[len] = small[i]; ++len; }",
      ""),
 ]

@@ -1,8 +1,9 @@
-"""Pins on the oracle's heuristic (Fig. 1 with Section III.B.3), each checked
-against something other than the oracle itself: hand-worked examples, closed
-forms that hold for any random stream, brute-force re-derivation of every
-step, an independent rescoring of every alignment, and the Smith-Waterman
-upper bound."""
+"""Pins on the oracle's heuristic, in the search mode (Fig. 1 with Section
+III.B.3) and the pairwise mode (Fig. 1 as written), each checked against
+something other than the oracle itself: hand-worked examples, closed forms
+that hold for any random stream, brute-force re-derivation of every step, an
+independent rescoring of every alignment, and the Smith-Waterman upper
+bound."""
 import os
 import re
 
@@ -93,7 +94,7 @@ def test_worked_examples(ex):
     gop, gep, pgp = map(int, ex["penalties"].split())
     lf, mf, sf = map(int, ex["factors"].split())
     p = O.Params(gop=gop, gep=gep, pgp=pgp, lfactor_q16=lf, minfactor_q16=mf, sfactor_q16=sf,
-                 rounds=1, seed=int(ex["seed"]))
+                 rounds=1, seed=int(ex["seed"]), full_slide=ex.get("mode") == "full")
     r = O.align_pair(O.encode(ex["query"]), O.encode(ex["target"]), int(ex["target_id"]), p,
                      trace=True)
     steps = [tuple(map(int, s.split())) for s in ex["steps"].split("|")]
@@ -299,3 +300,234 @@ def test_search_rank_and_planted():
     for i in (0, 5, 77):
         a = O.align_pair(qc, codes[off[i]:off[i + 1]], i, O.Params())
         assert a["score"] == sc[i]
+
+
+# ----------------------------------------------------------------------------
+# Pairwise mode (Fig. 1 as written): every placement with some overlap
+# ----------------------------------------------------------------------------
+def full_params(rng, rounds=None):
+    p = rand_params(rng)
+    p.full_slide = True
+    if rounds is not None:
+        p.rounds = rounds
+    return p
+
+
+def full_slide_reference(q, t, tid, p):
+    """Independent re-derivation of one pair in the pairwise mode, from the
+    wording of Fig. 1 and Section III.B.2.  Per round: draws from numpy's
+    Philox; per step, windows of ls and ss letters (no contained-shift clamp)
+    and every placement i = 0 .. ss + ls - 2 (shift k = i - ss + 1) scored
+    over the letters that face each other, the first best kept; small gives
+    up its whole window, large its letters through the last one facing small;
+    the rows are built column by column and scored by rescore().  Returns
+    (score, round, query row, target row, trace of that round)."""
+    al = O.alphabet()
+    target_large = len(t) >= len(q)
+    L, S = (t, q) if target_large else (q, t)
+    best = None
+    for rnd in range(p.rounds):
+        lf = max(p.minfactor_q16, numpy_draw(p.seed, tid, rnd, 0))
+        sf = max(p.minfactor_q16, numpy_draw(p.seed, tid, rnd, 1))
+        LF, SF = (p.lfactor_q16 * lf) >> 16, (p.sfactor_q16 * sf) >> 16
+        pL = pS = 0
+        rowL, rowS, trace = [], [], []
+        step = 0
+        while pL < len(L) and pS < len(S):
+            nL, nS = len(L) - pL, len(S) - pS
+            u = numpy_draw(p.seed, tid, rnd, 2 + step)
+            ls = max(1, (nL * LF) >> 16)
+            ss = max(1, (nS * SF * u) >> 32)
+            Lw, Sw = L[pL:pL + ls], S[pS:pS + ss]
+            Ds = []
+            for i in range(ss + ls - 1):
+                k = i - ss + 1
+                Ds.append(sum(int(B[Lw[k + j], Sw[j]]) for j in range(ss) if 0 <= k + j < ls))
+            i_best = Ds.index(max(Ds))
+            k = i_best - ss + 1
+            trace.append((pL, pS, ls, ss, k, max(Ds)))
+            for i in range(k):
+                rowL.append(al[Lw[i]])
+                rowS.append("-")
+            for j in range(ss):
+                rowL.append(al[Lw[k + j]] if 0 <= k + j < ls else "-")
+                rowS.append(al[Sw[j]])
+            pL += min(k + ss, ls)
+            pS += ss
+            step += 1
+        rowL += [al[c] for c in L[pL:]] + ["-"] * (len(S) - pS)
+        rowS += ["-"] * (len(L) - pL) + [al[c] for c in S[pS:]]
+        qrow, trow = ("".join(rowS), "".join(rowL)) if target_large else ("".join(rowL), "".join(rowS))
+        score = rescore(qrow, trow, p.gop, p.gep, p.pgp)
+        if best is None or score > best[0]:
+            best = (score, rnd, qrow, trow, trace)
+    return best
+
+
+@pytest.mark.parametrize("case", range(50))
+def test_full_slide_brute_force(case):
+    rng = np.random.default_rng(700 + case)
+    p = full_params(rng)
+    q = rand_seq(rng, int(rng.integers(1, 40)), 24)
+    t = rand_seq(rng, int(rng.integers(1, 60)), 24)
+    tid = int(rng.integers(0, 2**40))
+    r = O.align_pair(q, t, tid, p, trace=True)
+    score, rnd, qrow, trow, trace = full_slide_reference(q, t, tid, p)
+    assert (r["score"], r["round"]) == (score, rnd)
+    assert O.decode(r["qrow"]) == qrow and O.decode(r["trow"]) == trow
+    assert r["trace"] == trace
+
+
+def test_full_slide_differs_from_search():
+    """Some pairs do take shifts outside the contained range (the pins above
+    therefore exercise both kinds of overhang)."""
+    rng = np.random.default_rng(790)
+    neg = over = 0
+    for case in range(60):
+        p = full_params(rng)
+        q = rand_seq(rng, int(rng.integers(2, 40)))
+        t = rand_seq(rng, int(rng.integers(2, 60)))
+        r = O.align_pair(q, t, case, p, trace=True)
+        neg += any(k < 0 for (_, _, ls, ss, k, _) in r["trace"])
+        over += any(k + ss > ls for (_, _, ls, ss, k, _) in r["trace"])
+    assert neg > 5 and over > 5
+
+
+@pytest.mark.parametrize("case", range(40))
+def test_full_slide_identity_prefix(case):
+    """With LF = 1 (LFactor = MinFactor = 1) the large window is all that is
+    left of large, never shorter than the small window, and the identity
+    placement beats every other one term by term (each BLOSUM62 diagonal entry
+    is its column's maximum and positive), so the pair aligns ungapped at
+    offset 0 for any SF, seed and rounds."""
+    rng = np.random.default_rng(800 + case)
+    p = full_params(rng)
+    p.lfactor_q16 = p.minfactor_q16 = 65536
+    n, x = int(rng.integers(1, 100)), int(rng.integers(0, 60))
+    a, tail = rand_seq(rng, n), rand_seq(rng, x)
+    expect = int(sum(B[c, c] for c in a)) - p.pgp * x
+    r = O.align_pair(a, np.concatenate([a, tail]), int(rng.integers(0, 10**6)), p)
+    assert r["score"] == expect
+    assert r["ops"] == ([n << 2 | O.OP_M] + ([x << 2 | O.OP_D] if x else []))
+    r = O.align_pair(np.concatenate([a, tail]), a, int(rng.integers(0, 10**6)), p)
+    assert r["score"] == expect
+    assert r["ops"] == ([n << 2 | O.OP_M] + ([x << 2 | O.OP_I] if x else []))
+
+
+def _ss_sequence(p, tid, rnd, nL0, nS0, LF, SF, take_large):
+    """Window sizes of a round from numpy draws, given how many large letters
+    each step gives up (take_large(ls, ss))."""
+    out = []
+    nL, nS, step = nL0, nS0, 0
+    while nL > 0 and nS > 0:
+        u = numpy_draw(p.seed, tid, rnd, 2 + step)
+        ls = max(1, (nL * LF) >> 16)
+        ss = max(1, (nS * SF * u) >> 32)
+        out.append((ls, ss))
+        nL -= take_large(ls, ss)
+        nS -= ss
+        step += 1
+    return out, nL, nS
+
+
+@pytest.mark.parametrize("case", range(30))
+def test_full_slide_least_overlap(case):
+    """Every letter pair scores -3 (query all A, target all W): the best
+    placement overlaps one letter, and the first such is the one with small's
+    last window letter on large's first, so each step gives up one large
+    letter and ss small letters, ss - 1 of them against gaps in front.
+    Closed form of the score from the window sizes (numpy draws)."""
+    rng = np.random.default_rng(850 + case)
+    p = full_params(rng, rounds=1)
+    tid = int(rng.integers(0, 10**6))
+    nq, nt = int(rng.integers(1, 60)), int(rng.integers(1, 60))
+    q = O.encode("A" * nq)
+    t = O.encode("W" * nt)
+    L, S = (t, q) if nt >= nq else (q, t)
+    lf = max(p.minfactor_q16, numpy_draw(p.seed, tid, 0, 0))
+    sf = max(p.minfactor_q16, numpy_draw(p.seed, tid, 0, 1))
+    LF, SF = (p.lfactor_q16 * lf) >> 16, (p.sfactor_q16 * sf) >> 16
+    steps, nL, nS = _ss_sequence(p, tid, 0, len(L), len(S), LF, SF, lambda ls, ss: 1)
+    expect = -3 * len(steps)
+    for i, (ls, ss) in enumerate(steps):
+        g = ss - 1
+        if g:
+            expect -= p.pgp * g if i == 0 else p.gop + (g - 1) * p.gep
+    expect -= p.pgp * (nL + nS)
+    r = O.align_pair(q, t, tid, p, trace=True)
+    assert r["score"] == expect
+    assert [(ls, ss, k) for (_, _, ls, ss, k, _) in r["trace"]] == [(ls, ss, 1 - ss) for ls, ss in steps]
+
+
+@pytest.mark.parametrize("case", range(30))
+def test_full_slide_most_overlap(case):
+    """Every letter pair scores 11 (both sequences all W): the best placement
+    has the most overlap, min(ss, ls) letters, first reached at shift 0 when
+    the small window fits (ss <= ls) and at shift ls - ss < 0 otherwise, where
+    the first ss - ls small letters hang in front against gaps.  Closed form
+    of the score from the window sizes (numpy draws)."""
+    rng = np.random.default_rng(900 + case)
+    p = full_params(rng, rounds=1)
+    tid = int(rng.integers(0, 10**6))
+    nq, nt = int(rng.integers(1, 60)), int(rng.integers(1, 60))
+    q, t = O.encode("W" * nq), O.encode("W" * nt)
+    L, S = (t, q) if nt >= nq else (q, t)
+    lf = max(p.minfactor_q16, numpy_draw(p.seed, tid, 0, 0))
+    sf = max(p.minfactor_q16, numpy_draw(p.seed, tid, 0, 1))
+    LF, SF = (p.lfactor_q16 * lf) >> 16, (p.sfactor_q16 * sf) >> 16
+    steps, nL, nS = _ss_sequence(p, tid, 0, len(L), len(S), LF, SF, lambda ls, ss: min(ss, ls))
+    expect = 0
+    for i, (ls, ss) in enumerate(steps):
+        expect += 11 * min(ss, ls)
+        g = max(0, ss - ls)
+        if g:
+            expect -= p.pgp * g if i == 0 else p.gop + (g - 1) * p.gep
+    expect -= p.pgp * (nL + nS)
+    r = O.align_pair(q, t, tid, p, trace=True)
+    assert r["score"] == expect
+    assert [k for (_, _, _, _, k, _) in r["trace"]] == [min(0, ls - ss) for ls, ss in steps]
+
+
+@pytest.mark.parametrize("case", range(40))
+def test_full_slide_rescore(case):
+    rng = np.random.default_rng(950 + case)
+    p = full_params(rng)
+    q = rand_seq(rng, int(rng.integers(1, 150)), 24)
+    t = rand_seq(rng, int(rng.integers(1, 200)), 24)
+    r = O.align_pair(q, t, case, p)
+    qr, tr = O.decode(r["qrow"]), O.decode(r["trow"])
+    assert ungap(qr) == O.decode(q) and ungap(tr) == O.decode(t)
+    assert all(not (a == "-" and b == "-") for a, b in zip(qr, tr))
+    assert rescore(qr, tr, p.gop, p.gep, p.pgp) == r["score"]
+
+
+@pytest.mark.parametrize("case", range(30))
+def test_full_slide_below_smith_waterman(case):
+    rng = np.random.default_rng(1000 + case)
+    p = full_params(rng)
+    q = rand_seq(rng, int(rng.integers(1, 120)))
+    if case % 2:
+        t = q.copy()
+        t[rng.random(len(t)) < 0.3] = rng.integers(0, 20)
+        t = np.concatenate([rand_seq(rng, 4), t, rand_seq(rng, 9)])
+    else:
+        t = rand_seq(rng, int(rng.integers(1, 160)))
+    r = O.align_pair(q, t, case, p)
+    assert r["score"] <= O.sw_score(q, t, p.gop, p.gep)
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_full_slide_rounds_monotone(case):
+    """Up to the Rounds = 20 of the paper's alignment tests (Section V)."""
+    rng = np.random.default_rng(1050 + case)
+    p = full_params(rng)
+    q, t = rand_seq(rng, int(rng.integers(5, 80))), rand_seq(rng, int(rng.integers(5, 120)))
+    prev = None
+    for R in (1, 2, 5, 10, 20):
+        p.rounds = R
+        r = O.align_pair(q, t, case, p)
+        if prev is not None:
+            assert r["score"] >= prev[0]
+            if r["score"] == prev[0]:
+                assert r["round"] == prev[1]
+        prev = (r["score"], r["round"])
