@@ -247,6 +247,48 @@ int hs_search_threshold(const hs_db* db, const char* query, int32_t qlen, const 
                         int64_t* ops_used);
 
 /* ---------------------------------------------------------------------------
+ * Pairwise alignment mode.  Fig. 1 as printed: getBestSubsequenceAlignment
+ * slides the small window across the large one from one end to the other
+ * (start = 0, end = length(small) + length(large) - 2: every placement with
+ * at least one overlapping letter, Section III.B.2), and AlignSequences keeps
+ * the best of params->rounds rounds (Section III.B.1; the paper's alignment
+ * tests used Rounds = 20, Section V).  The database search uses the search
+ * mode of Section III.B.3 instead (contained shifts only).
+ *
+ * A placement at shift k gives up all ss letters of the small window -- those
+ * hanging over an end of the large window are set against gaps -- and the
+ * large window's letters through the last one facing small, min(k + ss, ls);
+ * the rest of the large window goes back to large.  Ties go to the first
+ * placement (most negative shift) and the first round.  The score is SCORE
+ * of the aligned rows, with the penalties of Section III.B.1.
+ * ------------------------------------------------------------------------- */
+#define HS_MAX_ALIGN 5600           /* longest sequence of a pairwise alignment */
+#define HS_MAX_ALIGN_PAIRS 1000000  /* most pairs in one call */
+
+/* Aligns n pairs (query i = qres[qoff[i] .. qoff[i+1]), target i =
+ * tres[toff[i] .. toff[i+1]), host ASCII, each 1..HS_MAX_ALIGN letters).
+ * Pair i's random draws are keyed by i in place of a target index.
+ *   scores[n]       host: each pair's score
+ *   rounds[n]       host: the round that scored best (may be NULL)
+ *   ops, ops_cap    host buffer for the run-length ops of every pair, back
+ *                   to back, oriented (query, target) as in hs_search;
+ *                   HS_ENOSPC when too small (*ops_used = size needed)
+ *   ops_off[n + 1]  host: pair i's ops are ops[ops_off[i] .. ops_off[i+1])
+ * Returns when the results are on the host; device memory is allocated per
+ * call.  Errors: HS_EINVAL (arguments, residues), HS_ENOSPC, HS_ENOMEM,
+ * HS_EDEVICE. */
+int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char* tres,
+                   const int64_t* toff, const hs_params* params, void* stream, int32_t* scores,
+                   int32_t* rounds, uint32_t* ops, int64_t ops_cap, int64_t* ops_off,
+                   int64_t* ops_used);
+
+/* One pair: hs_align_batch with n = 1; *n_ops receives the op count (also on
+ * HS_ENOSPC). */
+int hs_align(const char* query, int32_t qlen, const char* target, int32_t tlen,
+             const hs_params* params, void* stream, int32_t* score, int32_t* round, uint32_t* ops,
+             int64_t ops_cap, int64_t* n_ops);
+
+/* ---------------------------------------------------------------------------
  * Smith-Waterman baseline.  The exact optimum that the paper measures its
  * heuristic against (Sections I and IV compare the two for speed and
  * sensitivity): Smith & Waterman (1981) local alignment with Gotoh's (1982)

@@ -3,8 +3,10 @@ Nag & Karforma (arXiv 1508.06561): one query, or a batch, against a protein
 database, ranked, with alignments for the best hits.  The work runs in the
 HIP kernels of libhs.so behind the C ABI of include/hs.h; this package is the
 Python binding of that ABI."""
-from .hs import (ALPHABET, Batch, HSError, Database, DeviceSearch, Params, Result, Server,
-                 builtin_matrix, encode, lib, params_default, search_batch)
+from .hs import (ALPHABET, Alignment, Batch, HSError, Database, DeviceSearch, Params, Result,
+                 Server, align, align_batch, builtin_matrix, encode, lib, params_default,
+                 search_batch)
 
-__all__ = ["ALPHABET", "Batch", "HSError", "Database", "DeviceSearch", "Params", "Result",
-           "Server", "builtin_matrix", "encode", "lib", "params_default", "search_batch"]
+__all__ = ["ALPHABET", "Alignment", "Batch", "HSError", "Database", "DeviceSearch", "Params",
+           "Result", "Server", "align", "align_batch", "builtin_matrix", "encode", "lib",
+           "params_default", "search_batch"]

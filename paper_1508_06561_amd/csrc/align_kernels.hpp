@@ -1,0 +1,216 @@
+// align_kernels.hpp -- the pairwise mode of Fig. 1: the small window slides
+// across the large one from end to end (placements i = 0 .. ss + ls - 2,
+// shift k = i - ss + 1, at least one letter of overlap), and the best of
+// Rounds rounds is kept (the paper's alignment tests ran Rounds = 20).
+//
+// A placement gives up all ss letters of the small window -- those hanging
+// over an end of the large window face gaps -- and the large window's
+// letters through the last one facing small, min(k + ss, ls); the rest of
+// the large window goes back to large (Section III.B.2).
+//
+// One workgroup per (pair, round) scores that round: its threads share each
+// step's placements, summing the letters that face each other from the
+// two sequences staged in LDS.  One workgroup per pair then replays the
+// pair's best round and writes its run-length ops.
+#pragma once
+
+#include "device_common.hpp"
+#include "traceback_kernels.hpp"   // run-length op codes
+
+namespace hs {
+
+constexpr int kAlThreads = 256;
+constexpr int kAlWaves = kAlThreads / kLanes;
+constexpr int kAlMaxLen = 5600;    // longest sequence of the pairwise mode
+
+// One pair of a pairwise batch: query codes at qoff, target codes at toff.
+struct AlignPair {
+    int64_t qoff, toff;
+    int32_t qlen, tlen;
+    int64_t ops_off;     // first op of the pair's output
+};
+
+struct AlignLds {
+    int8_t mat[kNsym * kNsym];
+    uint64_t wbest[kAlWaves];
+    uint8_t L[kAlMaxLen], S[kAlMaxLen];
+};
+
+// Largest 64-bit key over the wavefront (all lanes active), by two 32-bit
+// maxima through DPP-free shuffles.
+__device__ __forceinline__ uint64_t al_wave_max(uint64_t key) {
+    for (int o = kLanes / 2; o > 0; o >>= 1) {
+        const uint64_t y = __shfl_xor(key, o, kLanes);
+        key = y > key ? y : key;
+    }
+    return key;
+}
+
+// Random draws of one (pair, round), one Philox block at a time.
+struct AlDraws {
+    int32_t blk;
+    uint64_t w[4];
+    __device__ __forceinline__ uint32_t get(uint64_t seed, int32_t id, int32_t round, uint32_t d) {
+        const int32_t b = (int32_t)(d >> 4);
+        if (b != blk) {
+            philox_block(seed, (uint64_t)id, (uint32_t)round, (uint32_t)b, w);
+            blk = b;
+        }
+        const uint32_t wi = (d >> 2) & 3;
+        const uint64_t x = wi == 0 ? w[0] : wi == 1 ? w[1] : wi == 2 ? w[2] : w[3];
+        return (uint32_t)(x >> (16 * (d & 3))) & 0xFFFFu;
+    }
+};
+
+// Appends n columns of op to the run-length ops (one thread).
+__device__ __forceinline__ void al_emit(uint32_t* ops, int32_t& n_ops, uint32_t op, int32_t n) {
+    if (n <= 0) return;
+    if (n_ops > 0 && (ops[n_ops - 1] & 3u) == op) ops[n_ops - 1] += (uint32_t)n << 2;
+    else ops[n_ops++] = ((uint32_t)n << 2) | op;
+}
+
+// One round of pair `id` by the whole workgroup: the round's score (SCORE of
+// its aligned rows, streamed step by step) and, with kEmit, its ops written
+// by thread 0.  L / S (lengths nl >= ns) are in LDS; tl: the target is L.
+template <bool kEmit>
+__device__ int32_t al_round(AlignLds& A, int32_t nl, int32_t ns, bool tl, const KParams& kp,
+                            int32_t id, int32_t round, uint32_t* ops, int32_t* n_ops_out) {
+    const int32_t tid = threadIdx.x, lane = tid & (kLanes - 1), wave = tid / kLanes;
+    AlDraws dr;
+    dr.blk = -1;
+    const uint32_t LF = round_factor(kp.lfactor, kp.minfactor, dr.get(kp.seed, id, round, 0));
+    const uint32_t SF = round_factor(kp.sfactor, kp.minfactor, dr.get(kp.seed, id, round, 1));
+    // ops: a large letter against a gap, a small letter against a gap
+    const uint32_t opL = tl ? kOpD : kOpI, opS = tl ? kOpI : kOpD;
+    int32_t n_ops = 0;
+    int32_t pL = 0, pS = 0, score = 0;
+    bool open_l = false;     // the last column was a gap of the large row, inside it
+    for (int32_t t = 0; pL < nl && pS < ns; ++t) {
+        const int32_t ls = window_large(nl - pL, LF);
+        int32_t ss = (int32_t)(((uint64_t)(ns - pS) * SF * dr.get(kp.seed, id, round, 2u + (uint32_t)t)) >> 32);
+        ss = ss < 1 ? 1 : ss;
+        // every placement i: shift k = i - ss + 1; the letters facing each
+        // other are small j in [max(0, -k), min(ss, ls - k))
+        const int32_t np = ls + ss - 1;
+        uint64_t best = 0;
+        for (int32_t i = tid; i < np; i += kAlThreads) {
+            const int32_t k = i - ss + 1;
+            const int32_t j0 = k < 0 ? -k : 0;
+            const int32_t j1 = ss < ls - k ? ss : ls - k;
+            const uint8_t* Lk = A.L + pL + k;
+            const uint8_t* Sj = A.S + pS;
+            int32_t D = 0;
+            for (int32_t j = j0; j < j1; ++j) D += A.mat[Lk[j] * kNsym + Sj[j]];
+            const uint64_t key = shift_key(D, i);
+            best = key > best ? key : best;
+        }
+        best = al_wave_max(best);
+        if (lane == 0) A.wbest[wave] = best;
+        __syncthreads();
+        uint64_t b = A.wbest[0];
+        for (int w = 1; w < kAlWaves; ++w) b = A.wbest[w] > b ? A.wbest[w] : b;
+        __syncthreads();          // wbest is rewritten by the next step
+        const int32_t k = key_shift(b) - ss + 1;
+        const int32_t D = key_score(b);
+        // gaps in front of the placement: large letters before a positive
+        // shift (small row; before small's first letter when pS == 0), or
+        // small letters before the large window (large row; before large's
+        // first letter when pL == 0, else continuing an inner run left open
+        // by the previous step's overhang)
+        if (k > 0) {
+            score -= pS == 0 ? kp.pgp * k : kp.gop + (k - 1) * kp.gep;
+            if (kEmit && tid == 0) al_emit(ops, n_ops, opL, k);
+        } else if (k < 0) {
+            const int32_t g = -k;
+            score -= pL == 0 ? kp.pgp * g : open_l ? kp.gep * g : kp.gop + (g - 1) * kp.gep;
+            if (kEmit && tid == 0) al_emit(ops, n_ops, opS, g);
+        }
+        score += D;
+        const int32_t face = (ss < ls - k ? ss : ls - k) - (k < 0 ? -k : 0);
+        if (kEmit && tid == 0) al_emit(ops, n_ops, kOpM, face);
+        const int32_t take = k + ss < ls ? k + ss : ls;
+        const int32_t hang = k + ss - ls;         // small letters past the window's end
+        pL += take;
+        pS += ss;
+        open_l = false;
+        if (hang > 0) {
+            // after large's last letter if large is used up, else an inner run
+            if (pL == nl) {
+                score -= kp.pgp * hang;
+            } else {
+                score -= kp.gop + (hang - 1) * kp.gep;
+                open_l = true;
+            }
+            if (kEmit && tid == 0) al_emit(ops, n_ops, opS, hang);
+        }
+    }
+    // what is left of either sequence faces gaps after the other's last letter
+    score -= kp.pgp * ((nl - pL) + (ns - pS));
+    if (kEmit && tid == 0) {
+        al_emit(ops, n_ops, opL, nl - pL);
+        al_emit(ops, n_ops, opS, ns - pS);
+        *n_ops_out = n_ops;
+    }
+    return score;
+}
+
+// Stages pair p in LDS as (large, small); returns (nl, ns, tl).
+__device__ __forceinline__ void al_stage(AlignLds& A, const AlignPair& P, const uint8_t* codes,
+                                         const KMatrix& km, int32_t& nl, int32_t& ns, bool& tl) {
+    tl = P.tlen >= P.qlen;
+    nl = tl ? P.tlen : P.qlen;
+    ns = tl ? P.qlen : P.tlen;
+    const uint8_t* src_l = codes + (tl ? P.toff : P.qoff);
+    const uint8_t* src_s = codes + (tl ? P.qoff : P.toff);
+    for (int32_t i = threadIdx.x; i < nl; i += kAlThreads) A.L[i] = src_l[i];
+    for (int32_t i = threadIdx.x; i < ns; i += kAlThreads) A.S[i] = src_s[i];
+    for (int32_t i = threadIdx.x; i < kNsym * kNsym; i += kAlThreads) A.mat[i] = km.m[i];
+    __syncthreads();
+}
+
+// Round blockIdx.x % rounds of pair blockIdx.x / rounds: its score to
+// round_scores[pair * rounds + round].
+__global__ __launch_bounds__(kAlThreads) void k_align_rounds(const AlignPair* __restrict__ pairs,
+                                                             const uint8_t* __restrict__ codes,
+                                                             KParams kp, KMatrix km,
+                                                             int32_t* __restrict__ round_scores) {
+    __shared__ AlignLds A;
+    const int32_t pair = blockIdx.x / kp.rounds, round = blockIdx.x % kp.rounds;
+    int32_t nl, ns;
+    bool tl;
+    al_stage(A, pairs[pair], codes, km, nl, ns, tl);
+    const int32_t s = al_round<false>(A, nl, ns, tl, kp, pair, round, nullptr, nullptr);
+    if (threadIdx.x == 0) round_scores[(int64_t)pair * kp.rounds + round] = s;
+}
+
+// Pair blockIdx.x: its best round (the first with the highest score),
+// replayed into ops at ops + pairs[p].ops_off; score, round and op count out.
+__global__ __launch_bounds__(kAlThreads) void k_align_replay(const AlignPair* __restrict__ pairs,
+                                                             const uint8_t* __restrict__ codes,
+                                                             KParams kp, KMatrix km,
+                                                             const int32_t* __restrict__ round_scores,
+                                                             int32_t* __restrict__ scores,
+                                                             int32_t* __restrict__ rounds,
+                                                             int32_t* __restrict__ n_ops,
+                                                             uint32_t* __restrict__ ops) {
+    __shared__ AlignLds A;
+    const int32_t pair = blockIdx.x;
+    const int32_t* rs = round_scores + (int64_t)pair * kp.rounds;
+    int32_t best = rs[0], best_r = 0;
+    for (int32_t r = 1; r < kp.rounds; ++r)
+        if (rs[r] > best) {
+            best = rs[r];
+            best_r = r;
+        }
+    int32_t nl, ns;
+    bool tl;
+    const AlignPair P = pairs[pair];
+    al_stage(A, P, codes, km, nl, ns, tl);
+    const int32_t s = al_round<true>(A, nl, ns, tl, kp, pair, best_r, ops + P.ops_off, n_ops + pair);
+    if (threadIdx.x == 0) {
+        scores[pair] = s;        // equal to best: the replay is the same round
+        rounds[pair] = best_r;
+    }
+}
+
+}  // namespace hs

@@ -92,8 +92,8 @@ __device__ __forceinline__ void philox_block(uint64_t seed, uint64_t target, uin
     philox4x64_10(w[0], w[1], w[2], w[3], seed, 0);
 }
 
-// Per-round factors (Fig. 1, AlignSequences): lf = MAX(minFactor, random())
-// scaled by LFactor, likewise sf by SFactor (Q16).
+// Per-round factor (Fig. 1, ALGORITHM AlignSequences): a random fraction
+// raised to at least MinFactor, scaled by LFactor (or SFactor), Q16.
 __device__ __forceinline__ uint32_t round_factor(uint32_t factor, uint32_t minf, uint32_t u) {
     return (uint32_t)(((uint64_t)factor * (u < minf ? minf : u)) >> 16);
 }

@@ -18,11 +18,13 @@
 #include "traceback_kernels.hpp"
 #include "sw_kernels.hpp"
 #include "threshold_kernels.hpp"
+#include "align_kernels.hpp"
 
 using namespace hs;
 
 static_assert(sizeof(hs_hit) == sizeof(DevHit), "hit layout");
 static_assert(sizeof(hs_aln) == sizeof(DevAln), "alignment layout");
+static_assert(kAlMaxLen == HS_MAX_ALIGN, "pairwise length limit");
 
 namespace {
 
@@ -1358,6 +1360,107 @@ int hs_search_threshold(const hs_db* db, const char* query, int32_t qlen, const 
         *n_alns = n_a;
     }
     return HS_OK;
+}
+
+int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char* tres,
+                   const int64_t* toff, const hs_params* params, void* stream, int32_t* scores,
+                   int32_t* rounds, uint32_t* ops, int64_t ops_cap, int64_t* ops_off,
+                   int64_t* ops_used) {
+    if (n < 1 || n > HS_MAX_ALIGN_PAIRS) return fail(HS_EINVAL, "n must lie in [1, HS_MAX_ALIGN_PAIRS]");
+    if (!qres || !qoff || !tres || !toff || !scores || !ops_off || !ops_used)
+        return fail(HS_EINVAL, "NULL pointer");
+    int rc = check_params(params);
+    if (rc) return rc;
+    if ((int64_t)n * params->rounds > 0x7FFFFFFF) return fail(HS_EINVAL, "n * rounds too large");
+    int64_t nq = 0, nt = 0, nops = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t a = qoff[i + 1] - qoff[i], b = toff[i + 1] - toff[i];
+        if (a < 1 || a > HS_MAX_ALIGN || b < 1 || b > HS_MAX_ALIGN)
+            return fail(HS_EINVAL, "pair " + std::to_string(i) + ": lengths must lie in [1, HS_MAX_ALIGN]");
+        nq += a;
+        nt += b;
+        nops += a + b;          // runs never outnumber columns
+    }
+    std::vector<uint8_t> codes((size_t)(nq + nt));
+    std::vector<AlignPair> pairs((size_t)n);
+    int64_t cq = 0, ct = nq, co = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        AlignPair& P = pairs[(size_t)i];
+        P.qlen = (int32_t)(qoff[i + 1] - qoff[i]);
+        P.tlen = (int32_t)(toff[i + 1] - toff[i]);
+        if ((rc = hs_encode(qres + qoff[i], P.qlen, codes.data() + cq))) return rc;
+        if ((rc = hs_encode(tres + toff[i], P.tlen, codes.data() + ct))) return rc;
+        P.qoff = cq;
+        P.toff = ct;
+        P.ops_off = co;
+        cq += P.qlen;
+        ct += P.tlen;
+        co += P.qlen + P.tlen;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const size_t o_codes = 0, o_pairs = align_up(codes.size()),
+                 o_rs = o_pairs + align_up(sizeof(AlignPair) * (size_t)n),
+                 o_sc = o_rs + align_up(sizeof(int32_t) * (size_t)n * params->rounds),
+                 o_rd = o_sc + align_up(sizeof(int32_t) * (size_t)n),
+                 o_no = o_rd + align_up(sizeof(int32_t) * (size_t)n),
+                 o_ops = o_no + align_up(sizeof(int32_t) * (size_t)n),
+                 total = o_ops + align_up(sizeof(uint32_t) * (size_t)nops);
+    char* d = nullptr;
+    if (hipMallocAsync((void**)&d, total, st) != hipSuccess)
+        return fail(HS_ENOMEM, "device allocation failed");
+    std::vector<int32_t> h_sc((size_t)n), h_rd((size_t)n), h_no((size_t)n);
+    std::vector<uint32_t> h_ops((size_t)nops);
+    const KParams kp = kparams(params);
+    const KMatrix km = kmatrix(params);
+    rc = HS_OK;
+    if (hipMemcpyAsync(d + o_codes, codes.data(), codes.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d + o_pairs, pairs.data(), sizeof(AlignPair) * (size_t)n, hipMemcpyHostToDevice,
+                       st) != hipSuccess)
+        rc = fail(HS_EDEVICE, "pair upload failed");
+    if (!rc) {
+        hipLaunchKernelGGL(k_align_rounds, dim3((unsigned)((int64_t)n * params->rounds)), dim3(kAlThreads),
+                           0, st, (const AlignPair*)(d + o_pairs), (const uint8_t*)(d + o_codes), kp, km,
+                           (int32_t*)(d + o_rs));
+        hipLaunchKernelGGL(k_align_replay, dim3((unsigned)n), dim3(kAlThreads), 0, st,
+                           (const AlignPair*)(d + o_pairs), (const uint8_t*)(d + o_codes), kp, km,
+                           (const int32_t*)(d + o_rs), (int32_t*)(d + o_sc), (int32_t*)(d + o_rd),
+                           (int32_t*)(d + o_no), (uint32_t*)(d + o_ops));
+        if (hipGetLastError() != hipSuccess) rc = fail(HS_EDEVICE, "pairwise kernels failed to launch");
+    }
+    if (!rc && (hipMemcpyAsync(h_sc.data(), d + o_sc, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st) ||
+                hipMemcpyAsync(h_rd.data(), d + o_rd, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st) ||
+                hipMemcpyAsync(h_no.data(), d + o_no, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st) ||
+                hipMemcpyAsync(h_ops.data(), d + o_ops, sizeof(uint32_t) * (size_t)nops,
+                               hipMemcpyDeviceToHost, st) ||
+                hipStreamSynchronize(st)))
+        rc = fail(HS_EDEVICE, "pairwise alignment failed on the device");
+    (void)hipFreeAsync(d, st);
+    if (rc) return rc;
+    int64_t need = 0;
+    for (int32_t i = 0; i < n; ++i) need += h_no[(size_t)i];
+    *ops_used = need;
+    if (need > ops_cap) return fail(HS_ENOSPC, "ops buffer too small");
+    int64_t off = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        ops_off[i] = off;
+        std::memcpy(ops + off, h_ops.data() + pairs[(size_t)i].ops_off, sizeof(uint32_t) * h_no[(size_t)i]);
+        off += h_no[(size_t)i];
+    }
+    ops_off[n] = off;
+    std::memcpy(scores, h_sc.data(), sizeof(int32_t) * (size_t)n);
+    if (rounds) std::memcpy(rounds, h_rd.data(), sizeof(int32_t) * (size_t)n);
+    return HS_OK;
+}
+
+int hs_align(const char* query, int32_t qlen, const char* target, int32_t tlen,
+             const hs_params* params, void* stream, int32_t* score, int32_t* round, uint32_t* ops,
+             int64_t ops_cap, int64_t* n_ops) {
+    if (!score || !n_ops) return fail(HS_EINVAL, "NULL pointer");
+    const int64_t qo[2] = {0, qlen}, to[2] = {0, tlen};
+    int64_t off[2] = {0, 0};
+    if (qlen < 1 || tlen < 1) return fail(HS_EINVAL, "lengths must lie in [1, HS_MAX_ALIGN]");
+    return hs_align_batch(1, query, qo, target, to, params, stream, score, round, ops, ops_cap, off,
+                          n_ops);
 }
 
 int64_t hs_sw_workspace_bytes(const hs_db* db) {

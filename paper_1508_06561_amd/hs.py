@@ -20,6 +20,7 @@ MAX_K = 4096
 MAX_QUERY = 5600
 MAX_BATCH = 4096
 MAX_SERVER_WORKERS = 8
+MAX_ALIGN = 5600
 ALPHABET = "ARNDCQEGHILKMFPSTWYVBZX*"
 
 
@@ -121,6 +122,10 @@ def lib():
         L.hs_search_batch.argtypes = [vp, i32, vp, P(ctypes.c_int64), P(_CParams), i32, i32, i32,
                                       vp, vp, pi32, vp, pi32, vp, i64, P(ctypes.c_int64)]
         L.hs_params_check.argtypes = [P(_CParams)]
+        L.hs_align_batch.argtypes = [i32, vp, P(ctypes.c_int64), vp, P(ctypes.c_int64), P(_CParams),
+                                     vp, pi32, pi32, vp, i64, P(ctypes.c_int64), P(ctypes.c_int64)]
+        L.hs_align.argtypes = [ctypes.c_char_p, i32, ctypes.c_char_p, i32, P(_CParams), vp, pi32,
+                               pi32, vp, i64, P(ctypes.c_int64)]
         L.hs_server_create.argtypes = [vp, i32, i32, i64, i32, i32, P(vp)]
         L.hs_server_create_workers.argtypes = [vp, i32, i32, i64, i32, i32, i32, P(vp)]
         L.hs_server_free.argtypes = [vp]
@@ -539,6 +544,51 @@ def search_batch(db, queries, params=None, k=50, n_aln=50, stream=None):
                                  alns.ctypes.data, n_alns.ctypes.data_as(P), ops.ctypes.data, cap,
                                  ctypes.byref(used)))
     return _split_batch(nq, k, n_aln, hits, n_hits, alns, n_alns, ops)
+
+
+@dataclasses.dataclass
+class Alignment:
+    score: int
+    round: int
+    ops: np.ndarray           # uint32 run-length ops, oriented (query, target)
+
+
+def align_batch(pairs, params=None, stream=None):
+    """hs_align_batch: the pairwise mode of Fig. 1 (every overlapping
+    placement, best of params.rounds rounds) for a list of (query, target)
+    pairs; pair i's draws are keyed by i.  Returns a list of Alignment."""
+    n = len(pairs)
+    qres, qoff = _pack_queries([q for q, _ in pairs])
+    tres, toff = _pack_queries([t for _, t in pairs])
+    p = (params or Params()).c()
+    scores = np.zeros(n, dtype=np.int32)
+    rounds = np.zeros(n, dtype=np.int32)
+    cap = max(1, int(np.diff(qoff).sum() + np.diff(toff).sum()))
+    ops = np.zeros(cap, dtype=np.uint32)
+    ops_off = np.zeros(n + 1, dtype=np.int64)
+    used = ctypes.c_int64()
+    P = ctypes.POINTER(ctypes.c_int32)
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    _check(lib().hs_align_batch(n, qres.ctypes.data_as(ctypes.c_void_p), qoff.ctypes.data_as(P64),
+                                tres.ctypes.data_as(ctypes.c_void_p), toff.ctypes.data_as(P64),
+                                ctypes.byref(p), _stream(stream), scores.ctypes.data_as(P),
+                                rounds.ctypes.data_as(P), ops.ctypes.data, cap,
+                                ops_off.ctypes.data_as(P64), ctypes.byref(used)))
+    return [Alignment(int(scores[i]), int(rounds[i]), ops[ops_off[i]:ops_off[i + 1]].copy())
+            for i in range(n)]
+
+
+def align(query, target, params=None, stream=None):
+    """hs_align: one pair in the pairwise mode (draws keyed by index 0)."""
+    q = query.encode() if isinstance(query, str) else bytes(query)
+    t = target.encode() if isinstance(target, str) else bytes(target)
+    p = (params or Params()).c()
+    cap = max(1, len(q) + len(t))
+    ops = np.zeros(cap, dtype=np.uint32)
+    sc, rd, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().hs_align(q, len(q), t, len(t), ctypes.byref(p), _stream(stream), ctypes.byref(sc),
+                          ctypes.byref(rd), ops.ctypes.data, cap, ctypes.byref(n)))
+    return Alignment(sc.value, rd.value, ops[:n.value].copy())
 
 
 class Server:
