@@ -125,6 +125,19 @@ int hs_encode(const char* ascii, int64_t n, uint8_t* codes);
 int hs_db_load(const char* residues, const int64_t* offsets, int64_t n_targets,
                void* stream, hs_db** out);
 
+/* Letter image that the one-query scoring kernel reads (Section III.B.5's
+ * database, stored two ways): bits = 8, the default, one alphabet code per
+ * byte; bits = 5, a dense 5-bit image (5/8 of the bytes), built on the device
+ * on first request and kept until hs_db_free.  Results are identical either
+ * way; only speed and memory traffic differ, so that the two layouts can be
+ * measured against each other.  The 5-bit image serves queries whose four
+ * profile copies fit in LDS beside a full workgroup (up to about 1,100
+ * letters); longer queries, batches, alignments and Smith-Waterman read the
+ * byte image.
+ * Not thread-safe against searches running on the same database.
+ * Errors: HS_EINVAL (bits not 8 or 5), HS_ENOMEM, HS_EDEVICE. */
+int hs_db_set_letters(hs_db* db, int32_t bits, void* stream);
+
 /* Releases a database and its device memory.  NULL is allowed. */
 int hs_db_free(hs_db* db);
 

@@ -105,6 +105,8 @@ struct hs_db {
     int64_t n_targets = 0;
     int64_t n_residues = 0;
     uint8_t* d_letters = nullptr;   // codes, index order, kLetterPad readable bytes after
+    uint8_t* d_letters5 = nullptr;  // the same letters at 5 bits each (built on request)
+    int32_t letter_bits = 8;        // image the one-query scoring kernel reads
     int64_t* d_offsets = nullptr;
     int32_t* d_lens = nullptr;
     int32_t* d_order = nullptr;     // longest first
@@ -137,11 +139,30 @@ __global__ __launch_bounds__(256) void k_encode(uint8_t* __restrict__ letters, i
     }
 }
 
+// 5-bit image: letter i at bits 5i .. 5i + 4 of a little-endian stream of
+// dwords; thread w writes dword w.  Letters past the last one read as the
+// zero-row code, like the byte image's padding.
+__global__ __launch_bounds__(256) void k_pack5(const uint8_t* __restrict__ letters, int64_t n,
+                                               int64_t n_words, uint32_t* __restrict__ out) {
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n_words;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b0 = 32 * w;                 // first bit of the dword
+        uint32_t v = 0;
+        for (int64_t i = b0 / 5; i * 5 < b0 + 32; ++i) {
+            const uint32_t c = i < n ? letters[i] : (uint32_t)kZeroRow;
+            const int64_t b = 5 * i;
+            v |= b >= b0 ? c << (uint32_t)(b - b0) : c >> (uint32_t)(b0 - b);
+        }
+        out[w] = v;
+    }
+}
+
 namespace {
 
 void free_db(hs_db* db) {
     if (!db) return;
     (void)hipFree(db->d_letters);
+    (void)hipFree(db->d_letters5);
     (void)hipFree(db->d_offsets);
     (void)hipFree(db->d_lens);
     (void)hipFree(db->d_order);
@@ -426,12 +447,12 @@ int prefer_ilp(const void* fn_default, const void* fn_ilp, int threads, size_t l
 // pairs of targets up to 384 letters, one pair of a target over 12,288.
 constexpr int64_t kLettersInFlight = 64 * 384;
 
-template <int kCopies, bool kCount, bool kIlp>
+template <int kCopies, bool kCount, bool kIlp, int kBits = 8>
 int launch_sched(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParams& kp,
                  const KMatrix& km, int32_t bias, hipStream_t st, const QueryWs& w,
                  int32_t* d_scores, int32_t* d_rounds, uint64_t* d_cells, int32_t* d_max,
                  const QueryLayout& L) {
-    const void* fn = (const void*)k_score_sched<kCopies, kCount, kIlp>;
+    const void* fn = (const void*)k_score_sched<kCopies, kCount, kIlp, kBits>;
     const int threads = L.waves * kLanes;
     int rc = set_lds_limit(fn, L.lds);
     if (rc) return rc;
@@ -452,8 +473,9 @@ int launch_sched(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParam
         std::min<int64_t>(kLanes, by_len), std::max<int64_t>(1, (db->n_targets + slots - 1) / slots));
     const int64_t want = (db->n_targets + (int64_t)cap * L.waves - 1) / ((int64_t)cap * L.waves);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * device_cus(), want));
-    hipLaunchKernelGGL((k_score_sched<kCopies, kCount, kIlp>), dim3(grid), dim3(threads), L.lds, st,
-                       (const PairRec*)db->d_recs, (int32_t)db->n_queue, db->d_letters, d_q, qlen,
+    hipLaunchKernelGGL((k_score_sched<kCopies, kCount, kIlp, kBits>), dim3(grid), dim3(threads), L.lds, st,
+                       (const PairRec*)db->d_recs, (int32_t)db->n_queue,
+                       kBits == 5 ? db->d_letters5 : db->d_letters, d_q, qlen,
                        kp, km, bias, cap, (uint32_t)cap, (const uint64_t*)w.draws, w.queue, d_scores, d_rounds,
                        (unsigned long long*)d_cells, d_max);
     HIP_TRY(hipGetLastError());
@@ -486,6 +508,19 @@ int launch_score(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs_par
     if (rc) return rc;
 #define HS_SCHED(C, K, I, cells) \
     launch_sched<C, K, I>(db, d_q, qlen, kp, km, bias, st, w, d_scores, d_rounds, cells, d_max, L)
+    // the 5-bit image serves launches with four profile copies; the one-copy
+    // launch of the longest queries reads the byte image
+    if (db->letter_bits == 5 && four) {
+        if (d_cells)
+            return ilp ? launch_sched<4, true, true, 5>(db, d_q, qlen, kp, km, bias, st, w, d_scores,
+                                                        d_rounds, d_cells, d_max, L)
+                       : launch_sched<4, true, false, 5>(db, d_q, qlen, kp, km, bias, st, w, d_scores,
+                                                         d_rounds, d_cells, d_max, L);
+        return ilp ? launch_sched<4, false, true, 5>(db, d_q, qlen, kp, km, bias, st, w, d_scores,
+                                                     d_rounds, nullptr, d_max, L)
+                   : launch_sched<4, false, false, 5>(db, d_q, qlen, kp, km, bias, st, w, d_scores,
+                                                      d_rounds, nullptr, d_max, L);
+    }
     if (d_cells) {
         if (four) return ilp ? HS_SCHED(4, true, true, d_cells) : HS_SCHED(4, true, false, d_cells);
         return ilp ? HS_SCHED(1, true, true, d_cells) : HS_SCHED(1, true, false, d_cells);
@@ -1129,6 +1164,27 @@ int hs_db_load(const char* residues, const int64_t* offsets, int64_t n_targets, 
     if (err) return cleanup(fail(HS_EINVAL, "database holds a residue outside the alphabet"));
     *out = db;
     return cleanup(HS_OK);
+}
+
+int hs_db_set_letters(hs_db* db, int32_t bits, void* stream) {
+    if (!db) return fail(HS_EINVAL, "db is NULL");
+    if (bits != 8 && bits != 5) return fail(HS_EINVAL, "bits must be 8 or 5");
+    if (bits == 5 && !db->d_letters5) {
+        const int64_t n = db->n_residues;
+        const int64_t n_words = (5 * (n + kLetterPad) + 31) / 32 + 4;
+        uint32_t* d = nullptr;
+        if (int rc = dev_alloc(&d, (size_t)n_words, &db->device_bytes)) return rc;
+        hipStream_t st = (hipStream_t)stream;
+        const int64_t blocks = std::min<int64_t>((n_words + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_pack5, dim3((unsigned)blocks), dim3(256), 0, st, db->d_letters, n, n_words, d);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+            (void)hipFree(d);
+            return fail(HS_EDEVICE, "packing the 5-bit letter image failed");
+        }
+        db->d_letters5 = (uint8_t*)d;
+    }
+    db->letter_bits = bits;
+    return HS_OK;
 }
 
 int hs_db_free(hs_db* db) {

@@ -206,16 +206,65 @@ __device__ __forceinline__ uint32_t pick4(const uint4& w, int32_t i) {
     return i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w;
 }
 
+// Letters as the block scorers read them, 16 per "chunk" (a uint4), letter
+// j of a chunk being at<j>.  kBits = 8: the byte image, a chunk is the 16
+// bytes from letter p on.  kBits = 5: the 5-bit image (letter p at bits
+// 5p .. 5p + 4 of a dense little-endian stream); a chunk is the 80 bits from
+// letter p on, funnel-shifted so that letter j sits at bits 5j of (x, y, z).
+template <int kBits>
+struct Letters;
+
+template <>
+struct Letters<8> {
+    static __device__ __forceinline__ uint4 load(const uint8_t* img, int64_t p) {
+        return load16(img + p);
+    }
+    template <int j>
+    static __device__ __forceinline__ uint32_t at(const uint4& w) {
+        return letter_of(pick4(w, j >> 2), j & 3);
+    }
+    // letter 4g + v, g known at run time only
+    template <int v>
+    static __device__ __forceinline__ uint32_t at_rt(const uint4& w, int32_t g) {
+        return letter_of(pick4(w, g), v);
+    }
+};
+
+template <>
+struct Letters<5> {
+    static __device__ __forceinline__ uint4 load(const uint8_t* img, int64_t p) {
+        const uint64_t b = (uint64_t)p * 5u;
+        uint4 w;
+        __builtin_memcpy(&w, img + ((b >> 5) << 2), 16);   // dword aligned
+        const uint32_t s = (uint32_t)b & 31u;
+        return make_uint4(__builtin_amdgcn_alignbit(w.y, w.x, s), __builtin_amdgcn_alignbit(w.z, w.y, s),
+                          __builtin_amdgcn_alignbit(w.w, w.z, s), 0u);
+    }
+    template <int j>
+    static __device__ __forceinline__ uint32_t at(const uint4& w) {
+        constexpr int b = 5 * j, d = b >> 5, o = b & 31;
+        if (o <= 27) return (pick4(w, d) >> o) & 31u;
+        return __builtin_amdgcn_alignbit(pick4(w, d + 1), pick4(w, d), (uint32_t)o) & 31u;
+    }
+    template <int v>
+    static __device__ __forceinline__ uint32_t at_rt(const uint4& w, int32_t g) {
+        const uint32_t b = 5u * (4u * (uint32_t)g + (uint32_t)v);
+        const int32_t d = (int32_t)(b >> 5);
+        return __builtin_amdgcn_alignbit(pick4(w, d + 1), pick4(w, d), b & 31u) & 31u;
+    }
+};
+
 // Unmasked run of `count` letters starting at T with read bases B.  Letters
 // come 16 at a time, fetched one chunk ahead; `first` holds letters 0..15 and
 // `tail` the 16 letters from count & ~15 on, both fetched by the caller.
 // kIlp issues the sixteen profile reads of a chunk before summing them: more
 // reads in flight for more registers (three wavefronts per SIMD instead of
 // four), which pays for long blocks only.
-template <int kCopies, bool kIlp = false>
-__device__ __forceinline__ void run_letters(const uint8_t* prof, int32_t ps, const uint8_t* T,
-                                            int32_t count, uint4 first, uint4 tail,
+template <int kCopies, bool kIlp = false, int kBits = 8>
+__device__ __forceinline__ void run_letters(const uint8_t* prof, int32_t ps, const uint8_t* img,
+                                            int64_t pos, int32_t count, uint4 first, uint4 tail,
                                             Bases<kCopies>& B, Acc8& a, int32_t& since_widen) {
+    using LT = Letters<kBits>;
     const int32_t n16 = count >> 4;
     if (kIlp && n16 > 0) {
         // one LDS pointer per letter position mod 4 (aligned down with one
@@ -230,19 +279,20 @@ __device__ __forceinline__ void run_letters(const uint8_t* prof, int32_t ps, con
         uint4 wn = first;
         for (int32_t q = 0; q < n16; ++q) {
             const uint4 w = wn;
-            T += 16;
-            wn = load16(T);      // the letter array is padded, so this stays in range
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                // the four letters of a dword: reads first, then the sums
-                const uint32_t wm = pick4(w, m);
-                const uint2 x0 = row8<kCopies>(prof, o0, 4 * m, ps, s0, letter_of(wm, 0));
-                const uint2 x1 = row8<kCopies>(prof, o1, 4 * m, ps, s1, letter_of(wm, 1));
-                const uint2 x2 = row8<kCopies>(prof, o2, 4 * m, ps, s2, letter_of(wm, 2));
-                const uint2 x3 = row8<kCopies>(prof, o3, 4 * m, ps, s3, letter_of(wm, 3));
-                a.b0 += (x0.x + x1.x) + (x2.x + x3.x);
-                a.b1 += (x0.y + x1.y) + (x2.y + x3.y);
+            pos += 16;
+            wn = LT::load(img, pos);   // the letter image is padded, so this stays in range
+            // the four letters of a group: reads first, then the sums
+#define HS_ILP_GROUP(m)                                                                  \
+            {                                                                            \
+                const uint2 x0 = row8<kCopies>(prof, o0, 4 * m, ps, s0, LT::template at<4 * m>(w));     \
+                const uint2 x1 = row8<kCopies>(prof, o1, 4 * m, ps, s1, LT::template at<4 * m + 1>(w)); \
+                const uint2 x2 = row8<kCopies>(prof, o2, 4 * m, ps, s2, LT::template at<4 * m + 2>(w)); \
+                const uint2 x3 = row8<kCopies>(prof, o3, 4 * m, ps, s3, LT::template at<4 * m + 3>(w)); \
+                a.b0 += (x0.x + x1.x) + (x2.x + x3.x);                                   \
+                a.b1 += (x0.y + x1.y) + (x2.y + x3.y);                                   \
             }
+            HS_ILP_GROUP(0) HS_ILP_GROUP(1) HS_ILP_GROUP(2) HS_ILP_GROUP(3)
+#undef HS_ILP_GROUP
             // advance the four offsets after this chunk's reads: as one
             // induction variable they would cost an extra add per letter
             asm volatile(
@@ -262,16 +312,16 @@ __device__ __forceinline__ void run_letters(const uint8_t* prof, int32_t ps, con
         uint4 wn = first;
         for (int32_t q = 0; q < n16; ++q) {
             const uint4 w = wn;
-            T += 16;
-            wn = load16(T);          // the letter array is padded, so this stays in range
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const uint32_t wm = pick4(w, m);
-                step_letter<kCopies>(prof, ps, B.v0 + 4 * m, letter_of(wm, 0), a);
-                step_letter<kCopies>(prof, ps, B.v1 + 4 * m, letter_of(wm, 1), a);
-                step_letter<kCopies>(prof, ps, B.v2 + 4 * m, letter_of(wm, 2), a);
-                step_letter<kCopies>(prof, ps, B.v3 + 4 * m, letter_of(wm, 3), a);
-            }
+            pos += 16;
+            wn = LT::load(img, pos);     // the letter image is padded, so this stays in range
+#define HS_GROUP(m)                                                                          \
+            step_letter<kCopies>(prof, ps, B.v0 + 4 * m, LT::template at<4 * m>(w), a);     \
+            step_letter<kCopies>(prof, ps, B.v1 + 4 * m, LT::template at<4 * m + 1>(w), a); \
+            step_letter<kCopies>(prof, ps, B.v2 + 4 * m, LT::template at<4 * m + 2>(w), a); \
+            step_letter<kCopies>(prof, ps, B.v3 + 4 * m, LT::template at<4 * m + 3>(w), a);
+            HS_GROUP(0) HS_GROUP(1) HS_GROUP(2)
+            HS_GROUP(3)
+#undef HS_GROUP
             B.advance(16);
             a.flush();
             if (++since_widen == 256) {
@@ -281,23 +331,21 @@ __device__ __forceinline__ void run_letters(const uint8_t* prof, int32_t ps, con
         }
     }
     const int32_t n4 = (count >> 2) & 3;
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-        if (u < n4) {
-            const uint32_t w = pick4(tail, u);
-            step_letter<kCopies>(prof, ps, B.v0, letter_of(w, 0), a);
-            step_letter<kCopies>(prof, ps, B.v1, letter_of(w, 1), a);
-            step_letter<kCopies>(prof, ps, B.v2, letter_of(w, 2), a);
-            step_letter<kCopies>(prof, ps, B.v3, letter_of(w, 3), a);
-            B.advance(4);
-        }
+#define HS_TAIL_GROUP(u)                                                       \
+    if (u < n4) {                                                              \
+        step_letter<kCopies>(prof, ps, B.v0, LT::template at<4 * u>(tail), a);     \
+        step_letter<kCopies>(prof, ps, B.v1, LT::template at<4 * u + 1>(tail), a); \
+        step_letter<kCopies>(prof, ps, B.v2, LT::template at<4 * u + 2>(tail), a); \
+        step_letter<kCopies>(prof, ps, B.v3, LT::template at<4 * u + 3>(tail), a); \
+        B.advance(4);                                                          \
     }
+    HS_TAIL_GROUP(0) HS_TAIL_GROUP(1) HS_TAIL_GROUP(2)
+#undef HS_TAIL_GROUP
     const int32_t rem = count & 3;
     if (rem) {
-        const uint32_t w = pick4(tail, n4);
-        step_letter<kCopies>(prof, ps, B.v0, letter_of(w, 0), a);
-        step_letter<kCopies>(prof, ps, B.v1, rem > 1 ? letter_of(w, 1) : (uint32_t)kZeroRow, a);
-        step_letter<kCopies>(prof, ps, B.v2, rem > 2 ? letter_of(w, 2) : (uint32_t)kZeroRow, a);
+        step_letter<kCopies>(prof, ps, B.v0, LT::template at_rt<0>(tail, n4), a);
+        step_letter<kCopies>(prof, ps, B.v1, rem > 1 ? LT::template at_rt<1>(tail, n4) : (uint32_t)kZeroRow, a);
+        step_letter<kCopies>(prof, ps, B.v2, rem > 2 ? LT::template at_rt<2>(tail, n4) : (uint32_t)kZeroRow, a);
         B.advance(4);
     }
     a.flush();
@@ -349,7 +397,7 @@ __device__ __forceinline__ uint64_t block_best_dir(const uint32_t v[8], int32_t 
 // last count % 16 of them preloaded); blocks of a large target also preload
 // their entry and exit ramps.
 struct BlockFetch {
-    const uint8_t* run;
+    int64_t run;        // letter position of the run's first letter
     int32_t count;
     uint4 first, tail, ramp_in, ramp_out;
 };
@@ -363,26 +411,29 @@ struct SlotInfo {
     uint64_t key;       // best placement of the current step so far
 };
 
-// Issues the letter loads of block k0 of slot `si`.
+// Issues the letter loads of block k0 of slot `si` from the letter image
+// (byte or 5-bit, kBits).
+template <int kBits = 8>
 __device__ __forceinline__ void fetch_block(const SlotInfo& si, int32_t k0,
                                             const uint8_t* __restrict__ letters, BlockFetch& f) {
+    using LT = Letters<kBits>;
     const int32_t ss = si.ss_tl & 0x7FFFFFFF;
     if (si.ss_tl < 0) {
-        const uint8_t* T = letters + si.tbase + si.pL + k0;
+        const int64_t T = si.tbase + si.pL + k0;
         f.run = T + 7;
         f.count = ss - 7;
         // letters 0..15: the entry ramp, or all ss + 7 letters of a short window
-        f.ramp_in = load16(T);
+        f.ramp_in = LT::load(letters, T);
         if (ss >= 7) {
-            f.ramp_out = load16(T + ss);
-            f.first = load16(f.run);
-            f.tail = load16(f.run + (f.count & ~15));
+            f.ramp_out = LT::load(letters, T + ss);
+            f.first = LT::load(letters, f.run);
+            f.tail = LT::load(letters, f.run + (f.count & ~15));
         }
     } else {
-        f.run = letters + si.tbase + si.pS;
+        f.run = si.tbase + si.pS;
         f.count = ss;
-        f.first = load16(f.run);
-        f.tail = load16(f.run + (ss & ~15));
+        f.first = LT::load(letters, f.run);
+        f.tail = LT::load(letters, f.run + (ss & ~15));
     }
 }
 
@@ -390,10 +441,11 @@ __device__ __forceinline__ void fetch_block(const SlotInfo& si, int32_t k0,
 // of letters, so that lanes holding blocks of either orientation run the same
 // loop; blocks of a large target add their masked entry and exit ramps, and
 // short windows of a large target (ss < 7) are summed cell by cell.
-template <int kCopies, bool kIlp = false>
+template <int kCopies, bool kIlp = false, int kBits = 8>
 __device__ __forceinline__ uint64_t score_block(const uint8_t* prof, int32_t ps, int32_t cpb,
                                                 int32_t bias, const SlotInfo& si, int32_t k0,
-                                                const BlockFetch& f) {
+                                                const BlockFetch& f, const uint8_t* letters) {
+    using LT = Letters<kBits>;
     const int32_t ss = si.ss_tl & 0x7FFFFFFF;
     const bool tl = si.ss_tl < 0;
     const int32_t off = (int32_t)__umul24((uint32_t)bias, (uint32_t)ss);
@@ -406,20 +458,25 @@ __device__ __forceinline__ uint64_t score_block(const uint8_t* prof, int32_t ps,
         uint32_t b0 = 0, b1 = 0;
         Bases<kCopies> Bs;
         Bs.set(si.pS - 7 + kPad, cpb);
-#pragma unroll
-        for (int i = 0; i < 13; ++i) {
-            const int32_t n = ss + 7 - i;          // bytes below this one are real
-            if (n > 0) {
-                const int32_t base = (i & 3) == 0 ? Bs.v0 : (i & 3) == 1 ? Bs.v1 : (i & 3) == 2 ? Bs.v2 : Bs.v3;
-                const uint32_t r = letter_of(pick4(f.ramp_in, i >> 2), i & 3);
-                const uint2 x = lds8<kCopies>(prof, (int32_t)(__umul24(r, (uint32_t)ps) + (uint32_t)base) + 4 * (i >> 2));
-                const uint64_t lo = i < 7 ? (~0ull << (8 * (7 - i))) : ~0ull;
-                const uint64_t hi = n >= 8 ? ~0ull : ((1ull << (8 * n)) - 1ull);
-                const uint64_t m = lo & hi;
-                b0 += x.x & (uint32_t)m;
-                b1 += x.y & (uint32_t)(m >> 32);
-            }
+#define HS_SHORT_LETTER(i)                                                                 \
+        {                                                                                  \
+            const int32_t n = ss + 7 - i;          /* bytes below this one are real */     \
+            if (n > 0) {                                                                   \
+                const int32_t base = (i & 3) == 0 ? Bs.v0 : (i & 3) == 1 ? Bs.v1 : (i & 3) == 2 ? Bs.v2 : Bs.v3; \
+                const uint32_t r = LT::template at<i>(f.ramp_in);                          \
+                const uint2 x = lds8<kCopies>(prof, (int32_t)(__umul24(r, (uint32_t)ps) + (uint32_t)base) + 4 * (i >> 2)); \
+                const uint64_t lo = i < 7 ? (~0ull << (8 * (7 - i))) : ~0ull;              \
+                const uint64_t hi = n >= 8 ? ~0ull : ((1ull << (8 * n)) - 1ull);           \
+                const uint64_t m = lo & hi;                                                \
+                b0 += x.x & (uint32_t)m;                                                   \
+                b1 += x.y & (uint32_t)(m >> 32);                                           \
+            }                                                                              \
         }
+        HS_SHORT_LETTER(0) HS_SHORT_LETTER(1) HS_SHORT_LETTER(2) HS_SHORT_LETTER(3)
+        HS_SHORT_LETTER(4) HS_SHORT_LETTER(5) HS_SHORT_LETTER(6) HS_SHORT_LETTER(7)
+        HS_SHORT_LETTER(8) HS_SHORT_LETTER(9) HS_SHORT_LETTER(10) HS_SHORT_LETTER(11)
+        HS_SHORT_LETTER(12)
+#undef HS_SHORT_LETTER
         // byte b of the reads is diagonal k0 + 7 - b
         v[0] = b0 & 0xFFu; v[1] = (b0 >> 8) & 0xFFu; v[2] = (b0 >> 16) & 0xFFu; v[3] = b0 >> 24;
         v[4] = b1 & 0xFFu; v[5] = (b1 >> 8) & 0xFFu; v[6] = (b1 >> 16) & 0xFFu; v[7] = b1 >> 24;
@@ -433,32 +490,32 @@ __device__ __forceinline__ uint64_t score_block(const uint8_t* prof, int32_t ps,
     if (tl) {
         // entry ramp: letters 0..6, letter i keeps bytes >= 7 - i
         B.set(e, cpb);
-        const uint32_t w0 = f.ramp_in.x, w1 = f.ramp_in.y;
-        step_letter<kCopies, 0u, 0xFF000000u>(prof, ps, B.v0, letter_of(w0, 0), a);
-        step_letter<kCopies, 0u, 0xFFFF0000u>(prof, ps, B.v1, letter_of(w0, 1), a);
-        step_letter<kCopies, 0u, 0xFFFFFF00u>(prof, ps, B.v2, letter_of(w0, 2), a);
-        step_letter<kCopies, 0u, 0xFFFFFFFFu>(prof, ps, B.v3, letter_of(w0, 3), a);
-        step_letter<kCopies, 0xFF000000u, 0xFFFFFFFFu>(prof, ps, B.v0 + 4, letter_of(w1, 0), a);
-        step_letter<kCopies, 0xFFFF0000u, 0xFFFFFFFFu>(prof, ps, B.v1 + 4, letter_of(w1, 1), a);
-        step_letter<kCopies, 0xFFFFFF00u, 0xFFFFFFFFu>(prof, ps, B.v2 + 4, letter_of(w1, 2), a);
+        const uint4& w = f.ramp_in;
+        step_letter<kCopies, 0u, 0xFF000000u>(prof, ps, B.v0, LT::template at<0>(w), a);
+        step_letter<kCopies, 0u, 0xFFFF0000u>(prof, ps, B.v1, LT::template at<1>(w), a);
+        step_letter<kCopies, 0u, 0xFFFFFF00u>(prof, ps, B.v2, LT::template at<2>(w), a);
+        step_letter<kCopies, 0u, 0xFFFFFFFFu>(prof, ps, B.v3, LT::template at<3>(w), a);
+        step_letter<kCopies, 0xFF000000u, 0xFFFFFFFFu>(prof, ps, B.v0 + 4, LT::template at<4>(w), a);
+        step_letter<kCopies, 0xFFFF0000u, 0xFFFFFFFFu>(prof, ps, B.v1 + 4, LT::template at<5>(w), a);
+        step_letter<kCopies, 0xFFFFFF00u, 0xFFFFFFFFu>(prof, ps, B.v2 + 4, LT::template at<6>(w), a);
         a.flush();
     }
     // the unmasked run: letters 7 .. ss - 1 of a large target (columns from
     // pS), or the ss letters of a small target (columns from pL + k0)
     int32_t sw = 0;
     B.set(tl ? e + 7 : si.pL + k0 + kPad, cpb);
-    run_letters<kCopies, kIlp>(prof, ps, f.run, f.count, f.first, f.tail, B, a, sw);
+    run_letters<kCopies, kIlp, kBits>(prof, ps, letters, f.run, f.count, f.first, f.tail, B, a, sw);
     if (tl) {
         // exit ramp: letters ss .. ss + 6; letter ss + u keeps bytes < 7 - u
         B.set(e + ss, cpb);
-        const uint32_t w0 = f.ramp_out.x, w1 = f.ramp_out.y;
-        step_letter<kCopies, 0xFFFFFFFFu, 0x00FFFFFFu>(prof, ps, B.v0, letter_of(w0, 0), a);
-        step_letter<kCopies, 0xFFFFFFFFu, 0x0000FFFFu>(prof, ps, B.v1, letter_of(w0, 1), a);
-        step_letter<kCopies, 0xFFFFFFFFu, 0x000000FFu>(prof, ps, B.v2, letter_of(w0, 2), a);
-        step_letter<kCopies, 0xFFFFFFFFu, 0u>(prof, ps, B.v3, letter_of(w0, 3), a);
-        step_letter<kCopies, 0x00FFFFFFu, 0u>(prof, ps, B.v0 + 4, letter_of(w1, 0), a);
-        step_letter<kCopies, 0x0000FFFFu, 0u>(prof, ps, B.v1 + 4, letter_of(w1, 1), a);
-        step_letter<kCopies, 0x000000FFu, 0u>(prof, ps, B.v2 + 4, letter_of(w1, 2), a);
+        const uint4& w = f.ramp_out;
+        step_letter<kCopies, 0xFFFFFFFFu, 0x00FFFFFFu>(prof, ps, B.v0, LT::template at<0>(w), a);
+        step_letter<kCopies, 0xFFFFFFFFu, 0x0000FFFFu>(prof, ps, B.v1, LT::template at<1>(w), a);
+        step_letter<kCopies, 0xFFFFFFFFu, 0x000000FFu>(prof, ps, B.v2, LT::template at<2>(w), a);
+        step_letter<kCopies, 0xFFFFFFFFu, 0u>(prof, ps, B.v3, LT::template at<3>(w), a);
+        step_letter<kCopies, 0x00FFFFFFu, 0u>(prof, ps, B.v0 + 4, LT::template at<4>(w), a);
+        step_letter<kCopies, 0x0000FFFFu, 0u>(prof, ps, B.v1 + 4, LT::template at<5>(w), a);
+        step_letter<kCopies, 0x000000FFu, 0u>(prof, ps, B.v2 + 4, LT::template at<6>(w), a);
         a.flush();
     }
     acc_values(a, v);
@@ -625,7 +682,7 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
 // longest first, so that neighbouring lanes get blocks of equal length;
 // every lane then scores blocks, and the best placement of each step is
 // folded into its slot's key in LDS.
-template <int kCopies, bool kIlp = false>
+template <int kCopies, bool kIlp = false, int kBits = 8>
 __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool stepping, bool tl,
                                               int32_t ss, int32_t& blk, int32_t nblk,
                                               const uint8_t* prof, int32_t ps, int32_t cpb,
@@ -685,7 +742,7 @@ __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool ste
             sl = (int32_t)(it >> 24);
             k0 = (int32_t)(it & 0xFFFFFFu) * kBlockDiags;
             si = W.slots[sl];
-            fetch_block(si, k0, letters, f);
+            fetch_block<kBits>(si, k0, letters, f);
         }
         while (have) {
             const int32_t in = i + kLanes;
@@ -698,9 +755,9 @@ __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool ste
                 sl_n = (int32_t)(it >> 24);
                 k0_n = (int32_t)(it & 0xFFFFFFu) * kBlockDiags;
                 si_n = W.slots[sl_n];
-                fetch_block(si_n, k0_n, letters, f_n);
+                fetch_block<kBits>(si_n, k0_n, letters, f_n);
             }
-            const uint64_t key = score_block<kCopies, kIlp>(prof, ps, cpb, bias, si, k0, f);
+            const uint64_t key = score_block<kCopies, kIlp, kBits>(prof, ps, cpb, bias, si, k0, f, letters);
             atomicMax((unsigned long long*)&W.slots[sl].key, (unsigned long long)key);
             si = si_n;
             sl = sl_n;
@@ -720,7 +777,7 @@ __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool ste
 // most `cap` pairs in flight (lanes 0..cap-1 hold them).  Returns when no
 // pair is left; scores go to scores[target], the best round to
 // rounds[target].  kExact allows a missing draw table (see pair_draw).
-template <int kCopies, bool kCount, bool kExact, bool kIlp>
+template <int kCopies, bool kCount, bool kExact, bool kIlp, int kBits = 8>
 __device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap, uint32_t grab,
                                            const uint8_t* prof, int32_t ps, int32_t cpb,
                                            int32_t bias, int32_t qlen, const KParams& kp,
@@ -806,7 +863,7 @@ __device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap
         if (__ballot(s.id >= 0) == 0) break;
 
         // ---- phases B and C ----
-        score_pending<kCopies, kIlp>(W, lane, s.id >= 0 && s.stepping, s.tl, s.ss, s.blk, s.nblk,
+        score_pending<kCopies, kIlp, kBits>(W, lane, s.id >= 0 && s.stepping, s.tl, s.ss, s.blk, s.nblk,
                                      prof, ps, cpb, bias, letters);
     }
 }
@@ -927,7 +984,7 @@ __device__ __forceinline__ uint64_t wave_step_key(int32_t lane, const uint8_t* p
             if (k0 < nk) {
                 BlockFetch f;
                 fetch_block(si, k0, letters, f);
-                const uint64_t key = score_block<kCopies, true>(prof, ps, cpb, bias, si, k0, f);
+                const uint64_t key = score_block<kCopies, true>(prof, ps, cpb, bias, si, k0, f, letters);
                 best = key > best ? key : best;
             }
         }
@@ -1059,7 +1116,9 @@ __device__ __forceinline__ void wave_score_one(int32_t lane, const uint8_t* prof
 // profile, every wavefront pulls pairs from the global queue, `grab`
 // positions at a time with at most `cap` in flight (small databases spread
 // thin over all wavefronts, large ones in grabs of 64).
-template <int kCopies, bool kCount, bool kIlp>
+// kBits: the letter image read by the block scorers, 8 (bytes) or 5 (the
+// packed image, a measured alternative).
+template <int kCopies, bool kCount, bool kIlp, int kBits = 8>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kIlp ? 1 : 4)))
 void k_score_sched(
     const PairRec* __restrict__ recs, int32_t n, const uint8_t* __restrict__ letters,
@@ -1079,7 +1138,7 @@ void k_score_sched(
     WaveLds& W = ((WaveLds*)(lds + profile_region_bytes(qlen, kCopies)))[threadIdx.x / kLanes];
     uint64_t cells = 0;
     int32_t best_seen = INT32_MIN;    // largest pair score written by this lane
-    wave_pairs<kCopies, kCount, false, kIlp>(W, lane, cap, grab, prof, ps, cpb, bias, qlen, kp,
+    wave_pairs<kCopies, kCount, false, kIlp, kBits>(W, lane, cap, grab, prof, ps, cpb, bias, qlen, kp,
                                              recs, (uint32_t)n, letters, draws, queue, scores,
                                              rounds, cells, best_seen);
     if (kCount) {

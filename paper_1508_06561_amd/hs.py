@@ -79,6 +79,7 @@ def lib():
         L.hs_encode.argtypes = [ctypes.c_char_p, ctypes.c_int64, P(ctypes.c_uint8)]
         L.hs_db_load.argtypes = [vp, P(ctypes.c_int64), ctypes.c_int64, vp, P(vp)]
         L.hs_db_free.argtypes = [vp]
+        L.hs_db_set_letters.argtypes = [vp, ctypes.c_int32, vp]
         L.hs_db_info.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
         L.hs_workspace_bytes.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_int32]
@@ -232,6 +233,11 @@ class Database:
             self.close()
         except Exception:
             pass
+
+    def set_letters(self, bits, stream=None):
+        """hs_db_set_letters: the letter image (8 = bytes, 5 = packed) that
+        the one-query scoring kernel reads."""
+        _check(lib().hs_db_set_letters(self._h, bits, _stream(stream)))
 
     def info(self):
         a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

@@ -46,7 +46,7 @@ def kernel_metadata(tmp_path):
 def test_no_scratch_and_default_occupancy(tmp_path):
     kernels = kernel_metadata(tmp_path)
     scoring = {n: v for n, v in kernels.items() if re.search(r"k_score_(sched|batch)", n)}
-    assert len(scoring) == 16, sorted(kernels)
+    assert len(scoring) == 20, sorted(kernels)
     assert any("k_trace_sched" in n for n in kernels) and any("k_trace_batch" in n for n in kernels)
     for name, (scratch, vgprs) in kernels.items():
         assert scratch == 0, f"{name} uses {scratch} bytes of scratch per lane"
