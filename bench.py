@@ -394,9 +394,11 @@ def measure_serving(args, rates):
         while len(timings) < len(qs):
             for t in srv.poll(timeout_ms=200):
                 _, tm = srv.result(t)
+                tm["qlen"] = len(qs[t - base])
                 timings.append(tm)
         th.join()
         lat = np.array([t["total_ms"] for t in timings])
+        slow = sorted(range(len(timings)), key=lambda i: -timings[i]["total_ms"])[:3]
         qms = np.array([t["queue_ms"] for t in timings])
         bms = np.array([t["batch_ms"] for t in timings])
         start = min(t["submit_ms"] for t in timings)
@@ -409,7 +411,13 @@ def measure_serving(args, rates):
                "sustained_qps": len(qs) / ((end - start) * 1e-3),
                "mean_batch": float(np.mean([t["batch_size"] for t in timings])),
                "max_batch": int(max(t["batch_size"] for t in timings)),
-               "mean_batch_ms": float(bms.mean())}
+               "mean_batch_ms": float(bms.mean()),
+               "slowest": [{"total_ms": timings[i]["total_ms"], "queue_ms": timings[i]["queue_ms"],
+                            "batch_ms": timings[i]["batch_ms"], "set_ms": timings[i]["set_ms"],
+                            "run_ms": timings[i]["run_ms"], "results_ms": timings[i]["results_ms"],
+                            "gpu_ms": timings[i]["gpu_ms"],
+                            "batch_size": timings[i]["batch_size"], "qlen": timings[i]["qlen"],
+                            "at_s": (timings[i]["submit_ms"] - start) * 1e-3} for i in slow]}
         log(f"rate {rate}/s: {row}")
         rows.append(row)
     srv.close()

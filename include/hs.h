@@ -438,23 +438,32 @@ int hs_search_batch(const hs_db* db, int32_t nq, const char* residues, const int
 /* ---------------------------------------------------------------------------
  * Serving.  A server owns a few workers, each a batch handle, a stream and a
  * thread, that run continuous batching: queries are submitted one at a time
- * (from any thread) and queue up; whenever a worker is free it takes every
- * waiting query, first come first served, that fits the batch footprint
- * fixed at creation -- at most max_batch queries and max_residues letters in
- * all (device memory, per worker), each at most max_qlen letters (LDS) --
- * searches them as one batch on its stream and publishes each query's
- * results.  With more than one worker, queries that arrive while a batch is
+ * (from any thread) and queue up; whenever a worker is free it takes the
+ * waiting queries, first come first served, while they fit the batch's
+ * footprint: device memory -- at most max_batch queries and max_residues
+ * letters in all, the capacity of the worker's buffers, each query at most
+ * max_qlen letters -- and LDS: a query whose score profile needs the one-copy
+ * layout (too long for four copies beside a full workgroup) is not batched
+ * with queries that keep four copies, so that it does not slow their launch;
+ * it starts the next batch.  The worker searches them as one batch on its
+ * stream and publishes each query's results.  With more than one worker, queries that arrive while a batch is
  * on the device start beside it.  Results are identical to a separate
  * hs_search of the same query and parameters.
  * ------------------------------------------------------------------------- */
 typedef struct hs_server hs_server;
 
-/* Per-query timing (milliseconds, host steady clock). */
+/* Per-query timing (milliseconds, host steady clock unless noted).  batch_ms
+ * is split into set_ms (encoding and upload of the batch's queries), run_ms
+ * (queueing its kernels) and results_ms (waiting for the device and copying
+ * the results back); gpu_ms is the device time of its kernels (HIP events on
+ * the worker's stream). */
 typedef struct hs_server_timing {
     double submit_ms;       /* submission time since the server was created */
     double queue_ms;        /* submission to the start of its batch */
     double batch_ms;        /* duration of its batch (upload, search, results) */
     double total_ms;        /* submission to results available */
+    double set_ms, run_ms, results_ms;
+    double gpu_ms;
     int32_t batch_size;     /* queries in its batch */
     int32_t pad_;
 } hs_server_timing;

@@ -157,6 +157,27 @@ __global__ __launch_bounds__(256) void k_pack5(const uint8_t* __restrict__ lette
     }
 }
 
+// Uploads and downloads of a batch between device memory and its pinned
+// host mirrors (coherent host memory, which the device reads and writes
+// directly, never caching it): segment s copies len[s] bytes from src +
+// soff[s] to dst + doff[s] (offsets and lengths multiples of 16).  A kernel
+// rather than a copy-engine transfer: served batches are small, and
+// hipMemcpyAsync of them now and then blocked the host for milliseconds.
+struct CopySegs {
+    int64_t soff[3], doff[3];
+    int64_t len[3];
+    int32_t n;
+};
+__global__ __launch_bounds__(256) void k_copy_segs(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                   CopySegs sg) {
+    for (int32_t k = 0; k < sg.n; ++k) {
+        const int64_t so = sg.soff[k] >> 4, d = sg.doff[k] >> 4, n = sg.len[k] >> 4;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+             i += (int64_t)gridDim.x * blockDim.x)
+            dst[d + i] = src[so + i];
+    }
+}
+
 namespace {
 
 void free_db(hs_db* db) {
@@ -691,6 +712,8 @@ struct hs_batch {
     // (hits, hit counts, alignments; packing offsets after them)
     char* h_up = nullptr;
     char* h_down = nullptr;
+    const char* d_up_view = nullptr;   // device addresses of h_up and h_down (copied by
+    char* d_down_view = nullptr;       // k_copy_segs)
     uint8_t* h_qcodes = nullptr;
     BatchQuery* h_qs = nullptr;
     KMatrix* h_mats = nullptr;
@@ -784,6 +807,17 @@ bool copies_fit(int32_t qlen, int copies, int min_waves = 1) {
     return fit_waves(batch_prof_bytes(qlen, copies)) >= min_waves;
 }
 
+}  // namespace
+
+namespace hs_internal {
+// LDS class of a query in a batch: 4 when its four profile copies fit beside
+// a full workgroup (the launch keeps aligned profile reads), else 1.  A batch
+// runs with the class of its longest query.
+int batch_lds_class(int32_t qlen) { return copies_fit(qlen, 4, kWaves) ? 4 : 1; }
+}  // namespace hs_internal
+
+namespace {
+
 template <int kCopies, bool kCount>
 const void* batch_fn(bool ilp) {
     return ilp ? (const void*)k_score_batch<kCopies, kCount, true>
@@ -801,6 +835,34 @@ size_t batch_lds(const hs_batch* b, int copies) {
 
 // Work items for the current queries: longest queries first, each cut into
 // ranges of `chunk` hand-out positions.
+// Queues a copy of up to three segments (byte offsets, lengths rounded up
+// to 16: every region is 256-byte aligned and padded).
+int copy_segments(const void* src, void* dst, hipStream_t st, const int64_t* soff,
+                  const int64_t* doff, const int64_t* len, int n) {
+    CopySegs sg;
+    sg.n = 0;
+    int64_t most = 0;
+    for (int i = 0; i < n; ++i) {
+        if (len[i] <= 0) continue;
+        sg.soff[sg.n] = soff[i];
+        sg.doff[sg.n] = doff[i];
+        sg.len[sg.n] = (len[i] + 15) & ~(int64_t)15;
+        most = std::max(most, sg.len[sg.n]);
+        ++sg.n;
+    }
+    if (sg.n == 0) return HS_OK;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((most / 16 + 255) / 256, 256));
+    hipLaunchKernelGGL(k_copy_segs, dim3((unsigned)blocks), dim3(256), 0, st, (const uint4*)src,
+                       (uint4*)dst, sg);
+    HIP_TRY(hipGetLastError());
+    return HS_OK;
+}
+
+// Upload of mirror segments to the same offsets of the device region.
+int pull_segments(hs_batch* b, hipStream_t st, const int64_t* off, const int64_t* len, int n) {
+    return copy_segments(b->d_up_view, b->d_mem, st, off, off, len, n);
+}
+
 int upload_items(hs_batch* b, hipStream_t st) {
     std::vector<int32_t> order((size_t)b->nq);
     for (int32_t q = 0; q < b->nq; ++q) order[(size_t)q] = q;
@@ -843,8 +905,10 @@ int upload_items(hs_batch* b, hipStream_t st) {
     // regions lie back to back), then wait for every upload of the batch
     if (!items.empty()) std::memcpy(b->h_items, items.data(), items.size() * sizeof(BatchItem));
     if (!titems.empty()) std::memcpy(b->h_titems, titems.data(), titems.size() * sizeof(BatchItem));
-    const size_t span = (size_t)((const char*)(b->h_titems + titems.size()) - (const char*)b->h_items);
-    HIP_TRY(hipMemcpyAsync(b->d_items, b->h_items, span, hipMemcpyHostToDevice, st));
+    const int64_t off[2] = {(const char*)b->h_items - b->h_up, (const char*)b->h_titems - b->h_up};
+    const int64_t len[2] = {(int64_t)(items.size() * sizeof(BatchItem)),
+                            (int64_t)(titems.size() * sizeof(BatchItem))};
+    if (int rc = pull_segments(b, st, off, len, 2)) return rc;
     HIP_TRY(hipStreamSynchronize(st));
     const void* fn = batch_kernel(b->copies, false, b->ilp);
     const size_t lds = batch_lds(b, b->copies);
@@ -1637,12 +1701,20 @@ int hs_batch_create(const hs_db* db, int32_t max_nq, int32_t max_qlen, int64_t m
     // the packing offsets and, right after them as on the device, up to
     // 64 KB of packed ops: results that small come back in one copy
     b->ops_prefix = std::min<size_t>(sizeof(uint32_t) * nal * (size_t)b->ops_stride, 64 * 1024);
-    const size_t down = sz[12] + sz[13] + sz[14] + align_up(sizeof(int64_t) * (nal + 1)) + b->ops_prefix;
-    if (hipHostMalloc((void**)&b->h_up, up, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&b->h_down, down, hipHostMallocDefault) != hipSuccess) {
+    // (plus slack: the copy kernel moves whole 16-byte words)
+    const size_t down = sz[12] + sz[13] + sz[14] + align_up(sizeof(int64_t) * (nal + 1)) +
+                        align_up(b->ops_prefix);
+    void* up_view = nullptr;
+    void* down_view = nullptr;
+    if (hipHostMalloc((void**)&b->h_up, up, hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_down, down, hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer(&up_view, b->h_up, 0) != hipSuccess ||
+        hipHostGetDevicePointer(&down_view, b->h_down, 0) != hipSuccess) {
         free_batch(b);
         return fail(HS_ENOMEM, "pinned host allocation for the batch failed");
     }
+    b->d_up_view = (const char*)up_view;
+    b->d_down_view = (char*)down_view;
     b->h_qcodes = (uint8_t*)b->h_up;
     b->h_qs = (BatchQuery*)(b->h_up + sz[0]);
     b->h_mats = (KMatrix*)(b->h_up + sz[0] + sz[1]);
@@ -1719,11 +1791,13 @@ int hs_batch_set(hs_batch* b, int32_t nq, const char* residues, const int64_t* o
     }
     b->nq = 0;      // not usable until the upload below completes
     drop_graph(b);
-    // codes, queries and matrices in one copy (their device regions lie
-    // back to back, like the mirror's); the work items follow in
-    // upload_items, which waits for both
-    const size_t span = (size_t)((const char*)(mats + nq) - b->h_up);
-    HIP_TRY(hipMemcpyAsync(b->d_qcodes, b->h_up, span, hipMemcpyHostToDevice, st));
+    // codes, queries and matrices (their device regions lie at the mirror's
+    // offsets); the work items follow in upload_items, which waits for both
+    {
+        const int64_t off[3] = {0, (const char*)qs - b->h_up, (const char*)mats - b->h_up};
+        const int64_t len[3] = {total, (int64_t)sizeof(BatchQuery) * nq, (int64_t)sizeof(KMatrix) * nq};
+        if (int rc = pull_segments(b, st, off, len, 3)) return rc;
+    }
     if (new_table && b->db->n_queue > 0) {
         const int32_t nqueue = (int32_t)b->db->n_queue;
         hipLaunchKernelGGL(k_draws, dim3((2 * (int64_t)nqueue + 255) / 256), dim3(256), 0, st,
@@ -1910,13 +1984,19 @@ int hs_batch_results(hs_batch* b, void* stream, hs_hit* hits, int32_t* n_hits, h
                            (const int64_t*)b->d_pos, b->d_packed);
         HIP_TRY(hipGetLastError());
     }
+    // hits, counts and alignments (back to back on the device and in the
+    // mirror); packing offsets and the packed ops' first ops_prefix bytes
     const size_t span = na > 0 ? (size_t)((const char*)(h_alns + (size_t)nq * na) - (const char*)h_hits)
                                : (size_t)((const char*)(h_nh + nq) - (const char*)h_hits);
-    HIP_TRY(hipMemcpyAsync(b->h_hits, b->d_hits, span, hipMemcpyDeviceToHost, st));
-    if (na > 0)   // packing offsets and the packed ops' first ops_prefix bytes
-        HIP_TRY(hipMemcpyAsync(b->h_pos, b->d_pos,
-                               (size_t)((const char*)b->h_packed - (const char*)b->h_pos) + b->ops_prefix,
-                               hipMemcpyDeviceToHost, st));
+    {
+        const int64_t soff[2] = {(const char*)b->d_hits - b->d_mem, (const char*)b->d_pos - b->d_mem};
+        const int64_t doff[2] = {0, (const char*)b->h_pos - b->h_down};
+        const int64_t len[2] = {(int64_t)span,
+                                na > 0 ? (int64_t)((const char*)b->h_packed - (const char*)b->h_pos) +
+                                             (int64_t)b->ops_prefix
+                                       : 0};
+        if ((rc = copy_segments(b->d_mem, b->d_down_view, st, soff, doff, len, 2))) return rc;
+    }
     HIP_TRY(hipStreamSynchronize(st));
     if (na > 0) {
         const int64_t need = h_pos[(size_t)nq * na];

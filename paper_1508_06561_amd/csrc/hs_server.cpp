@@ -1,9 +1,11 @@
 // hs_server.cpp -- serving loop of the C ABI (include/hs.h): queries are
 // submitted one at a time from any thread; each of a few worker threads owns
 // a batch handle and a stream and runs continuous batching -- whenever it is
-// free it takes every waiting query that fits its batch's footprint (count,
-// total letters, longest query; fixed when the server is created), searches
-// them as one batch on its stream and publishes each query's results.  With
+// free it takes the waiting queries, oldest first, that fit its batch's
+// footprint (device memory: count and total letters within the handle's
+// buffers; LDS: queries that keep four profile copies are not batched with
+// ones that need the one-copy layout), searches them as one batch on its
+// stream and publishes each query's results.  With
 // two workers, queries that arrive while one batch is on the device start at
 // once beside it.  Every result equals a separate hs_search of that query:
 // batching never changes results.
@@ -32,6 +34,7 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 
 struct Pending {
     uint64_t tag;
+    int lds_class;          // profile copies its batch can keep (4 or 1)
     std::string query;
     hs_params params;
     bool own_matrix;
@@ -50,9 +53,11 @@ struct Done {
 
 }  // namespace
 
-// The library's per-thread error message (hs_last_error), set in hs_lib.hip.
+// The library's per-thread error message (hs_last_error), and the LDS class
+// of a query in a batch, both in hs_lib.hip.
 namespace hs_internal {
 void set_error(const std::string& msg);
+int batch_lds_class(int32_t qlen);
 }
 
 namespace {
@@ -72,6 +77,7 @@ namespace {
 struct Worker {
     hs_batch* batch = nullptr;
     hipStream_t stream = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};   // around each batch's kernels
     std::thread thread;
 };
 
@@ -115,10 +121,15 @@ void hs_server::run(Worker& wk) {
             std::unique_lock<std::mutex> lk(mu);
             cv_work.wait(lk, [&] { return stop || !queue.empty(); });
             if (stop) return;
-            // admission: first come first served while the batch footprint allows
+            // admission, first come first served, while the batch's footprint
+            // allows: device memory (queries and letters within the batch
+            // handle's buffers) and LDS -- a query whose profile needs the
+            // one-copy layout starts a batch of its own class rather than
+            // taking a batch of shorter queries down to one copy with it
             int64_t res = 0;
             while (!queue.empty() && (int32_t)cur.size() < max_batch &&
-                   res + (int64_t)queue.front().query.size() <= max_residues) {
+                   res + (int64_t)queue.front().query.size() <= max_residues &&
+                   (cur.empty() || queue.front().lds_class == cur[0].lds_class)) {
                 res += (int64_t)queue.front().query.size();
                 inflight.insert(queue.front().tag);
                 cur.push_back(std::move(queue.front()));
@@ -146,12 +157,20 @@ void hs_server::run(Worker& wk) {
         ops.resize((size_t)(ops_cap > 0 ? ops_cap : 1));
         int64_t used = 0;
         int rc = hs_batch_set(batch, nq, residues.data(), offsets.data(), params.data(), nq, stream);
-        if (!rc) rc = hs_batch_run(batch, stream);
+        const Clock::time_point t_set = Clock::now();
+        if (!rc) {
+            (void)hipEventRecord(wk.ev[0], stream);
+            rc = hs_batch_run(batch, stream);
+            (void)hipEventRecord(wk.ev[1], stream);
+        }
+        const Clock::time_point t_run = Clock::now();
         if (!rc)
             rc = hs_batch_results(batch, stream, hits.data(), n_hits.data(), alns.data(),
                                   n_alns.data(), ops.data(), ops_cap, &used);
         const std::string err = rc ? hs_last_error() : "";
         const Clock::time_point t_done = Clock::now();
+        float gpu_ms = 0.f;
+        if (!rc && hipEventElapsedTime(&gpu_ms, wk.ev[0], wk.ev[1]) != hipSuccess) gpu_ms = -1.f;
         {
             std::lock_guard<std::mutex> lk(mu);
             for (int32_t i = 0; i < nq; ++i) {
@@ -161,6 +180,10 @@ void hs_server::run(Worker& wk) {
                 d.timing.queue_ms = ms_between(cur[(size_t)i].t_submit, t_start);
                 d.timing.total_ms = ms_between(cur[(size_t)i].t_submit, t_done);
                 d.timing.batch_ms = ms_between(t_start, t_done);
+                d.timing.set_ms = ms_between(t_start, t_set);
+                d.timing.run_ms = ms_between(t_set, t_run);
+                d.timing.results_ms = ms_between(t_run, t_done);
+                d.timing.gpu_ms = gpu_ms;
                 d.timing.batch_size = nq;
                 d.timing.submit_ms = ms_between(t0, cur[(size_t)i].t_submit);
                 if (!rc) {
@@ -207,10 +230,14 @@ int hs_server_create_workers(const hs_db* db, int32_t max_batch, int32_t max_qle
         rc = hs_batch_create(db, max_batch, max_qlen, max_residues, k, n_aln, &wk.batch);
         if (!rc && hipStreamCreateWithFlags(&wk.stream, hipStreamNonBlocking) != hipSuccess)
             rc = sfail(HS_EDEVICE, "stream creation failed");
+        if (!rc && (hipEventCreate(&wk.ev[0]) != hipSuccess || hipEventCreate(&wk.ev[1]) != hipSuccess))
+            rc = sfail(HS_EDEVICE, "event creation failed");
     }
     if (!rc && hipGetDevice(&s->device) != hipSuccess) rc = sfail(HS_EDEVICE, "no current device");
     if (rc) {
         for (Worker& wk : s->workers) {
+            for (hipEvent_t e : wk.ev)
+                if (e) (void)hipEventDestroy(e);
             if (wk.stream) (void)hipStreamDestroy(wk.stream);
             if (wk.batch) hs_batch_free(wk.batch);
         }
@@ -247,6 +274,8 @@ int hs_server_free(hs_server* s) {
         if (wk.thread.joinable()) wk.thread.join();
     for (Worker& wk : s->workers) {
         (void)hipStreamSynchronize(wk.stream);
+        for (hipEvent_t e : wk.ev)
+            if (e) (void)hipEventDestroy(e);
         (void)hipStreamDestroy(wk.stream);
         hs_batch_free(wk.batch);
     }
@@ -265,6 +294,7 @@ int hs_server_submit(hs_server* s, const char* query, int32_t qlen, const hs_par
     if (hs_encode(query, qlen, codes.data())) return HS_EINVAL;
     Pending p;
     p.tag = tag;
+    p.lds_class = hs_internal::batch_lds_class(qlen);
     p.query.assign(query, (size_t)qlen);
     p.params = *params;
     p.own_matrix = params->matrix != nullptr;

@@ -50,6 +50,8 @@ class Aln(ctypes.Structure):
 class ServerTiming(ctypes.Structure):
     _fields_ = [("submit_ms", ctypes.c_double), ("queue_ms", ctypes.c_double),
                 ("batch_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("set_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
+                ("results_ms", ctypes.c_double), ("gpu_ms", ctypes.c_double),
                 ("batch_size", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 

@@ -145,3 +145,36 @@ def test_two_workers_overlap_on_device(served):
     assert overlaps >= 1
     assert srv.stats()["batches"] == len(qs)
     srv.close()
+
+
+def test_lds_class_admission(served):
+    """A query too long for four profile copies is not batched with queries
+    that keep them: with one worker and a burst short, long, short, the long
+    query runs in a batch of its own class; every result still equals a
+    separate search."""
+    w, codes, db = served
+    rng = np.random.default_rng(12)
+    short = [bytes(synth.random_protein(rng, int(n))) for n in rng.integers(30, 200, 6)]
+    longq = [bytes(synth.random_protein(rng, 1800)), bytes(synth.random_protein(rng, 1900))]
+    order = short[:3] + longq + short[3:]
+    srv = H().Server(db, max_batch=16, max_qlen=5600, max_residues=30000, k=20, n_aln=5,
+                     workers=1)
+    # hold the worker on a long first query so that the rest queue up as one burst
+    srv.submit(bytes(synth.random_protein(rng, 5600)), tag=99)
+    for i, q in enumerate(order):
+        srv.submit(q, tag=200 + i)
+    tags = drain(srv, len(order) + 1)
+    assert len(tags) == len(order) + 1
+    sizes = {}
+    for tag in tags:
+        r, t = srv.result(tag)
+        sizes[tag] = t["batch_size"]
+        if tag == 99:
+            continue
+        q = order[tag - 200]
+        alone = db.search(q, H().Params(), k=20, n_aln=5)
+        assert (r.hits == alone.hits).all() and (r.ops == alone.ops).all()
+    # the two long queries were served together, apart from the short ones
+    assert sizes[203] == sizes[204] == 2
+    assert all(sizes[200 + i] <= 3 for i in (0, 1, 2, 5, 6, 7))
+    srv.close()
