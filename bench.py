@@ -425,6 +425,81 @@ def measure_serving(args, rates):
     return rows
 
 
+def measure_threshold(args, db, ds, w):
+    """Threshold reporting (every target at or above min_score, ranked, no
+    cap) on the full workload's query: a threshold admitting about 100,000
+    targets and none (all 500,200 ranked), device form, HIP events."""
+    import numpy as np
+    import torch
+
+    import paper_1508_06561_amd as H
+
+    stream = torch.cuda.current_stream()
+    scores = torch.empty(w.n_targets, dtype=torch.int32, device="cuda")
+    db.score_dev(ds.q, ds.qlen, H.Params(), ds.ws, scores)
+    s = np.sort(scores.cpu().numpy())[::-1]
+    ws = torch.empty(db.threshold_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    hits = torch.empty(w.n_targets * 16, dtype=torch.uint8, device="cuda")
+    n = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rows = []
+    for label, thr in (("about 100,000 targets", int(s[100_000])), ("every target", -(2**31))):
+        p = H.Params(min_score=thr)
+        for _ in range(2):
+            db.search_threshold_dev(ds.q, ds.qlen, p, w.n_targets, 0, ws, hits, n)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            db.search_threshold_dev(ds.q, ds.qlen, p, w.n_targets, 0, ws, hits, n)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        rows.append({"threshold": label, "min_score": thr, "hits": int(n.cpu()[0]),
+                     "ms_per_search": ms})
+        log(f"threshold search ({label}): {ms:.3f} ms, {int(n.cpu()[0])} hits")
+    return {"workload": "the full workload's query, every target at or above min_score ranked "
+                        "(no cap), device form", "rows": rows}
+
+
+def measure_align(args):
+    """Pairwise mode (every overlapping placement, best of Rounds = 20) on
+    1,000 pairs: a log-normal query (median 300) against a mutated copy with
+    indels (20-90% identity) embedded in a flank, plus the longest accepted
+    pair (5,600 x 5,600); host in and out (hs_align_batch)."""
+    import numpy as np
+    import torch
+
+    import paper_1508_06561_amd as H
+    import synth
+
+    rng = np.random.default_rng(synth.BASE_SEED + 7)
+    pairs = []
+    for L in synth.lognormal_lengths(rng, 1000, 300, 0.6, 20, 2000):
+        q = synth.random_protein(rng, int(L))
+        tl = int(synth.lognormal_lengths(rng, 1, 300, 0.6, 20, 2000)[0])
+        t = synth.embed(rng, synth.mutate(rng, q, rng.uniform(0.2, 0.9)), tl)[:5600]
+        pairs.append((bytes(q), bytes(t)))
+    p = H.Params(rounds=20)
+    H.align_batch(pairs[:10], p)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps = max(1, args.steps // 10)
+    for _ in range(reps):
+        H.align_batch(pairs, p)
+    ms = (time.perf_counter() - t) * 1e3 / reps
+    big = (bytes(synth.random_protein(rng, 5600)), bytes(synth.random_protein(rng, 5600)))
+    H.align(*big, p)
+    t = time.perf_counter()
+    H.align(*big, p)
+    ms_big = (time.perf_counter() - t) * 1e3
+    log(f"pairwise mode: {ms:.2f} ms per 1,000 pairs (Rounds 20), longest pair {ms_big:.2f} ms")
+    return {"workload": "pairwise mode (Fig. 1 full slide), Rounds 20: 1,000 pairs, query "
+                        "log-normal median 300, target a 20-90% identity copy with indels in a "
+                        "flank; host in and out",
+            "ms_per_1000_pairs": ms, "pairs_per_s": 1000 / (ms * 1e-3),
+            "ms_longest_pair_5600x5600": ms_big}
+
+
 SW_OPS_PER_CELL = 11     # Gotoh cell: 4 subtractions, 1 addition, 6 maxima (with the running best)
 SW_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit integer ops: 64 lanes per CU per clock
 
@@ -536,7 +611,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["full", "batched", "long", "serving", "sw"], default="full")
+    ap.add_argument("--workload", choices=["full", "batched", "long", "serving", "sw", "align"],
+                    default="full")
+    ap.add_argument("--letters", type=int, choices=[8, 5], default=8,
+                    help="full workload: letter image of the scoring kernel (8 = bytes, 5 = packed)")
     ap.add_argument("--rates", type=float, nargs="+", default=[50, 200, 500])
     ap.add_argument("--schedule", type=int, nargs=3, metavar=("COPIES", "CAP", "CHUNK"),
                     help="batch workloads: fixed schedule instead of the autotuner")
@@ -571,6 +649,9 @@ def main():
         return bench_serving(args)
     if args.workload == "sw":
         return bench_sw(args)
+    if args.workload == "align":
+        print(json.dumps(measure_align(args)), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -586,8 +667,10 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     db = H.Database(w.residues, w.offsets)
+    if args.letters != 8:
+        db.set_letters(args.letters)
     torch.cuda.synchronize()
-    log(f"database loaded: {db.info()}")
+    log(f"database loaded: {db.info()}, letters {args.letters} bits")
     p = H.Params()
     ds = H.DeviceSearch(db, len(q), w.k, w.n_aln)
     ds.set_query(bytes(q))
@@ -652,9 +735,13 @@ def main():
     }
     out["homolog_recall"] = {"k": w.k, "planted": len(w.planted), "recall": recall,
                              "note": "planted homologs ranked in the top k (information only)"}
+    if args.letters != 8:
+        out["config"]["letters"] = f"{args.letters}-bit image"
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, q, args.cpu_budget)
         log(f"cpu baseline: {out['cpu_baseline']}")
+    if not args.full_only:
+        out["threshold"] = measure_threshold(args, db, ds, w)
     db.close()
     del ds, scores, cells_t
     if not args.full_only:
@@ -668,6 +755,7 @@ def main():
                           "schedule": bt["config"]["schedule"], "roofline": bt["roofline"]}
         rates = list(args.rates) + ([args.saturate] if args.saturate else [])
         rows = measure_serving(args, rates)
+        out["align"] = measure_align(args)
         out["serving"] = {"workload": SERVING_DESC.format(rates=", ".join(f"{r:g}" for r in rates),
                                                           secs=args.serve_s),
                           "rows": rows,
