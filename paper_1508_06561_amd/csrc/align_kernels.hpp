@@ -213,4 +213,47 @@ __global__ __launch_bounds__(kAlThreads) void k_align_replay(const AlignPair* __
     }
 }
 
+// Exclusive prefix sums of the pairs' op counts, one workgroup: off[i] is
+// the first packed op of pair i, off[n] the total.  Each thread sums a run of
+// consecutive counts, the run totals are scanned in LDS, and each thread
+// then writes its run's offsets.
+constexpr int kAlScanThreads = 1024;
+__global__ __launch_bounds__(kAlScanThreads) void k_align_ops_scan(const int32_t* __restrict__ cnt,
+                                                                   int32_t n, int64_t* __restrict__ off) {
+    __shared__ int64_t part[kAlScanThreads];
+    const int32_t per = (n + kAlScanThreads - 1) / kAlScanThreads;
+    const int32_t lo = (int32_t)threadIdx.x * per;
+    const int32_t hi = lo + per < n ? lo + per : n;
+    int64_t sum = 0;
+    for (int32_t i = lo; i < hi; ++i) sum += cnt[i];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int o = 1; o < kAlScanThreads; o <<= 1) {
+        const int64_t y = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += y;
+        __syncthreads();
+    }
+    int64_t run = part[threadIdx.x] - sum;
+    for (int32_t i = lo; i < hi; ++i) {
+        off[i] = run;
+        run += cnt[i];
+    }
+    if (threadIdx.x == kAlScanThreads - 1) off[n] = part[kAlScanThreads - 1];
+}
+
+// One wavefront per pair moves the pair's ops from its slot in `ops` to its
+// packed place.
+__global__ __launch_bounds__(kAlThreads) void k_align_ops_pack(const AlignPair* __restrict__ pairs,
+                                                               int32_t n, const int32_t* __restrict__ cnt,
+                                                               const int64_t* __restrict__ off,
+                                                               const uint32_t* __restrict__ ops,
+                                                               uint32_t* __restrict__ packed) {
+    const int32_t pair = (int32_t)blockIdx.x * kAlWaves + (int32_t)(threadIdx.x / kLanes);
+    if (pair >= n) return;
+    const int64_t src = pairs[pair].ops_off, dst = off[pair];
+    for (int32_t j = (int32_t)(threadIdx.x & (kLanes - 1)); j < cnt[pair]; j += kLanes)
+        packed[dst + j] = ops[src + j];
+}
+
 }  // namespace hs

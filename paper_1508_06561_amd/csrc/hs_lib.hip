@@ -1518,18 +1518,22 @@ int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char*
         co += P.qlen + P.tlen;
     }
     hipStream_t st = (hipStream_t)stream;
+    // device layout: codes, pairs, per-round scores, then one region of
+    // scores, rounds and packed offsets (read back by one copy), op counts,
+    // ops in per-pair slots, packed ops
     const size_t o_codes = 0, o_pairs = align_up(codes.size()),
                  o_rs = o_pairs + align_up(sizeof(AlignPair) * (size_t)n),
                  o_sc = o_rs + align_up(sizeof(int32_t) * (size_t)n * params->rounds),
-                 o_rd = o_sc + align_up(sizeof(int32_t) * (size_t)n),
-                 o_no = o_rd + align_up(sizeof(int32_t) * (size_t)n),
+                 o_rd = o_sc + sizeof(int32_t) * (size_t)n,
+                 o_off = (o_rd + sizeof(int32_t) * (size_t)n + 7) & ~(size_t)7,
+                 o_no = align_up(o_off + sizeof(int64_t) * ((size_t)n + 1)),
                  o_ops = o_no + align_up(sizeof(int32_t) * (size_t)n),
-                 total = o_ops + align_up(sizeof(uint32_t) * (size_t)nops);
+                 o_pk = o_ops + align_up(sizeof(uint32_t) * (size_t)nops),
+                 total = o_pk + align_up(sizeof(uint32_t) * (size_t)nops);
     char* d = nullptr;
     if (hipMallocAsync((void**)&d, total, st) != hipSuccess)
         return fail(HS_ENOMEM, "device allocation failed");
-    std::vector<int32_t> h_sc((size_t)n), h_rd((size_t)n), h_no((size_t)n);
-    std::vector<uint32_t> h_ops((size_t)nops);
+    std::vector<char> h_head(o_no - o_sc);
     const KParams kp = kparams(params);
     const KMatrix km = kmatrix(params);
     rc = HS_OK;
@@ -1538,37 +1542,40 @@ int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char*
                        st) != hipSuccess)
         rc = fail(HS_EDEVICE, "pair upload failed");
     if (!rc) {
+        const AlignPair* d_pairs = (const AlignPair*)(d + o_pairs);
         hipLaunchKernelGGL(k_align_rounds, dim3((unsigned)((int64_t)n * params->rounds)), dim3(kAlThreads),
-                           0, st, (const AlignPair*)(d + o_pairs), (const uint8_t*)(d + o_codes), kp, km,
-                           (int32_t*)(d + o_rs));
-        hipLaunchKernelGGL(k_align_replay, dim3((unsigned)n), dim3(kAlThreads), 0, st,
-                           (const AlignPair*)(d + o_pairs), (const uint8_t*)(d + o_codes), kp, km,
-                           (const int32_t*)(d + o_rs), (int32_t*)(d + o_sc), (int32_t*)(d + o_rd),
-                           (int32_t*)(d + o_no), (uint32_t*)(d + o_ops));
+                           0, st, d_pairs, (const uint8_t*)(d + o_codes), kp, km, (int32_t*)(d + o_rs));
+        hipLaunchKernelGGL(k_align_replay, dim3((unsigned)n), dim3(kAlThreads), 0, st, d_pairs,
+                           (const uint8_t*)(d + o_codes), kp, km, (const int32_t*)(d + o_rs),
+                           (int32_t*)(d + o_sc), (int32_t*)(d + o_rd), (int32_t*)(d + o_no),
+                           (uint32_t*)(d + o_ops));
+        hipLaunchKernelGGL(k_align_ops_scan, dim3(1), dim3(kAlScanThreads), 0, st,
+                           (const int32_t*)(d + o_no), n, (int64_t*)(d + o_off));
+        hipLaunchKernelGGL(k_align_ops_pack, dim3((unsigned)((n + kAlWaves - 1) / kAlWaves)), dim3(kAlThreads),
+                           0, st, d_pairs, n, (const int32_t*)(d + o_no), (const int64_t*)(d + o_off),
+                           (const uint32_t*)(d + o_ops), (uint32_t*)(d + o_pk));
         if (hipGetLastError() != hipSuccess) rc = fail(HS_EDEVICE, "pairwise kernels failed to launch");
     }
-    if (!rc && (hipMemcpyAsync(h_sc.data(), d + o_sc, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st) ||
-                hipMemcpyAsync(h_rd.data(), d + o_rd, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st) ||
-                hipMemcpyAsync(h_no.data(), d + o_no, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st) ||
-                hipMemcpyAsync(h_ops.data(), d + o_ops, sizeof(uint32_t) * (size_t)nops,
-                               hipMemcpyDeviceToHost, st) ||
+    // scores, rounds and offsets first; then exactly the packed ops, straight
+    // into the caller's buffer when they fit
+    if (!rc && (hipMemcpyAsync(h_head.data(), d + o_sc, h_head.size(), hipMemcpyDeviceToHost, st) ||
                 hipStreamSynchronize(st)))
         rc = fail(HS_EDEVICE, "pairwise alignment failed on the device");
+    const int64_t* h_off = (const int64_t*)(h_head.data() + (o_off - o_sc));
+    const int64_t need = rc ? 0 : h_off[n];
+    if (!rc) {
+        *ops_used = need;
+        if (need > ops_cap) rc = fail(HS_ENOSPC, "ops buffer too small");
+    }
+    if (!rc && need > 0 && (!ops || hipMemcpyAsync(ops, d + o_pk, sizeof(uint32_t) * (size_t)need,
+                                                   hipMemcpyDeviceToHost, st) ||
+                            hipStreamSynchronize(st)))
+        rc = fail(HS_EDEVICE, "pairwise alignment ops copy failed");
     (void)hipFreeAsync(d, st);
     if (rc) return rc;
-    int64_t need = 0;
-    for (int32_t i = 0; i < n; ++i) need += h_no[(size_t)i];
-    *ops_used = need;
-    if (need > ops_cap) return fail(HS_ENOSPC, "ops buffer too small");
-    int64_t off = 0;
-    for (int32_t i = 0; i < n; ++i) {
-        ops_off[i] = off;
-        std::memcpy(ops + off, h_ops.data() + pairs[(size_t)i].ops_off, sizeof(uint32_t) * h_no[(size_t)i]);
-        off += h_no[(size_t)i];
-    }
-    ops_off[n] = off;
-    std::memcpy(scores, h_sc.data(), sizeof(int32_t) * (size_t)n);
-    if (rounds) std::memcpy(rounds, h_rd.data(), sizeof(int32_t) * (size_t)n);
+    std::memcpy(ops_off, h_off, sizeof(int64_t) * ((size_t)n + 1));
+    std::memcpy(scores, h_head.data(), sizeof(int32_t) * (size_t)n);
+    if (rounds) std::memcpy(rounds, h_head.data() + (o_rd - o_sc), sizeof(int32_t) * (size_t)n);
     return HS_OK;
 }
 

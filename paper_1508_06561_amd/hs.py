@@ -419,7 +419,7 @@ class DeviceSearch:
 
 def _pack_queries(queries):
     """(concatenated ASCII bytes as uint8, int64 offsets) of a list of queries."""
-    bs = [q.encode() if isinstance(q, str) else bytes(q) for q in queries]
+    bs = [q if isinstance(q, bytes) else q.encode() if isinstance(q, str) else bytes(q) for q in queries]
     off = np.zeros(len(bs) + 1, dtype=np.int64)
     off[1:] = np.cumsum([len(b) for b in bs])
     res = np.frombuffer(b"".join(bs), dtype=np.uint8).copy()
@@ -582,8 +582,9 @@ def align_batch(pairs, params=None, stream=None):
                                 ctypes.byref(p), _stream(stream), scores.ctypes.data_as(P),
                                 rounds.ctypes.data_as(P), ops.ctypes.data, cap,
                                 ops_off.ctypes.data_as(P64), ctypes.byref(used)))
-    return [Alignment(int(scores[i]), int(rounds[i]), ops[ops_off[i]:ops_off[i + 1]].copy())
-            for i in range(n)]
+    # one buffer holds every pair's ops; each Alignment keeps a view of its run
+    o, s, r = ops_off.tolist(), scores.tolist(), rounds.tolist()
+    return [Alignment(s[i], r[i], ops[o[i]:o[i + 1]]) for i in range(n)]
 
 
 def align(query, target, params=None, stream=None):
