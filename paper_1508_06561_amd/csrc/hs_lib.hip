@@ -467,6 +467,7 @@ int prefer_ilp(const void* fn_default, const void* fn_ilp, int threads, size_t l
 // Target letters a wavefront of the one-query search keeps in flight: 64
 // pairs of targets up to 384 letters, one pair of a target over 12,288.
 constexpr int64_t kLettersInFlight = 64 * 384;
+constexpr uint32_t kTailGrab = 32;       // counter grabs of the short tail (striped schedule)
 
 template <int kCopies, bool kCount, bool kIlp, int kBits = 8>
 int launch_sched(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParams& kp,
@@ -494,10 +495,22 @@ int launch_sched(const hs_db* db, const uint8_t* d_q, int32_t qlen, const KParam
         std::min<int64_t>(kLanes, by_len), std::max<int64_t>(1, (db->n_targets + slots - 1) / slots));
     const int64_t want = (db->n_targets + (int64_t)cap * L.waves - 1) / ((int64_t)cap * L.waves);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * device_cus(), want));
+    // With every lane holding a pair (many short targets), the longest three
+    // quarters of the length ranks are striped over the wavefronts and the
+    // rest taken from the counter 32 at a time: grabs of 64 positions left
+    // the last wavefronts holding up to 64 pairs while others sat idle, and
+    // the counter's tail lets the faster wavefronts (older ones take issue
+    // priority on a SIMD) take more of the short pairs.  Scoring of the full
+    // search: 0.606 ms with grabs of 64, 0.568 ms striping every rank, 0.52 ms
+    // with this.
+    const uint32_t stride = cap == kLanes ? (uint32_t)grid * (uint32_t)L.waves : 0u;
+    const uint32_t r0 = stride ? (uint32_t)(db->n_queue * 3 / 4 / stride) * stride : 0u;
+    const uint32_t grab = stride ? kTailGrab : (uint32_t)cap;
     hipLaunchKernelGGL((k_score_sched<kCopies, kCount, kIlp, kBits>), dim3(grid), dim3(threads), L.lds, st,
                        (const PairRec*)db->d_recs, (int32_t)db->n_queue,
                        kBits == 5 ? db->d_letters5 : db->d_letters, d_q, qlen,
-                       kp, km, bias, cap, (uint32_t)cap, (const uint64_t*)w.draws, w.queue, d_scores, d_rounds,
+                       kp, km, bias, cap, grab, stride, r0, (const uint64_t*)w.draws, w.queue, d_scores,
+                       d_rounds,
                        (unsigned long long*)d_cells, d_max);
     HIP_TRY(hipGetLastError());
     return HS_OK;

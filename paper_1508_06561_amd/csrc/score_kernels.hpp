@@ -770,15 +770,28 @@ __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool ste
     wave_sync();
 }
 
+// Hand-out position of length rank r (longest first): positions hold rank
+// i * nb + b at kGrab * b + i (nb batches of kGrab positions).
+__device__ __forceinline__ uint32_t rank_position(uint32_t r, uint32_t nb) {
+    return (r % nb) * kGrab + r / nb;
+}
+
 // One wavefront's share of the pairs of one query: hand-out positions below
 // `hi`, taken from the counter `ctr` (global, or a workgroup counter in LDS)
 // at least `grab` at a time -- a large grab keeps atomics on a global
 // counter rare, grab 0 takes exactly what the wavefront needs -- with at
-// most `cap` pairs in flight (lanes 0..cap-1 hold them).  Returns when no
-// pair is left; scores go to scores[target], the best round to
-// rounds[target].  kExact allows a missing draw table (see pair_draw).
+// most `cap` pairs in flight (lanes 0..cap-1 hold them).
+// With stride > 0 (the one-query kernel on a database of many short
+// targets) the pairs go by length rank instead: wavefront gw of `stride`
+// takes ranks gw, gw + stride, ... below r0 (the longest ones, the same mix
+// of lengths for every wavefront, with no atomics), then ranks from r0 on
+// from the counter, `grab` at a time, so that the wavefronts that run
+// faster take more of the short tail and all finish together.
+// Returns when no pair is left; scores go to scores[target], the best round
+// to rounds[target].  kExact allows a missing draw table (see pair_draw).
 template <int kCopies, bool kCount, bool kExact, bool kIlp, int kBits = 8>
 __device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap, uint32_t grab,
+                                           uint32_t stride, uint32_t r0, uint32_t gw,
                                            const uint8_t* prof, int32_t ps, int32_t cpb,
                                            int32_t bias, int32_t qlen, const KParams& kp,
                                            const PairRec* __restrict__ recs, uint32_t hi,
@@ -791,7 +804,9 @@ __device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap
     s.id = -1;
     s.stepping = false;
     bool exhausted = false;
-    uint32_t q_next = 0, q_end = 0;   // held range of queue positions (wavefront-uniform)
+    uint32_t q_next = 0, q_end = 0;   // held range of the counter (wavefront-uniform)
+    uint32_t k_next = 0;              // ranks of the stripe handed out (stride > 0)
+    const uint32_t nb = hi / kGrab;
 
     for (;;) {
         // ---- phase A: apply last step's winner, advance, refill ----
@@ -815,18 +830,39 @@ __device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap
             if (!mask) break;
             const uint32_t cnt = (uint32_t)__popcll(mask);
             const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1));
-            // from the range already held, then from one new range
-            const uint32_t take1 = cnt < q_end - q_next ? cnt : q_end - q_next;
-            uint32_t qi = q_next + rank;
-            q_next += take1;
-            if (take1 < cnt) {
-                const uint32_t g = cnt - take1 > grab ? cnt - take1 : grab;
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(ctr, g);
-                base = (uint32_t)__builtin_amdgcn_readlane((int)base, 0);
-                if (rank >= take1) qi = base + (rank - take1);
-                q_next = base + (cnt - take1);
-                q_end = base + g;
+            uint32_t qi = hi;
+            // the first n_static lanes take the next ranks of the stripe
+            uint32_t n_static = 0;
+            if (stride) {
+                const uint32_t k0 = r0 / stride;
+                n_static = k_next < k0 ? (cnt < k0 - k_next ? cnt : k0 - k_next) : 0u;
+                if (rank < n_static) qi = rank_position(gw + (k_next + rank) * stride, nb);
+                k_next += n_static;
+            }
+            const uint32_t cnt_d = cnt - n_static;
+            if (cnt_d) {
+                // the others: from the range already held, then from one new range
+                const uint32_t rank_d = rank - n_static;     // used where rank >= n_static
+                const uint32_t take1 = cnt_d < q_end - q_next ? cnt_d : q_end - q_next;
+                uint32_t d = q_next + rank_d;
+                q_next += take1;
+                if (take1 < cnt_d) {
+                    const uint32_t g = cnt_d - take1 > grab ? cnt_d - take1 : grab;
+                    uint32_t base = 0;
+                    if (lane == 0) base = atomicAdd(ctr, g);
+                    base = (uint32_t)__builtin_amdgcn_readlane((int)base, 0);
+                    if (rank_d >= take1) d = base + (rank_d - take1);
+                    q_next = base + (cnt_d - take1);
+                    q_end = base + g;
+                }
+                if (rank >= n_static) {
+                    if (!stride) {
+                        qi = d;
+                    } else {
+                        const uint32_t r = r0 + d;      // past the last rank: exhausted
+                        qi = r >= r0 && r < hi ? rank_position(r, nb) : hi;
+                    }
+                }
             }
             if (need && qi < hi) {
                 // Every field of the record and the first draw word are
@@ -1123,7 +1159,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kIlp ?
 void k_score_sched(
     const PairRec* __restrict__ recs, int32_t n, const uint8_t* __restrict__ letters,
     const uint8_t* __restrict__ qcodes, int32_t qlen, KParams kp, KMatrix km, int32_t bias,
-    int32_t cap, uint32_t grab,
+    int32_t cap, uint32_t grab, uint32_t stride, uint32_t r0,
     const uint64_t* __restrict__ draws, uint32_t* queue, int32_t* __restrict__ scores,
     int32_t* __restrict__ rounds, unsigned long long* cells_total, int32_t* max_score) {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -1138,7 +1174,10 @@ void k_score_sched(
     WaveLds& W = ((WaveLds*)(lds + profile_region_bytes(qlen, kCopies)))[threadIdx.x / kLanes];
     uint64_t cells = 0;
     int32_t best_seen = INT32_MIN;    // largest pair score written by this lane
-    wave_pairs<kCopies, kCount, false, kIlp, kBits>(W, lane, cap, grab, prof, ps, cpb, bias, qlen, kp,
+    const uint32_t gw = blockIdx.x * (blockDim.x / kLanes) +
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kLanes));
+    wave_pairs<kCopies, kCount, false, kIlp, kBits>(W, lane, cap, grab, stride, r0, gw, prof, ps, cpb,
+                                                    bias, qlen, kp,
                                              recs, (uint32_t)n, letters, draws, queue, scores,
                                              rounds, cells, best_seen);
     if (kCount) {
@@ -1189,7 +1228,7 @@ void k_score_batch(
                                threadIdx.x, blockDim.x);
         __syncthreads();
         int32_t best_seen = INT32_MIN;
-        wave_pairs<kCopies, kCount, true, kIlp>(W, lane, cap, 0u, lds, ps, cpb, Q.bias, Q.qlen,
+        wave_pairs<kCopies, kCount, true, kIlp>(W, lane, cap, 0u, 0u, 0u, 0u, lds, ps, cpb, Q.bias, Q.qlen,
                                                 Q.kp, recs, item.hi, letters,
                                                 Q.table ? draws : nullptr, &s_ctr,
                                                 scores + (int64_t)q * stride,
