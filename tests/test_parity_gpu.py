@@ -203,6 +203,29 @@ def test_group_boundaries(n):
         db.close()
 
 
+@pytest.mark.parametrize("n", [258_049, 300_007])
+def test_striped_schedule_sizes(n):
+    """Databases just large enough for the one-query kernel to put a pair on
+    every lane of every resident wavefront (so it stripes length ranks over
+    the wavefronts and takes the short tail from the counter), at a size that
+    leaves a smaller grid and one with padding positions: every score and
+    the work count, then the ranked list and alignments."""
+    rng = np.random.default_rng(4000 + n)
+    res, off = synth.random_db(rng, rng.integers(10, 121, size=n))
+    q = synth.random_protein(rng, 40)
+    codes = O.encode_db(res, off)
+    db = H().Database(res, off)
+    try:
+        say(f"striped schedule: {n} targets")
+        s, _, cells = db.scores(bytes(q))
+        ref, ref_cells = oracle_scores(codes, off, O.encode(bytes(q)), O.Params())
+        assert (s == ref).all(), f"{(s != ref).sum()} scores differ"
+        assert cells == ref_cells
+        check_search(db, codes, off, q, H().Params(), k=100, n_aln=10)
+    finally:
+        db.close()
+
+
 def test_identical_targets_tie_on_index():
     """Equal scores are ranked by target index (every target identical)."""
     rng = np.random.default_rng(3)
