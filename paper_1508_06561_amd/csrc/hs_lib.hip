@@ -645,7 +645,9 @@ size_t threshold_ws_bytes(const hs_db* db) {
     const size_t n = (size_t)std::max<int64_t>(db->n_targets, 1);
     const size_t tiles = (size_t)std::max<int64_t>(rs_tiles(db->n_targets), 1);
     return query_ws_bytes(db->n_targets, db->n_queue, 1) + align_up(sizeof(RsState)) +
-           align_up(sizeof(uint32_t) * kRsBins * tiles) + 4 * align_up(sizeof(uint32_t) * n);
+           align_up(sizeof(uint32_t) * kRsBins * tiles) +
+           align_up(sizeof(uint32_t) * (size_t)rs_segments((int64_t)tiles)) +
+           4 * align_up(sizeof(uint32_t) * n);
 }
 
 RsWs carve_rs(void* ws, const hs_db* db) {
@@ -657,6 +659,8 @@ RsWs carve_rs(void* ws, const hs_db* db) {
     p += align_up(sizeof(RsState));
     r.hist = (uint32_t*)p;
     p += align_up(sizeof(uint32_t) * kRsBins * tiles);
+    r.part = (uint32_t*)p;
+    p += align_up(sizeof(uint32_t) * (size_t)rs_segments((int64_t)tiles));
     r.v[0] = (uint32_t*)p;
     p += align_up(sizeof(uint32_t) * n);
     r.v[1] = (uint32_t*)p;
@@ -687,7 +691,10 @@ int launch_threshold(const hs_db* db, const uint8_t* d_q, int32_t qlen, const hs
     for (int pass = 0; pass < 4; ++pass) {
         hipLaunchKernelGGL(k_rs_hist, dim3(tiles), dim3(kRsThreads), 0, st, pass,
                            (const int32_t*)w.scores, n, (const TopkState*)w.topk, r, tiles);
-        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(kRsScanThreads), 0, st, pass, r, tiles);
+        const int64_t L = (int64_t)kRsBins * tiles, G = rs_segments(tiles);
+        hipLaunchKernelGGL(k_rs_scan_reduce, dim3((unsigned)G), dim3(kRsThreads), 0, st, pass, r, L);
+        hipLaunchKernelGGL(k_rs_scan_top, dim3(1), dim3(kRsScanThreads), 0, st, pass, r, G);
+        hipLaunchKernelGGL(k_rs_scan_down, dim3((unsigned)G), dim3(kRsThreads), 0, st, pass, r, L);
         hipLaunchKernelGGL(k_rs_scatter, dim3(tiles), dim3(kRsThreads), 0, st, pass,
                            (const int32_t*)w.scores, n, (const TopkState*)w.topk, r, tiles);
     }

@@ -11,10 +11,11 @@
 // zero for every key would leave the order unchanged: it is skipped, and
 // so are all later passes (their digits are zero too).
 //
-// A pass is three launches: per-tile digit histograms, one exclusive scan
-// over (digit, tile), and a stable scatter in which every tile places its
-// keys round by round, a wavefront's equal digits ranked by lane order
-// (ballots over the digit bits), wavefronts in order.
+// A pass is per-tile digit histograms, an exclusive scan over (digit, tile)
+// (segment sums, a scan of those, then each segment scanned with its
+// offset), and a stable scatter in which every tile places its keys round by
+// round, a wavefront's equal digits ranked by lane order (ballots over the
+// digit bits), wavefronts in order.
 #pragma once
 
 #include "device_common.hpp"
@@ -28,6 +29,7 @@ constexpr int kRsRounds = 8;
 constexpr int kRsTile = kRsThreads * kRsRounds;   // keys per tile
 constexpr int kRsBins = 256;
 constexpr int kRsScanThreads = 1024;
+constexpr int kRsSeg = 4 * kRsThreads;        // histogram entries per scan segment
 
 struct RsState {
     uint32_t m;         // eligible targets
@@ -39,11 +41,16 @@ struct RsState {
 struct RsWs {
     RsState* st;
     uint32_t* hist;     // [kRsBins][tiles], digit-major
+    uint32_t* part;     // one sum per scan segment of hist
     uint32_t* v[2];     // keys, ping-pong
     int32_t* id[2];
 };
 
 __host__ __device__ inline int64_t rs_tiles(int64_t n) { return (n + kRsTile - 1) / kRsTile; }
+// Scan segments of a histogram of `tiles` tiles.
+__host__ __device__ inline int64_t rs_segments(int64_t tiles) {
+    return (kRsBins * tiles + kRsSeg - 1) / kRsSeg;
+}
 
 // A pass p > 0 runs only if some key has a non-zero digit p or above.
 __device__ __forceinline__ bool rs_pass_live(const RsState* st, int pass) {
@@ -131,30 +138,86 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(int pass, const int32_t*
     }
 }
 
-// Exclusive scan of hist (kRsBins * ntiles entries) in place, one workgroup.
-__global__ __launch_bounds__(kRsScanThreads) void k_rs_scan(int pass, RsWs w, int32_t ntiles) {
-    __shared__ uint32_t part[kRsScanThreads];
-    if (!rs_pass_live(w.st, pass)) return;
-    const int64_t L = (int64_t)kRsBins * ntiles;
-    const int64_t per = (L + kRsScanThreads - 1) / kRsScanThreads;
-    const int64_t lo = threadIdx.x * per;
-    const int64_t hi = lo + per < L ? lo + per : L;
-    uint32_t sum = 0;
-    for (int64_t i = lo; i < hi; ++i) sum += w.hist[i];
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    // inclusive scan of the per-thread sums (Hillis-Steele)
-    for (int off = 1; off < kRsScanThreads; off <<= 1) {
-        const uint32_t add = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += add;
-        __syncthreads();
+// Inclusive prefix sum over the wavefront (all lanes active).
+__device__ __forceinline__ uint32_t rs_wave_inclusive(uint32_t x, int lane) {
+    for (int o = 1; o < kLanes; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, kLanes);
+        if (lane >= o) x += y;
     }
-    uint32_t run = part[threadIdx.x] - sum;
-    for (int64_t i = lo; i < hi; ++i) {
-        const uint32_t c = w.hist[i];
-        w.hist[i] = run;
-        run += c;
+    return x;
+}
+
+// The scan of hist (L = kRsBins * ntiles entries, a multiple of 4) in three
+// launches.  First the sum of each segment of kRsSeg entries, one workgroup
+// per segment, each thread reading four consecutive entries.
+__global__ __launch_bounds__(kRsThreads) void k_rs_scan_reduce(int pass, RsWs w, int64_t L) {
+    __shared__ uint32_t wsum[kRsWaves];
+    if (!rs_pass_live(w.st, pass)) return;
+    const int64_t i = (int64_t)blockIdx.x * kRsSeg + 4 * (int64_t)threadIdx.x;
+    uint32_t s = 0;
+    if (i < L) {
+        const uint4 v = *(const uint4*)(w.hist + i);
+        s = v.x + v.y + v.z + v.w;
+    }
+    for (int o = kLanes / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kLanes);
+    if ((threadIdx.x & (kLanes - 1)) == 0) wsum[threadIdx.x / kLanes] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int k = 0; k < kRsWaves; ++k) t += wsum[k];
+        w.part[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of the G segment sums in place, one workgroup, 1,024 at a
+// time with the running total carried over.
+__global__ __launch_bounds__(kRsScanThreads) void k_rs_scan_top(int pass, RsWs w, int64_t G) {
+    constexpr int kW = kRsScanThreads / kLanes;
+    __shared__ uint32_t tot[kW];
+    if (!rs_pass_live(w.st, pass)) return;
+    const int lane = threadIdx.x & (kLanes - 1), wave = threadIdx.x / kLanes;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < G; base += kRsScanThreads) {
+        const int64_t i = base + threadIdx.x;
+        const uint32_t v = i < G ? w.part[i] : 0u;
+        const uint32_t inc = rs_wave_inclusive(v, lane);
+        if (lane == kLanes - 1) tot[wave] = inc;
+        __syncthreads();
+        uint32_t before = carry, all = carry;
+        for (int k = 0; k < kW; ++k) {
+            before += k < wave ? tot[k] : 0u;
+            all += tot[k];
+        }
+        if (i < G) w.part[i] = before + inc - v;
+        __syncthreads();              // tot is rewritten by the next chunk
+        carry = all;
+    }
+}
+
+// Each segment's exclusive scan plus the segment's offset, written back.
+__global__ __launch_bounds__(kRsThreads) void k_rs_scan_down(int pass, RsWs w, int64_t L) {
+    __shared__ uint32_t wsum[kRsWaves];
+    if (!rs_pass_live(w.st, pass)) return;
+    const int64_t i = (int64_t)blockIdx.x * kRsSeg + 4 * (int64_t)threadIdx.x;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (i < L) v = *(const uint4*)(w.hist + i);
+    const uint32_t t = v.x + v.y + v.z + v.w;
+    const int lane = threadIdx.x & (kLanes - 1), wave = threadIdx.x / kLanes;
+    const uint32_t inc = rs_wave_inclusive(t, lane);
+    if (lane == kLanes - 1) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t run = w.part[blockIdx.x] + inc - t;
+    for (int k = 0; k < wave; ++k) run += wsum[k];
+    if (i < L) {
+        uint4 o;
+        o.x = run;
+        run += v.x;
+        o.y = run;
+        run += v.y;
+        o.z = run;
+        run += v.z;
+        o.w = run;
+        *(uint4*)(w.hist + i) = o;
     }
 }
 
