@@ -51,16 +51,26 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-SCORING_SOURCES = ("device_common.hpp", "score_kernels.hpp", "hs_lib.hip")
+SCORING_SOURCES = ("device_common.hpp", "score_kernels.hpp")
+
+
+def _launch_text(src):
+    """The part of hs_lib.hip that sizes and launches the one-query scoring
+    kernel: from query_layout through the end of launch_score (with the
+    constants between them)."""
+    i = src.index("\nint query_layout(")
+    j = src.index("\n}\n", src.index("\nint launch_score(", i))
+    return src[i:j + 3]
 
 
 def kernel_source_hash():
-    """Hash of the sources the scoring kernel and its launch are built from
-    (the device code and the host code that sizes and launches it)."""
+    """Hash of the sources the scoring kernel and its launch are built from:
+    the device code and the host code that sizes and launches it."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1508_06561_amd", "csrc")
     for f in SCORING_SOURCES:
         h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(_launch_text(open(os.path.join(csrc, "hs_lib.hip")).read()).encode())
     return h.hexdigest()[:16]
 
 
