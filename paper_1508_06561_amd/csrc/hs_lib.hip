@@ -1628,18 +1628,26 @@ int hs_sw_scores_dev(const hs_db* db, const uint8_t* d_qcodes, int32_t qlen, con
     const size_t lds = (size_t)kNsym * (size_t)qp;
     const void* fn = (const void*)k_sw_scores;
     if ((rc = set_lds_limit(fn, lds))) return rc;
-    // Targets whose one-lane sweep (a step per letter and 16-row pass) would
-    // outlast half the wavefront sweep of the longest target (a step per
-    // letter, plus 63, and 1,024-row pass) take a wavefront each: the lanes
-    // near the threshold share their SIMDs with other wavefronts, and at half
-    // the full search ran in 62 ms instead of 72 (a quarter gained nothing).
     const int64_t lane_passes = (qlen + kSwRows - 1) / kSwRows;
     const int64_t wave_passes = (qlen + kSwWaveRows - 1) / kSwWaveRows;
-    const int64_t thr = wave_passes * ((int64_t)db->lens_desc[0] + kLanes - 1) / (2 * lane_passes);
+    const int32_t G = sw_group_lanes(qlen);
+    // Queries of one pass: a group of G lanes sweeps a target in tlen + G - 1
+    // steps against the lane role's G passes of tlen steps with a boundary
+    // written and read between passes, so every target of at least
+    // kSwGroupMin * G letters takes a group (the full workload: 61.5 ms when
+    // one target held a wavefront whatever the query's length, 20.3 ms from
+    // 2 G letters on, 19.9 ms from G on).  Longer queries: targets whose
+    // one-lane sweep would outlast half the wavefront sweep of the longest
+    // target take a wavefront each (at half the threshold the lanes near it,
+    // which share their SIMDs, ran 62 ms instead of 72; a quarter gained nothing).
+    const int64_t thr = G < kLanes ? (int64_t)kSwGroupMin * G - 1
+                                   : wave_passes * ((int64_t)db->lens_desc[0] + kLanes - 1) /
+                                         (2 * lane_passes);
     const int32_t n_long = (int32_t)(std::partition_point(db->lens_desc.begin(), db->lens_desc.end(),
                                                           [&](int32_t L) { return L > thr; }) -
                                      db->lens_desc.begin());
-    const int64_t wave_blocks = (n_long + kSwThreads / kLanes - 1) / (kSwThreads / kLanes);
+    const int64_t per_block = (int64_t)(kSwThreads / kLanes) * (kLanes / G);
+    const int64_t wave_blocks = (n_long + per_block - 1) / per_block;
     const int64_t grid = wave_blocks + (db->n_targets - n_long + kSwThreads - 1) / kSwThreads;
     hipLaunchKernelGGL(k_sw_scores, dim3((unsigned)grid), dim3(kSwThreads), lds, (hipStream_t)stream,
                        db->view(), n_long, d_qcodes, qlen, qp, kmatrix(params), params->gop,

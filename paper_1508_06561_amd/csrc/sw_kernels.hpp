@@ -26,6 +26,7 @@ constexpr int kSwRows = 16;          // query rows per pass: one 16-byte profile
 constexpr int kSwThreads = 256;
 constexpr int kSwWaveRows = kSwRows * kLanes;    // query rows per pass of the wavefront role
 constexpr int32_t kSwNeg = -(1 << 29);   // minus infinity; one subtraction stays in range
+constexpr int32_t kSwGroupMin = 1;       // shortest group-role target, in group lanes
 
 // Query profile bytes in LDS for a query of qlen letters.
 __host__ __device__ inline int32_t sw_profile_stride(int32_t qlen) {
@@ -98,23 +99,32 @@ __device__ __forceinline__ int32_t sw_lane(const uint8_t* __restrict__ t, int32_
     return best;
 }
 
-// Wavefront role: the whole target on one wavefront, in passes of
-// kSwWaveRows query rows.  Lane l holds rows [p0 + 16 l, p0 + 16 l + 16) and
-// works one column behind lane l - 1, whose bottom row it takes by a one-lane
-// shift at each step, so that a pass takes tlen + 63 steps.  Lane 0 reads the
-// previous pass's bottom row from cb, lane 63 writes its own there.  Returns
-// the best cell of the whole matrix on every lane.
-__device__ __forceinline__ int32_t sw_wave(int32_t lane, const uint8_t* __restrict__ t,
-                                           int32_t tlen, int2* __restrict__ cb,
-                                           const uint8_t* prof, int32_t qlen, int32_t qp,
-                                           int32_t gop, int32_t gep) {
+// Wavefront role: a target on a group of G consecutive lanes of a
+// wavefront (G = 64 for queries longer than one pass of kSwWaveRows rows;
+// otherwise G = ceil(qlen / kSwRows), so that 64 / G targets share the
+// wavefront and the lanes past the query's rows are not left idle), in
+// passes of G * kSwRows query rows.  Lane ll of a group holds rows
+// [p0 + 16 ll, p0 + 16 ll + 16) and works one column behind lane ll - 1,
+// whose bottom row it takes by a one-lane shift at each step, so that a
+// pass takes tlen + G - 1 steps.  Lane 0 of the group reads the previous
+// pass's bottom row from cb, lane G - 1 writes its own there.  `active`
+// lanes belong to a group with a target.  Returns each lane's best cell; the
+// group's best is the maximum over its lanes.
+__device__ __forceinline__ int32_t sw_wave(int32_t lane, int32_t G, bool active,
+                                           const uint8_t* __restrict__ t, int32_t tlen,
+                                           int2* __restrict__ cb, const uint8_t* prof, int32_t qlen,
+                                           int32_t qp, int32_t gop, int32_t gep) {
+    const int32_t ll = lane % G;
+    int32_t steps = active ? tlen + G - 1 : 0;     // the same for every lane: the longest group
+    for (int o = kLanes / 2; o >= 1; o >>= 1) steps = max(steps, __shfl_xor(steps, o));
+    const int32_t rows_pass = G * kSwRows;
     int32_t best = 0;
-    for (int32_t p0 = 0; p0 < qlen; p0 += kSwWaveRows) {
+    for (int32_t p0 = 0; p0 < qlen; p0 += rows_pass) {
         const bool first = p0 == 0;
-        const bool last = p0 + kSwWaveRows >= qlen;
-        const int32_t i0 = p0 + lane * kSwRows;
+        const bool last = p0 + rows_pass >= qlen;
+        const int32_t i0 = p0 + ll * kSwRows;
         const int32_t valid = qlen - i0;          // rows r < valid are query rows
-        const bool has_rows = valid > 0;          // lanes past the query skip the work
+        const bool has_rows = active && valid > 0;
         const int32_t i0c = has_rows ? i0 : 0;
         int32_t H[kSwRows], Fr[kSwRows];
 #pragma unroll
@@ -124,43 +134,47 @@ __device__ __forceinline__ int32_t sw_wave(int32_t lane, const uint8_t* __restri
         }
         int32_t top_prev = 0;
         int32_t out_h = 0, out_v = kSwNeg;        // this lane's bottom row at its last column
-        int32_t c_next = lane == 0 ? t[0] : 0;    // step 0 works on column -lane
-        int2 b_next = (lane == 0 && !first) ? cb[0] : make_int2(0, kSwNeg);
-        const int32_t steps = tlen + kLanes - 1;
+        int32_t c_next = (ll == 0 && active) ? t[0] : 0;    // step 0 works on column -ll
+        int2 b_next = (ll == 0 && active && !first) ? cb[0] : make_int2(0, kSwNeg);
         for (int32_t st = 0; st < steps; ++st) {
-            const int32_t j = st - lane;
+            const int32_t j = st - ll;
             int32_t up = __shfl_up(out_h, 1);
             int32_t v = __shfl_up(out_v, 1);
-            if (lane == 0) {
+            if (ll == 0) {
                 up = b_next.x;
                 v = b_next.y;
             }
             const int32_t c = c_next;
             const int32_t jn = j + 1;
-            if (jn >= 0 && jn < tlen) {
+            if (active && jn >= 0 && jn < tlen) {
                 c_next = t[jn];
-                if (lane == 0 && !first) b_next = cb[jn];
+                if (ll == 0 && !first) b_next = cb[jn];
             }
             if (j >= 0 && j < tlen && has_rows) {
                 const uint4 sv = *(const uint4*)(prof + c * qp + i0c);
                 sw_column(sv, H, Fr, top_prev, up, v, best, valid, gop, gep);
                 out_h = up;
                 out_v = v;
-                if (lane == kLanes - 1 && !last) cb[j] = make_int2(up, v);
+                if (ll == G - 1 && !last) cb[j] = make_int2(up, v);
             }
         }
-        __threadfence_block();   // lane 63's boundary stores land before lane 0 reads them
+        __threadfence_block();   // lane G - 1's boundary stores land before lane 0 reads them
     }
-    for (int o = kLanes / 2; o >= 1; o >>= 1) best = max(best, __shfl_xor(best, o));
     return best;
+}
+
+// Lanes per wavefront-role target: one pass of up to kSwWaveRows rows on as
+// few lanes as hold the query, or the whole wavefront for longer queries.
+__host__ __device__ inline int32_t sw_group_lanes(int32_t qlen) {
+    return qlen > kSwWaveRows ? kLanes : (qlen + kSwRows - 1) / kSwRows;
 }
 
 // scores[t] = optimal local score of the query against target t (index
 // order).  The n_long longest targets (order[0 .. n_long - 1]) take the
-// wavefront role, one per wavefront, in the first ceil(n_long / 4)
-// workgroups; the others take the lane role, one per lane.  col: workspace
-// of one int2 per database letter (index as the letters).  LDS: kNsym * qp
-// bytes.
+// wavefront role, 64 / G to a wavefront (G = sw_group_lanes(qlen)), in the
+// first workgroups; the others take the lane role, one per lane.  col:
+// workspace of one int2 per database letter (index as the letters).  LDS:
+// kNsym * qp bytes.
 __global__ __launch_bounds__(kSwThreads) void k_sw_scores(
     DbView db, int32_t n_long, const uint8_t* __restrict__ q, int32_t qlen, int32_t qp, KMatrix km,
     int32_t gop, int32_t gep, int2* __restrict__ col, int32_t* __restrict__ scores) {
@@ -173,16 +187,27 @@ __global__ __launch_bounds__(kSwThreads) void k_sw_scores(
     }
     __syncthreads();
     constexpr int kWavesPerBlock = kSwThreads / kLanes;
-    const int32_t wave_blocks = (n_long + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int32_t G = sw_group_lanes(qlen), NG = kLanes / G;
+    const int32_t per_block = kWavesPerBlock * NG;
+    const int32_t wave_blocks = (n_long + per_block - 1) / per_block;
     if ((int32_t)blockIdx.x < wave_blocks) {
         const int32_t w = (int32_t)blockIdx.x * kWavesPerBlock + (int32_t)(threadIdx.x / kLanes);
-        if (w >= n_long) return;                  // uniform over the wavefront
+        if (w * NG >= n_long) return;             // uniform over the wavefront
         const int32_t lane = threadIdx.x & (kLanes - 1);
-        const int32_t tgt = db.order[w];
-        const int64_t off = db.offsets[tgt];
-        const int32_t best = sw_wave(lane, db.letters + off, db.lens[tgt], col + off, sw_prof, qlen,
+        const int32_t g = lane / G, slot = w * NG + g;
+        const bool active = g < NG && slot < n_long;
+        const int32_t tgt = active ? db.order[slot] : 0;
+        const int64_t off = active ? db.offsets[tgt] : 0;
+        const int32_t tlen = active ? db.lens[tgt] : 0;
+        const int32_t best = sw_wave(lane, G, active, db.letters + off, tlen, col + off, sw_prof, qlen,
                                      qp, gop, gep);
-        if (lane == 0) scores[tgt] = best;
+        // the group's best: lane 0 of the group takes the maximum over its lanes
+        int32_t gb = best;
+        for (int32_t k = 1; k < G; ++k) {
+            const int32_t o = __shfl(best, lane + k < kLanes ? lane + k : lane);
+            if (lane % G + k < G) gb = max(gb, o);
+        }
+        if (active && lane % G == 0) scores[tgt] = gb;
         return;
     }
     const int64_t g = (int64_t)(blockIdx.x - wave_blocks) * blockDim.x + threadIdx.x + n_long;

@@ -60,9 +60,11 @@ def tiny():
     db.close()
 
 
-@pytest.mark.parametrize("qlen", [1, 2, 15, 16, 17, 31, 33, 64, 300])
+@pytest.mark.parametrize("qlen", [1, 2, 15, 16, 17, 31, 33, 64, 300, 700, 1000, 1024, 1025, 1100])
 def test_tiny_every_score(tiny, qlen):
-    """Every target, query lengths around the 16-row pass (ragged last pass)."""
+    """Every target, query lengths around the 16-row pass (ragged last
+    pass), lane groups of 1 to 64 lanes sharing a wavefront, and around the
+    1,024-row wavefront pass (one pass of 63 or 64 lanes, then two passes)."""
     w, codes, db = tiny
     rng = np.random.default_rng(100 + qlen)
     q = query(rng, qlen, ALPHA)
