@@ -19,8 +19,11 @@
 
 namespace hs {
 
-constexpr int kAlThreads = 256;
+constexpr int kAlThreads = 256;                  // threads per (pair, round) of short pairs
 constexpr int kAlWaves = kAlThreads / kLanes;
+constexpr int kAlThreadsLong = 1024;             // of batches holding a long pair
+constexpr int kAlWavesMax = kAlThreadsLong / kLanes;
+constexpr int kAlLongPair = 4000;                // letters: a long pair
 constexpr int kAlMaxLen = 5600;    // longest sequence of the pairwise mode
 
 // One pair of a pairwise batch: query codes at qoff, target codes at toff.
@@ -32,7 +35,7 @@ struct AlignPair {
 
 struct AlignLds {
     int8_t mat[kNsym * kNsym];
-    uint64_t wbest[kAlWaves];
+    uint64_t wbest[kAlWavesMax];
     uint8_t L[kAlMaxLen], S[kAlMaxLen];
 };
 
@@ -69,10 +72,11 @@ __device__ __forceinline__ void al_emit(uint32_t* ops, int32_t& n_ops, uint32_t 
     else ops[n_ops++] = ((uint32_t)n << 2) | op;
 }
 
-// One round of pair `id` by the whole workgroup: the round's score (SCORE of
-// its aligned rows, streamed step by step) and, with kEmit, its ops written
-// by thread 0.  L / S (lengths nl >= ns) are in LDS; tl: the target is L.
-template <bool kEmit>
+// One round of pair `id` by the whole workgroup of kT threads: the round's
+// score (SCORE of its aligned rows, streamed step by step) and, with kEmit,
+// its ops written by thread 0.  L / S (lengths nl >= ns) are in LDS; tl: the
+// target is L.
+template <int kT, bool kEmit>
 __device__ int32_t al_round(AlignLds& A, int32_t nl, int32_t ns, bool tl, const KParams& kp,
                             int32_t id, int32_t round, uint32_t* ops, int32_t* n_ops_out) {
     const int32_t tid = threadIdx.x, lane = tid & (kLanes - 1), wave = tid / kLanes;
@@ -93,7 +97,7 @@ __device__ int32_t al_round(AlignLds& A, int32_t nl, int32_t ns, bool tl, const 
         // other are small j in [max(0, -k), min(ss, ls - k))
         const int32_t np = ls + ss - 1;
         uint64_t best = 0;
-        for (int32_t i = tid; i < np; i += kAlThreads) {
+        for (int32_t i = tid; i < np; i += kT) {
             const int32_t k = i - ss + 1;
             const int32_t j0 = k < 0 ? -k : 0;
             const int32_t j1 = ss < ls - k ? ss : ls - k;
@@ -108,7 +112,7 @@ __device__ int32_t al_round(AlignLds& A, int32_t nl, int32_t ns, bool tl, const 
         if (lane == 0) A.wbest[wave] = best;
         __syncthreads();
         uint64_t b = A.wbest[0];
-        for (int w = 1; w < kAlWaves; ++w) b = A.wbest[w] > b ? A.wbest[w] : b;
+        for (int w = 1; w < kT / kLanes; ++w) b = A.wbest[w] > b ? A.wbest[w] : b;
         __syncthreads();          // wbest is rewritten by the next step
         const int32_t k = key_shift(b) - ss + 1;
         const int32_t D = key_score(b);
@@ -154,7 +158,8 @@ __device__ int32_t al_round(AlignLds& A, int32_t nl, int32_t ns, bool tl, const 
     return score;
 }
 
-// Stages pair p in LDS as (large, small); returns (nl, ns, tl).
+// Stages pair p in LDS as (large, small) with kT threads; returns (nl, ns, tl).
+template <int kT>
 __device__ __forceinline__ void al_stage(AlignLds& A, const AlignPair& P, const uint8_t* codes,
                                          const KMatrix& km, int32_t& nl, int32_t& ns, bool& tl) {
     tl = P.tlen >= P.qlen;
@@ -162,15 +167,16 @@ __device__ __forceinline__ void al_stage(AlignLds& A, const AlignPair& P, const 
     ns = tl ? P.qlen : P.tlen;
     const uint8_t* src_l = codes + (tl ? P.toff : P.qoff);
     const uint8_t* src_s = codes + (tl ? P.qoff : P.toff);
-    for (int32_t i = threadIdx.x; i < nl; i += kAlThreads) A.L[i] = src_l[i];
-    for (int32_t i = threadIdx.x; i < ns; i += kAlThreads) A.S[i] = src_s[i];
-    for (int32_t i = threadIdx.x; i < kNsym * kNsym; i += kAlThreads) A.mat[i] = km.m[i];
+    for (int32_t i = threadIdx.x; i < nl; i += kT) A.L[i] = src_l[i];
+    for (int32_t i = threadIdx.x; i < ns; i += kT) A.S[i] = src_s[i];
+    for (int32_t i = threadIdx.x; i < kNsym * kNsym; i += kT) A.mat[i] = km.m[i];
     __syncthreads();
 }
 
 // Round blockIdx.x % rounds of pair blockIdx.x / rounds: its score to
-// round_scores[pair * rounds + round].
-__global__ __launch_bounds__(kAlThreads) void k_align_rounds(const AlignPair* __restrict__ pairs,
+// round_scores[pair * rounds + round].  kT threads per workgroup.
+template <int kT>
+__global__ __launch_bounds__(kT) void k_align_rounds(const AlignPair* __restrict__ pairs,
                                                              const uint8_t* __restrict__ codes,
                                                              KParams kp, KMatrix km,
                                                              int32_t* __restrict__ round_scores) {
@@ -178,14 +184,15 @@ __global__ __launch_bounds__(kAlThreads) void k_align_rounds(const AlignPair* __
     const int32_t pair = blockIdx.x / kp.rounds, round = blockIdx.x % kp.rounds;
     int32_t nl, ns;
     bool tl;
-    al_stage(A, pairs[pair], codes, km, nl, ns, tl);
-    const int32_t s = al_round<false>(A, nl, ns, tl, kp, pair, round, nullptr, nullptr);
+    al_stage<kT>(A, pairs[pair], codes, km, nl, ns, tl);
+    const int32_t s = al_round<kT, false>(A, nl, ns, tl, kp, pair, round, nullptr, nullptr);
     if (threadIdx.x == 0) round_scores[(int64_t)pair * kp.rounds + round] = s;
 }
 
 // Pair blockIdx.x: its best round (the first with the highest score),
 // replayed into ops at ops + pairs[p].ops_off; score, round and op count out.
-__global__ __launch_bounds__(kAlThreads) void k_align_replay(const AlignPair* __restrict__ pairs,
+template <int kT>
+__global__ __launch_bounds__(kT) void k_align_replay(const AlignPair* __restrict__ pairs,
                                                              const uint8_t* __restrict__ codes,
                                                              KParams kp, KMatrix km,
                                                              const int32_t* __restrict__ round_scores,
@@ -205,8 +212,8 @@ __global__ __launch_bounds__(kAlThreads) void k_align_replay(const AlignPair* __
     int32_t nl, ns;
     bool tl;
     const AlignPair P = pairs[pair];
-    al_stage(A, P, codes, km, nl, ns, tl);
-    const int32_t s = al_round<true>(A, nl, ns, tl, kp, pair, best_r, ops + P.ops_off, n_ops + pair);
+    al_stage<kT>(A, P, codes, km, nl, ns, tl);
+    const int32_t s = al_round<kT, true>(A, nl, ns, tl, kp, pair, best_r, ops + P.ops_off, n_ops + pair);
     if (threadIdx.x == 0) {
         scores[pair] = s;        // equal to best: the replay is the same round
         rounds[pair] = best_r;

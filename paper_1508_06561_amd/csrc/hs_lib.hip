@@ -1512,9 +1512,10 @@ int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char*
     int rc = check_params(params);
     if (rc) return rc;
     if ((int64_t)n * params->rounds > 0x7FFFFFFF) return fail(HS_EINVAL, "n * rounds too large");
-    int64_t nq = 0, nt = 0, nops = 0;
+    int64_t nq = 0, nt = 0, nops = 0, longest = 0;
     for (int32_t i = 0; i < n; ++i) {
         const int64_t a = qoff[i + 1] - qoff[i], b = toff[i + 1] - toff[i];
+        longest = std::max(longest, std::max(a, b));
         if (a < 1 || a > HS_MAX_ALIGN || b < 1 || b > HS_MAX_ALIGN)
             return fail(HS_EINVAL, "pair " + std::to_string(i) + ": lengths must lie in [1, HS_MAX_ALIGN]");
         nq += a;
@@ -1563,12 +1564,28 @@ int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char*
         rc = fail(HS_EDEVICE, "pair upload failed");
     if (!rc) {
         const AlignPair* d_pairs = (const AlignPair*)(d + o_pairs);
-        hipLaunchKernelGGL(k_align_rounds, dim3((unsigned)((int64_t)n * params->rounds)), dim3(kAlThreads),
-                           0, st, d_pairs, (const uint8_t*)(d + o_codes), kp, km, (int32_t*)(d + o_rs));
-        hipLaunchKernelGGL(k_align_replay, dim3((unsigned)n), dim3(kAlThreads), 0, st, d_pairs,
-                           (const uint8_t*)(d + o_codes), kp, km, (const int32_t*)(d + o_rs),
-                           (int32_t*)(d + o_sc), (int32_t*)(d + o_rd), (int32_t*)(d + o_no),
-                           (uint32_t*)(d + o_ops));
+        const uint8_t* d_codes = (const uint8_t*)(d + o_codes);
+        const unsigned nr = (unsigned)((int64_t)n * params->rounds);
+        // a batch holding a pair of kAlLongPair letters or more gives each
+        // (pair, round) 1,024 threads: a step of a long pair has thousands of
+        // placements (the 5,600 x 5,600 pair at Rounds 20: 5.8 ms with 256
+        // threads, 1.6 ms with 1,024); batches of shorter pairs keep 256 (1,000
+        // pairs of up to 2,000 letters took 3.9 ms instead of 2.0 with 1,024)
+        if (longest >= kAlLongPair) {
+            hipLaunchKernelGGL(k_align_rounds<kAlThreadsLong>, dim3(nr), dim3(kAlThreadsLong), 0, st,
+                               d_pairs, d_codes, kp, km, (int32_t*)(d + o_rs));
+            hipLaunchKernelGGL(k_align_replay<kAlThreadsLong>, dim3((unsigned)n), dim3(kAlThreadsLong), 0,
+                               st, d_pairs, d_codes, kp, km, (const int32_t*)(d + o_rs),
+                               (int32_t*)(d + o_sc), (int32_t*)(d + o_rd), (int32_t*)(d + o_no),
+                               (uint32_t*)(d + o_ops));
+        } else {
+            hipLaunchKernelGGL(k_align_rounds<kAlThreads>, dim3(nr), dim3(kAlThreads), 0, st, d_pairs,
+                               d_codes, kp, km, (int32_t*)(d + o_rs));
+            hipLaunchKernelGGL(k_align_replay<kAlThreads>, dim3((unsigned)n), dim3(kAlThreads), 0, st,
+                               d_pairs, d_codes, kp, km, (const int32_t*)(d + o_rs),
+                               (int32_t*)(d + o_sc), (int32_t*)(d + o_rd), (int32_t*)(d + o_no),
+                               (uint32_t*)(d + o_ops));
+        }
         hipLaunchKernelGGL(k_align_ops_scan, dim3(1), dim3(kAlScanThreads), 0, st,
                            (const int32_t*)(d + o_no), n, (int64_t*)(d + o_off));
         hipLaunchKernelGGL(k_align_ops_pack, dim3((unsigned)((n + kAlWaves - 1) / kAlWaves)), dim3(kAlThreads),
