@@ -774,6 +774,8 @@ struct hs_batch {
     bool ilp = false;                   // high-ILP letter loop (see prefer_ilp)
     int32_t grid = 0, n_items = 0;
     int32_t waves = kWaves;             // wavefronts per workgroup (LDS permitting)
+    bool lmode = false;                 // scoring with WaveLdsLong records (see choose_schedule)
+    int32_t swaves = kWaves;            // the scoring kernel's wavefronts per workgroup
     // alignment pass: hits per work item, in flight per wavefront, workgroups
     int32_t tchunk = 0, tcap = 0, tgrid = 0, n_titems = 0;
     bool trace_one = false;          // alignments one hit per wavefront
@@ -851,6 +853,34 @@ const void* batch_kernel(int copies, bool count, bool ilp) {
 
 size_t batch_lds(const hs_batch* b, int copies) {
     return batch_prof_bytes(b->cur_max_qlen, copies) + sizeof(WaveLds) * b->waves;
+}
+// LDS and kernel of the batch's scoring launch (the wavefront records of
+// the long mode are smaller, and its workgroups larger).
+size_t batch_lds_score(const hs_batch* b, int copies) {
+    return b->lmode ? batch_prof_bytes(b->cur_max_qlen, copies) + sizeof(WaveLdsLong) * b->swaves
+                    : batch_lds(b, copies);
+}
+
+// (the cell-counting long kernel, which runs once per batch to measure the
+// work, keeps the default letter loop: the high-ILP one would spill there)
+template <int kCopies, bool kCount>
+const void* batch_fn_long(bool ilp) {
+    return ilp && !kCount ? (const void*)k_score_batch<kCopies, kCount, !kCount, true>
+                          : (const void*)k_score_batch<kCopies, kCount, false, true>;
+}
+
+const void* batch_kernel_score(const hs_batch* b, bool count) {
+    if (!b->lmode) return batch_kernel(b->copies, count, b->ilp);
+    if (b->copies == 4) return count ? batch_fn_long<4, true>(b->ilp) : batch_fn_long<4, false>(b->ilp);
+    return count ? batch_fn_long<1, true>(b->ilp) : batch_fn_long<1, false>(b->ilp);
+}
+
+// Wavefronts of up to kLongWaves whose long-mode records fit in the LDS
+// beside a profile of prof_bytes.
+int fit_waves_long(size_t prof_bytes) {
+    for (int w = kLongWaves; w >= 1; --w)
+        if (prof_bytes + sizeof(WaveLdsLong) * w + 16 <= device_lds_limit()) return w;
+    return 0;
 }
 
 // Work items for the current queries: longest queries first, each cut into
@@ -930,11 +960,11 @@ int upload_items(hs_batch* b, hipStream_t st) {
                             (int64_t)(titems.size() * sizeof(BatchItem))};
     if (int rc = pull_segments(b, st, off, len, 2)) return rc;
     HIP_TRY(hipStreamSynchronize(st));
-    const void* fn = batch_kernel(b->copies, false, b->ilp);
-    const size_t lds = batch_lds(b, b->copies);
-    const int threads = b->waves * kLanes;
+    const void* fn = batch_kernel_score(b, false);
+    const size_t lds = batch_lds_score(b, b->copies);
+    const int threads = b->swaves * kLanes;
     int rc = set_lds_limit(fn, lds);
-    if (!rc) rc = set_lds_limit(batch_kernel(b->copies, true, b->ilp), lds);
+    if (!rc) rc = set_lds_limit(batch_kernel_score(b, true), lds);
     if (!rc && b->score_one) {
         const bool four = b->copies == 4;
         rc = set_lds_limit(four ? (const void*)k_score_one<4, false> : (const void*)k_score_one<1, false>, lds);
@@ -946,9 +976,9 @@ int upload_items(hs_batch* b, hipStream_t st) {
     if (per_cu < 1) return fail(HS_ENOMEM, "batch scoring kernel does not fit on a compute unit");
     b->grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * device_cus(), b->n_items));
     const void* tfn = b->copies == 4 ? (const void*)k_trace_batch<4> : (const void*)k_trace_batch<1>;
-    if ((rc = set_lds_limit(tfn, lds))) return rc;
+    if ((rc = set_lds_limit(tfn, batch_lds(b, b->copies)))) return rc;
     per_cu = 0;
-    if (int rc_o = occupancy(tfn, threads, lds, &per_cu)) return rc_o;
+    if (int rc_o = occupancy(tfn, b->waves * kLanes, batch_lds(b, b->copies), &per_cu)) return rc_o;
     if (per_cu < 1) return fail(HS_ENOMEM, "batch alignment kernel does not fit on a compute unit");
     b->tgrid = (int32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * device_cus(), b->n_titems));
     drop_graph(b);
@@ -963,6 +993,8 @@ int choose_schedule(hs_batch* b, hipStream_t st) {
     if (!copies_fit(b->cur_max_qlen, b->copies))
         return fail(HS_EINVAL, "profile copies do not fit in LDS for the longest query");
     b->waves = fit_waves(batch_prof_bytes(b->cur_max_qlen, b->copies));
+    b->lmode = false;
+    b->swaves = b->waves;
     b->cap = b->fix_cap ? b->fix_cap : kLanes;
     int rc = prefer_ilp(batch_kernel(b->copies, false, false), batch_kernel(b->copies, false, true),
                         b->waves * kLanes, batch_lds(b, b->copies), &b->ilp);
@@ -1006,6 +1038,14 @@ int choose_schedule(hs_batch* b, hipStream_t st) {
             1, kLettersInFlight / std::max<int32_t>(b->db->median_len, 1));
         b->cap = std::min(std::min(kLanes, by_len), std::max(1, (b->chunk + b->waves - 1) / b->waves));
     }
+    // Long mode: with at most kLongSlots pairs in flight per wavefront, the
+    // smaller WaveLdsLong records let more wavefronts share the LDS beside a
+    // long query's profile (16 instead of 8 for the long-sequence batch,
+    // whose 4,834-letter profile takes 121 KB): 93 ms -> 77 ms there, with 4
+    // pairs in flight.
+    const int32_t lw = fit_waves_long(batch_prof_bytes(b->cur_max_qlen, b->copies));
+    b->lmode = b->cap <= kLongSlots && lw > b->waves;
+    b->swaves = b->lmode ? lw : b->waves;
     return upload_items(b, st);
 }
 
@@ -1018,6 +1058,19 @@ void launch_batch_kernel(const hs_batch* b, hipStream_t st, uint64_t* d_cells) {
                            (const KMatrix*)b->d_mats, (const uint8_t*)b->d_qcodes,
                            (const BatchItem*)b->d_items, b->n_items, b->d_ctr,
                            (int32_t)batch_prof_bytes(b->cur_max_qlen, kCopies),
+                           (const PairRec*)db->d_recs, (const uint8_t*)db->d_letters,
+                           (const uint64_t*)b->d_draws, b->d_scores, b->d_rounds,
+                           (int64_t)db->n_targets, &b->d_st->max_score,
+                           (int32_t)(sizeof(TopkState) / sizeof(int32_t)), (unsigned long long*)d_cells);
+        return;
+    }
+    if (b->lmode) {
+        hipLaunchKernelGGL((k_score_batch<kCopies, kCount, kIlp && !kCount, true>), dim3(b->grid),
+                           dim3(b->swaves * kLanes), batch_lds_score(b, kCopies), st,
+                           (const BatchQuery*)b->d_qs,
+                           (const KMatrix*)b->d_mats, (const uint8_t*)b->d_qcodes,
+                           (const BatchItem*)b->d_items, b->n_items, b->d_ctr,
+                           (int32_t)batch_prof_bytes(b->cur_max_qlen, kCopies), b->cap,
                            (const PairRec*)db->d_recs, (const uint8_t*)db->d_letters,
                            (const uint64_t*)b->d_draws, b->d_scores, b->d_rounds,
                            (int64_t)db->n_targets, &b->d_st->max_score,
@@ -1909,7 +1962,7 @@ int hs_batch_tune(hs_batch* b, void* stream, int32_t reps, float* best_ms) {
         if (chunk_c.empty() || chunk_c.back() != r) chunk_c.push_back(r);
         if (c <= 64) break;
     }
-    const int32_t cap_c[] = {16, 32, 64};
+    const int32_t cap_c[] = {4, 8, 16, 32, 64};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0) (void)hipEventDestroy(e0);

@@ -27,6 +27,7 @@
 //     first and last 7 letters carry cells outside the window: those bytes
 //     are masked with compile-time masks (entry and exit ramps).
 #pragma once
+#include <type_traits>
 
 #include "device_common.hpp"
 #include "topk_kernels.hpp"
@@ -634,8 +635,20 @@ __device__ __forceinline__ void advance_pair(PairState& s, const KParams& kp,
 
 // Wavefront-private LDS: slots, issued blocks, bin counters.
 struct WaveLds {
+    static constexpr int kItems = kItemCap;
     SlotInfo slots[kLanes];
     uint32_t items[kItemCap];
+    uint32_t bins[kBins];
+};
+// The record of a wavefront holding at most kLongSlots pairs, in workgroups
+// of up to kLongWaves wavefronts (batches of long queries, whose profile
+// leaves little LDS: smaller records let more wavefronts share it).
+constexpr int kLongSlots = 16;
+constexpr int kLongWaves = 16;
+struct WaveLdsLong {
+    static constexpr int kItems = 256;
+    SlotInfo slots[kLongSlots];
+    uint32_t items[kItems];
     uint32_t bins[kBins];
 };
 
@@ -682,8 +695,8 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
 // longest first, so that neighbouring lanes get blocks of equal length;
 // every lane then scores blocks, and the best placement of each step is
 // folded into its slot's key in LDS.
-template <int kCopies, bool kIlp = false, int kBits = 8>
-__device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool stepping, bool tl,
+template <int kCopies, bool kIlp = false, int kBits = 8, class WL = WaveLds>
+__device__ __forceinline__ void score_pending(WL& W, int32_t lane, bool stepping, bool tl,
                                               int32_t ss, int32_t& blk, int32_t nblk,
                                               const uint8_t* prof, int32_t ps, int32_t cpb,
                                               int32_t bias, const uint8_t* __restrict__ letters) {
@@ -719,14 +732,14 @@ __device__ __forceinline__ void score_pending(WaveLds& W, int32_t lane, bool ste
         start = (int32_t)(W.bins[bkey] + off);
     }
     if (want > 0) {
-        int32_t issue = kItemCap - start;
+        int32_t issue = WL::kItems - start;
         issue = issue < 0 ? 0 : (issue > want ? want : issue);
         for (int32_t b = 0; b < issue; ++b)
             W.items[start + b] = ((uint32_t)lane << 24) | (uint32_t)(blk + b);
         blk += issue;
     }
     // blocks issued = number of slots' wants, capped
-    const int32_t n_items = (int32_t)(nw < (uint32_t)kItemCap ? nw : (uint32_t)kItemCap);
+    const int32_t n_items = (int32_t)(nw < (uint32_t)WL::kItems ? nw : (uint32_t)WL::kItems);
     wave_sync();
 
     // ---- phase C: score the blocks; each lane fetches the letters of its
@@ -789,8 +802,8 @@ __device__ __forceinline__ uint32_t rank_position(uint32_t r, uint32_t nb) {
 // faster take more of the short tail and all finish together.
 // Returns when no pair is left; scores go to scores[target], the best round
 // to rounds[target].  kExact allows a missing draw table (see pair_draw).
-template <int kCopies, bool kCount, bool kExact, bool kIlp, int kBits = 8>
-__device__ __forceinline__ void wave_pairs(WaveLds& W, int32_t lane, int32_t cap, uint32_t grab,
+template <int kCopies, bool kCount, bool kExact, bool kIlp, int kBits = 8, class WL = WaveLds>
+__device__ __forceinline__ void wave_pairs(WL& W, int32_t lane, int32_t cap, uint32_t grab,
                                            uint32_t stride, uint32_t r0, uint32_t gw,
                                            const uint8_t* prof, int32_t ps, int32_t cpb,
                                            int32_t bias, int32_t qlen, const KParams& kp,
@@ -1196,8 +1209,11 @@ void k_score_sched(
 // profile, then its wavefronts pull the item's pairs from a counter in LDS,
 // at most `cap` in flight per wavefront.  Query q's scores go to
 // scores[q * stride + target], its maximum score to max_score[q * ms_stride].
-template <int kCopies, bool kCount, bool kIlp>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kIlp ? 1 : 4)))
+// kLong: the long mode, WaveLdsLong records and up to kLongWaves wavefronts
+// per workgroup, at most kLongSlots pairs in flight per wavefront.
+template <int kCopies, bool kCount, bool kIlp, bool kLong = false>
+__global__ __launch_bounds__(kLong ? kLongWaves * kLanes : kThreads)
+__attribute__((amdgpu_waves_per_eu(kIlp && !kLong ? 1 : 4)))
 void k_score_batch(
     const BatchQuery* __restrict__ qs, const KMatrix* __restrict__ mats,
     const uint8_t* __restrict__ qcodes, const BatchItem* __restrict__ items, int32_t n_items,
@@ -1208,7 +1224,8 @@ void k_score_batch(
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t s_item, s_ctr;
     const int32_t lane = threadIdx.x & (kLanes - 1);
-    WaveLds& W = ((WaveLds*)(lds + prof_bytes))[threadIdx.x / kLanes];
+    using WL = typename std::conditional<kLong, WaveLdsLong, WaveLds>::type;
+    WL& W = ((WL*)(lds + prof_bytes))[threadIdx.x / kLanes];
     uint64_t cells = 0;
     for (;;) {
         if (threadIdx.x == 0) {
@@ -1228,7 +1245,8 @@ void k_score_batch(
                                threadIdx.x, blockDim.x);
         __syncthreads();
         int32_t best_seen = INT32_MIN;
-        wave_pairs<kCopies, kCount, true, kIlp>(W, lane, cap, 0u, 0u, 0u, 0u, lds, ps, cpb, Q.bias, Q.qlen,
+        wave_pairs<kCopies, kCount, true, kIlp>(W, lane, kLong && cap > kLongSlots ? kLongSlots : cap,
+                                                0u, 0u, 0u, 0u, lds, ps, cpb, Q.bias, Q.qlen,
                                                 Q.kp, recs, item.hi, letters,
                                                 Q.table ? draws : nullptr, &s_ctr,
                                                 scores + (int64_t)q * stride,
