@@ -774,7 +774,7 @@ struct hs_batch {
     bool ilp = false;                   // high-ILP letter loop (see prefer_ilp)
     int32_t grid = 0, n_items = 0;
     int32_t waves = kWaves;             // wavefronts per workgroup (LDS permitting)
-    bool lmode = false;                 // scoring with WaveLdsLong records (see choose_schedule)
+    int32_t rec = 0;                    // the scoring kernel's record kind (see choose_schedule)
     int32_t swaves = kWaves;            // the scoring kernel's wavefronts per workgroup
     // alignment pass: hits per work item, in flight per wavefront, workgroups
     int32_t tchunk = 0, tcap = 0, tgrid = 0, n_titems = 0;
@@ -856,30 +856,50 @@ size_t batch_lds(const hs_batch* b, int copies) {
 }
 // LDS and kernel of the batch's scoring launch (the wavefront records of
 // the long mode are smaller, and its workgroups larger).
-size_t batch_lds_score(const hs_batch* b, int copies) {
-    return b->lmode ? batch_prof_bytes(b->cur_max_qlen, copies) + sizeof(WaveLdsLong) * b->swaves
-                    : batch_lds(b, copies);
+size_t rec_bytes(int rec) {
+    return rec == 1 ? sizeof(WaveLds16) : rec == 2 ? sizeof(WaveLds64) : sizeof(WaveLds);
 }
 
-// (the cell-counting long kernel, which runs once per batch to measure the
-// work, keeps the default letter loop: the high-ILP one would spill there)
-template <int kCopies, bool kCount>
-const void* batch_fn_long(bool ilp) {
-    return ilp && !kCount ? (const void*)k_score_batch<kCopies, kCount, !kCount, true>
-                          : (const void*)k_score_batch<kCopies, kCount, false, true>;
+size_t batch_lds_score(const hs_batch* b, int copies) {
+    return b->rec ? batch_prof_bytes(b->cur_max_qlen, copies) + rec_bytes(b->rec) * b->swaves
+                  : batch_lds(b, copies);
+}
+
+// (the cell-counting kernels of the big workgroups, which run once per
+// batch to measure the work, keep the default letter loop: the high-ILP one
+// would spill at four wavefronts per SIMD)
+template <int kCopies, bool kCount, int kRec>
+const void* batch_fn_rec(bool ilp) {
+    return ilp && !kCount ? (const void*)k_score_batch<kCopies, kCount, !kCount, kRec>
+                          : (const void*)k_score_batch<kCopies, kCount, false, kRec>;
+}
+
+template <int kRec>
+const void* batch_kernel_rec(int copies, bool count, bool ilp) {
+    if (copies == 4) return count ? batch_fn_rec<4, true, kRec>(ilp) : batch_fn_rec<4, false, kRec>(ilp);
+    return count ? batch_fn_rec<1, true, kRec>(ilp) : batch_fn_rec<1, false, kRec>(ilp);
 }
 
 const void* batch_kernel_score(const hs_batch* b, bool count) {
-    if (!b->lmode) return batch_kernel(b->copies, count, b->ilp);
-    if (b->copies == 4) return count ? batch_fn_long<4, true>(b->ilp) : batch_fn_long<4, false>(b->ilp);
-    return count ? batch_fn_long<1, true>(b->ilp) : batch_fn_long<1, false>(b->ilp);
+    if (b->rec == 1) return batch_kernel_rec<1>(b->copies, count, b->ilp);
+    if (b->rec == 2) return batch_kernel_rec<2>(b->copies, count, b->ilp);
+    return batch_kernel(b->copies, count, b->ilp);
 }
 
-// Wavefronts of up to kLongWaves whose long-mode records fit in the LDS
-// beside a profile of prof_bytes.
-int fit_waves_long(size_t prof_bytes) {
-    for (int w = kLongWaves; w >= 1; --w)
-        if (prof_bytes + sizeof(WaveLdsLong) * w + 16 <= device_lds_limit()) return w;
+// Wavefronts (at most max_w) whose records of `rec_b` bytes fit in one
+// workgroup's LDS beside a profile of prof_bytes, and the wavefronts per
+// compute unit that gives (workgroups as many as the LDS holds).
+int fit_waves_rec(size_t prof_bytes, size_t rec_b, int max_w, int* per_cu_waves) {
+    const size_t lim = device_lds_limit();
+    for (int w = max_w; w >= 1; --w) {
+        const size_t wg = prof_bytes + rec_b * w + 16;
+        if (wg <= lim) {
+            const int wgs = (int)std::min<size_t>(lim / wg, (size_t)(kBigWaves / w));
+            *per_cu_waves = w * std::max(wgs, 1);
+            return w;
+        }
+    }
+    *per_cu_waves = 0;
     return 0;
 }
 
@@ -993,7 +1013,7 @@ int choose_schedule(hs_batch* b, hipStream_t st) {
     if (!copies_fit(b->cur_max_qlen, b->copies))
         return fail(HS_EINVAL, "profile copies do not fit in LDS for the longest query");
     b->waves = fit_waves(batch_prof_bytes(b->cur_max_qlen, b->copies));
-    b->lmode = false;
+    b->rec = 0;
     b->swaves = b->waves;
     b->cap = b->fix_cap ? b->fix_cap : kLanes;
     int rc = prefer_ilp(batch_kernel(b->copies, false, false), batch_kernel(b->copies, false, true),
@@ -1038,15 +1058,43 @@ int choose_schedule(hs_batch* b, hipStream_t st) {
             1, kLettersInFlight / std::max<int32_t>(b->db->median_len, 1));
         b->cap = std::min(std::min(kLanes, by_len), std::max(1, (b->chunk + b->waves - 1) / b->waves));
     }
-    // Long mode: with at most kLongSlots pairs in flight per wavefront, the
-    // smaller WaveLdsLong records let more wavefronts share the LDS beside a
-    // long query's profile (16 instead of 8 for the long-sequence batch,
-    // whose 4,834-letter profile takes 121 KB): 93 ms -> 77 ms there, with 4
-    // pairs in flight.
-    const int32_t lw = fit_waves_long(batch_prof_bytes(b->cur_max_qlen, b->copies));
-    b->lmode = b->cap <= kLongSlots && lw > b->waves;
-    b->swaves = b->lmode ? lw : b->waves;
+    // Record kind: the smaller records (16 slots when at most 16 pairs are
+    // in flight, else 64) in workgroups of up to 16 wavefronts when they put
+    // more wavefronts on a compute unit than the full records: the
+    // long-sequence batch (a 121 KB profile) gets 16 instead of 8 (93 ms ->
+    // 77 ms, with 4 pairs in flight), the 256-query batch with four copies
+    // (104 KB) 15 instead of 8 (0.90 ms -> 0.85 ms).
+    {
+        const size_t prof = batch_prof_bytes(b->cur_max_qlen, b->copies);
+        int best = 0;
+        fit_waves_rec(prof, sizeof(WaveLds), kWaves, &best);
+        for (int rec = 1; rec <= 2; ++rec) {
+            if (b->cap > rec_slots(rec)) continue;
+            int cu = 0;
+            const int w = fit_waves_rec(prof, rec_bytes(rec), kBigWaves, &cu);
+            if (cu > best) {
+                best = cu;
+                b->rec = rec;
+                b->swaves = w;
+            }
+        }
+    }
     return upload_items(b, st);
+}
+
+// The scoring launch of a batch with the smaller records (kind kRec).
+template <int kCopies, bool kCount, bool kIlp, int kRec>
+void launch_batch_rec(const hs_batch* b, hipStream_t st, uint64_t* d_cells) {
+    const hs_db* db = b->db;
+    hipLaunchKernelGGL((k_score_batch<kCopies, kCount, kIlp, kRec>), dim3(b->grid), dim3(b->swaves * kLanes),
+                       batch_lds_score(b, kCopies), st, (const BatchQuery*)b->d_qs,
+                       (const KMatrix*)b->d_mats, (const uint8_t*)b->d_qcodes,
+                       (const BatchItem*)b->d_items, b->n_items, b->d_ctr,
+                       (int32_t)batch_prof_bytes(b->cur_max_qlen, kCopies), b->cap,
+                       (const PairRec*)db->d_recs, (const uint8_t*)db->d_letters,
+                       (const uint64_t*)b->d_draws, b->d_scores, b->d_rounds,
+                       (int64_t)db->n_targets, &b->d_st->max_score,
+                       (int32_t)(sizeof(TopkState) / sizeof(int32_t)), (unsigned long long*)d_cells);
 }
 
 template <int kCopies, bool kCount, bool kIlp>
@@ -1064,17 +1112,12 @@ void launch_batch_kernel(const hs_batch* b, hipStream_t st, uint64_t* d_cells) {
                            (int32_t)(sizeof(TopkState) / sizeof(int32_t)), (unsigned long long*)d_cells);
         return;
     }
-    if (b->lmode) {
-        hipLaunchKernelGGL((k_score_batch<kCopies, kCount, kIlp && !kCount, true>), dim3(b->grid),
-                           dim3(b->swaves * kLanes), batch_lds_score(b, kCopies), st,
-                           (const BatchQuery*)b->d_qs,
-                           (const KMatrix*)b->d_mats, (const uint8_t*)b->d_qcodes,
-                           (const BatchItem*)b->d_items, b->n_items, b->d_ctr,
-                           (int32_t)batch_prof_bytes(b->cur_max_qlen, kCopies), b->cap,
-                           (const PairRec*)db->d_recs, (const uint8_t*)db->d_letters,
-                           (const uint64_t*)b->d_draws, b->d_scores, b->d_rounds,
-                           (int64_t)db->n_targets, &b->d_st->max_score,
-                           (int32_t)(sizeof(TopkState) / sizeof(int32_t)), (unsigned long long*)d_cells);
+    if (b->rec == 1) {
+        launch_batch_rec<kCopies, kCount, kIlp && !kCount, 1>(b, st, d_cells);
+        return;
+    }
+    if (b->rec == 2) {
+        launch_batch_rec<kCopies, kCount, kIlp && !kCount, 2>(b, st, d_cells);
         return;
     }
     hipLaunchKernelGGL((k_score_batch<kCopies, kCount, kIlp>), dim3(b->grid), dim3(b->waves * kLanes),

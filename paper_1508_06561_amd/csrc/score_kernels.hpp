@@ -27,7 +27,6 @@
 //     first and last 7 letters carry cells outside the window: those bytes
 //     are masked with compile-time masks (entry and exit ramps).
 #pragma once
-#include <type_traits>
 
 #include "device_common.hpp"
 #include "topk_kernels.hpp"
@@ -640,17 +639,34 @@ struct WaveLds {
     uint32_t items[kItemCap];
     uint32_t bins[kBins];
 };
-// The record of a wavefront holding at most kLongSlots pairs, in workgroups
-// of up to kLongWaves wavefronts (batches of long queries, whose profile
-// leaves little LDS: smaller records let more wavefronts share it).
-constexpr int kLongSlots = 16;
-constexpr int kLongWaves = 16;
-struct WaveLdsLong {
+// Smaller records for batches whose profile leaves little LDS, so that more
+// wavefronts share it, in workgroups of up to kBigWaves wavefronts: at most
+// 16 pairs in flight and 256 blocks per phase (2 KB), or 64 pairs and 256
+// blocks (3.6 KB).
+constexpr int kBigWaves = 16;
+template <int kSlots>
+struct WaveLdsSmall {
     static constexpr int kItems = 256;
-    SlotInfo slots[kLongSlots];
+    SlotInfo slots[kSlots];
     uint32_t items[kItems];
     uint32_t bins[kBins];
 };
+using WaveLds16 = WaveLdsSmall<16>;
+using WaveLds64 = WaveLdsSmall<kLanes>;
+// Record kinds of the batch kernel: 0 WaveLds, 1 WaveLds16, 2 WaveLds64.
+template <int kRec>
+struct RecOf {
+    using type = WaveLds;
+};
+template <>
+struct RecOf<1> {
+    using type = WaveLds16;
+};
+template <>
+struct RecOf<2> {
+    using type = WaveLds64;
+};
+__host__ __device__ constexpr int rec_slots(int rec) { return rec == 1 ? 16 : kLanes; }
 
 // Queue positions are taken from the global counter 64 at a time per
 // wavefront, so that the counter sees one atomic per 64 pairs.
@@ -1209,11 +1225,11 @@ void k_score_sched(
 // profile, then its wavefronts pull the item's pairs from a counter in LDS,
 // at most `cap` in flight per wavefront.  Query q's scores go to
 // scores[q * stride + target], its maximum score to max_score[q * ms_stride].
-// kLong: the long mode, WaveLdsLong records and up to kLongWaves wavefronts
-// per workgroup, at most kLongSlots pairs in flight per wavefront.
-template <int kCopies, bool kCount, bool kIlp, bool kLong = false>
-__global__ __launch_bounds__(kLong ? kLongWaves * kLanes : kThreads)
-__attribute__((amdgpu_waves_per_eu(kIlp && !kLong ? 1 : 4)))
+// kRec: the wavefront records (RecOf); kinds 1 and 2 run workgroups of up
+// to kBigWaves wavefronts, kind 1 at most 16 pairs in flight per wavefront.
+template <int kCopies, bool kCount, bool kIlp, int kRec = 0>
+__global__ __launch_bounds__(kRec ? kBigWaves * kLanes : kThreads)
+__attribute__((amdgpu_waves_per_eu(kIlp && !kRec ? 1 : 4)))
 void k_score_batch(
     const BatchQuery* __restrict__ qs, const KMatrix* __restrict__ mats,
     const uint8_t* __restrict__ qcodes, const BatchItem* __restrict__ items, int32_t n_items,
@@ -1224,7 +1240,7 @@ void k_score_batch(
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t s_item, s_ctr;
     const int32_t lane = threadIdx.x & (kLanes - 1);
-    using WL = typename std::conditional<kLong, WaveLdsLong, WaveLds>::type;
+    using WL = typename RecOf<kRec>::type;
     WL& W = ((WL*)(lds + prof_bytes))[threadIdx.x / kLanes];
     uint64_t cells = 0;
     for (;;) {
@@ -1245,7 +1261,7 @@ void k_score_batch(
                                threadIdx.x, blockDim.x);
         __syncthreads();
         int32_t best_seen = INT32_MIN;
-        wave_pairs<kCopies, kCount, true, kIlp>(W, lane, kLong && cap > kLongSlots ? kLongSlots : cap,
+        wave_pairs<kCopies, kCount, true, kIlp>(W, lane, cap > rec_slots(kRec) ? rec_slots(kRec) : cap,
                                                 0u, 0u, 0u, 0u, lds, ps, cpb, Q.bias, Q.qlen,
                                                 Q.kp, recs, item.hi, letters,
                                                 Q.table ? draws : nullptr, &s_ctr,

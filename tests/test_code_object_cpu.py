@@ -46,13 +46,14 @@ def kernel_metadata(tmp_path):
 def test_no_scratch_and_default_occupancy(tmp_path):
     kernels = kernel_metadata(tmp_path)
     scoring = {n: v for n, v in kernels.items() if re.search(r"k_score_(sched|batch)", n)}
-    # 12 one-query kernels, 8 batch kernels and 6 of the batch's long mode
-    assert len(scoring) == 26, sorted(kernels)
+    # 12 one-query kernels, 8 batch kernels with full wavefront records and
+    # 12 with the smaller records of workgroups of up to 16 wavefronts
+    assert len(scoring) == 32, sorted(kernels)
     assert any("k_trace_sched" in n for n in kernels) and any("k_trace_batch" in n for n in kernels)
     for name, (scratch, vgprs) in kernels.items():
         assert scratch == 0, f"{name} uses {scratch} bytes of scratch per lane"
     for name, (scratch, vgprs) in scoring.items():
         copies, count, ilp = re.search(r"ILi(\d)ELb(\d)ELb(\d)E", name).groups()
-        long_mode = re.search(r"k_score_batchILi\dELb\dELb\dELb1E", name) is not None
-        if (ilp == "0" and count == "0") or long_mode:
+        big_groups = re.search(r"k_score_batchILi\dELb\dELb\dELi[12]E", name) is not None
+        if (ilp == "0" and count == "0") or big_groups:
             assert vgprs <= 128, f"{name}: {vgprs} VGPRs (more than four wavefronts per SIMD allow)"
