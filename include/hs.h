@@ -385,8 +385,23 @@ int hs_batch_schedule(hs_batch* b, int32_t copies, int32_t cap, int32_t chunk, v
 int hs_batch_get_schedule(const hs_batch* b, int32_t* copies, int32_t* cap, int32_t* chunk,
                           int32_t* grid, int32_t* n_items);
 
+/* The scoring launch that the schedule in use selects (Section III.B.4's
+ * work, distributed over the device; any pointer may be NULL):
+ *   record   per-wavefront LDS record: 0 = 64 pairs in flight and 512
+ *            blocks per phase, 1 = 16 pairs and 256 blocks, 2 = 64 pairs
+ *            and 256 blocks (1 and 2 in workgroups of up to 16 wavefronts,
+ *            chosen when they fit more wavefronts on a compute unit)
+ *   waves    wavefronts per workgroup of the scoring launch
+ *   ilp      1 when the letter loop issues a chunk's profile reads before
+ *            summing them
+ *   one_pair 1 when the batch is scored one pair per wavefront (all lanes of
+ *            a wavefront on one pair; record is then 0)
+ * Valid after hs_batch_set; HS_EINVAL before it. */
+int hs_batch_get_launch(const hs_batch* b, int32_t* record, int32_t* waves, int32_t* ilp,
+                        int32_t* one_pair);
+
 /* Autotuner: times the scoring pass of the current queries under every
- * candidate schedule (copies x cap in {16, 32, 64} x chunk halvings), `reps`
+ * candidate schedule (copies x cap in {4, 8, 16, 32, 64} x chunk halvings), `reps`
  * timed passes each on `stream`, keeps the fastest as the fixed schedule and
  * reports its mean time in *best_ms (may be NULL).  Synchronizes `stream`. */
 int hs_batch_tune(hs_batch* b, void* stream, int32_t reps, float* best_ms);

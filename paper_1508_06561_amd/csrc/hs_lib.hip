@@ -1991,6 +1991,17 @@ int hs_batch_get_schedule(const hs_batch* b, int32_t* copies, int32_t* cap, int3
     return HS_OK;
 }
 
+int hs_batch_get_launch(const hs_batch* b, int32_t* record, int32_t* waves, int32_t* ilp,
+                        int32_t* one_pair) {
+    int rc = check_batch_ready(b);
+    if (rc) return rc;
+    if (record) *record = b->score_one ? 0 : b->rec;
+    if (waves) *waves = b->score_one ? b->waves : b->swaves;
+    if (ilp) *ilp = b->score_one ? 0 : (int32_t)b->ilp;
+    if (one_pair) *one_pair = b->score_one ? 1 : 0;
+    return HS_OK;
+}
+
 int hs_batch_tune(hs_batch* b, void* stream, int32_t reps, float* best_ms) {
     int rc = check_batch_ready(b);
     if (rc) return rc;

@@ -114,6 +114,7 @@ def lib():
         L.hs_batch_set.argtypes = [vp, i32, vp, P(ctypes.c_int64), P(_CParams), i32, vp]
         L.hs_batch_schedule.argtypes = [vp, i32, i32, i32, vp]
         L.hs_batch_get_schedule.argtypes = [vp, pi32, pi32, pi32, pi32, pi32]
+        L.hs_batch_get_launch.argtypes = [vp, pi32, pi32, pi32, pi32]
         L.hs_batch_tune.argtypes = [vp, vp, i32, P(ctypes.c_float)]
         L.hs_batch_run.argtypes = [vp, vp]
         L.hs_batch_run_graph.argtypes = [vp, vp]
@@ -493,6 +494,13 @@ class Batch:
         v = [ctypes.c_int32() for _ in range(5)]
         _check(lib().hs_batch_get_schedule(self._h, *[ctypes.byref(x) for x in v]))
         return dict(zip(("copies", "cap", "chunk", "grid", "n_items"), [x.value for x in v]))
+
+    def get_launch(self):
+        """The scoring launch the schedule selects: LDS record kind, wavefronts
+        per workgroup, high-ILP letter loop, one pair per wavefront."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().hs_batch_get_launch(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("record", "waves", "ilp", "one_pair"), [x.value for x in v]))
 
     def tune(self, reps=2, stream=None):
         ms = ctypes.c_float()

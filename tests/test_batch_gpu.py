@@ -131,6 +131,42 @@ def test_schedule_invariance(batched, batched_oracle, sched):
     b.close()
 
 
+# (queries, schedule, expected LDS record kind): beside the four-copy
+# profile of the 32 queries of every length (up to 1,000 letters, about
+# 100 KB) one workgroup of eight full records fits per compute unit, so
+# they run the smaller records (sixteen wavefronts), of 64 slots at 64
+# pairs in flight and of 16 slots at 16; with one copy (25 KB), or with
+# queries of at most 300 letters, two full workgroups fit and the full
+# records stay.
+RECORD_CASES = [("every length", (4, 64, 0), 2), ("every length", (4, 16, 64), 1),
+                ("every length", (1, 64, 0), 0), ("at most 300", (4, 64, 0), 0),
+                ("at most 300", (4, 8, 128), 0)]
+
+
+@pytest.mark.parametrize("case", RECORD_CASES,
+                         ids=[f"{q.split()[-1]}_c{s[0]}_cap{s[1]}_rec{r}" for q, s, r in RECORD_CASES])
+def test_record_kinds(batched, batched_oracle, case):
+    """Each per-wavefront LDS record kind of the batch kernel runs in one of
+    these launches, and every query still equals the oracle."""
+    which, sched, rec = case
+    w, codes, db = batched
+    if which == "every length":
+        sel = list(range(0, len(w.queries), 8))
+    else:
+        sel = [i for i in range(len(w.queries)) if len(w.queries[i]) <= 300][:32]
+    qs = [bytes(w.queries[i]) for i in sel]
+    b = H().Batch(db, len(qs), 1000, sum(map(len, qs)), k=w.k, n_aln=w.n_aln)
+    b.schedule(*sched)
+    b.set(qs)
+    launch = b.get_launch()
+    say(f"{which} {sched}: schedule {b.get_schedule()}, launch {launch}")
+    assert launch["record"] == rec and launch["one_pair"] == 0
+    b.run()
+    for r, i in zip(b.results(), sel):
+        same_result(r, batched_oracle[i], f"query {i} under {sched}, record {rec}")
+    b.close()
+
+
 def test_graph_replays(batched, batched_oracle):
     """The captured graph, replayed several times with other work on the
     stream in between, gives the eager result every time."""
