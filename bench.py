@@ -508,11 +508,33 @@ def measure_align(args):
     H.align(*big, p)
     ms_big = (time.perf_counter() - t) * 1e3
     log(f"pairwise mode: {ms:.2f} ms per 1,000 pairs (Rounds 20), longest pair {ms_big:.2f} ms")
-    return {"workload": "pairwise mode (Fig. 1 full slide), Rounds 20: 1,000 pairs, query "
-                        "log-normal median 300, target a 20-90% identity copy with indels in a "
-                        "flank; host in and out",
-            "ms_per_1000_pairs": ms, "pairs_per_s": 1000 / (ms * 1e-3),
-            "ms_longest_pair_5600x5600": ms_big}
+    out = {"workload": "pairwise mode (Fig. 1 full slide), Rounds 20: 1,000 pairs, query "
+                       "log-normal median 300, target a 20-90% identity copy with indels in a "
+                       "flank; host in and out",
+           "ms_per_1000_pairs": ms, "pairs_per_s": 1000 / (ms * 1e-3),
+           "ms_longest_pair_5600x5600": ms_big}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_align(pairs, args.cpu_budget / 4)
+        log(f"cpu baseline (pairwise mode): {out['cpu_baseline']}")
+    return out
+
+
+def cpu_baseline_align(pairs, budget_s):
+    """Oracle pairwise mode (plain single-threaded C, Rounds 20, full slide)
+    on the benchmark's pairs in order until about budget_s seconds have
+    passed."""
+    import oracle as O
+    op = O.Params(rounds=20, full_slide=True)
+    n = 0
+    t = time.perf_counter()
+    while n < len(pairs) and time.perf_counter() - t < budget_s:
+        q, tg = pairs[n]
+        O.align_pair(O.encode(q), O.encode(tg), target_id=n, params=op)
+        n += 1
+    dt = time.perf_counter() - t
+    return {"value": n / dt, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} of {len(pairs)} pairs, Rounds 20, single thread, {dt:.1f} s",
+            **host_facts()}
 
 
 SW_OPS_PER_CELL = 11     # Gotoh cell: 4 subtractions, 1 addition, 6 maxima (with the running best)

@@ -9,9 +9,13 @@
 // the large window goes back to large (Section III.B.2).
 //
 // One workgroup per (pair, round) scores that round: its threads share each
-// step's placements, summing the letters that face each other from the
-// two sequences staged in LDS.  One workgroup per pair then replays the
-// pair's best round and writes its run-length ops.
+// step's placements (one to a thread, or for long pairs four neighbouring
+// ones, which share their letter reads), summing the letters that face each
+// other from the two sequences staged in LDS.  The
+// workgroup that finishes a pair's last round then replays the pair's best
+// round (its sequences are still staged) and writes its run-length ops, so
+// that a long pair's replay follows its own rounds rather than waiting for
+// every pair's.
 #pragma once
 
 #include "device_common.hpp"
@@ -33,10 +37,34 @@ struct AlignPair {
     int64_t ops_off;     // first op of the pair's output
 };
 
-struct AlignLds {
-    int8_t mat[kNsym * kNsym];
+// LDS of a workgroup (dynamic, sized by the launch to the batch's longest
+// sequence, `cap` letters): a fixed head -- the substitution matrix
+// transposed (row = the small sequence's letter), the wavefronts' best keys,
+// the replay's round and flag -- then the large sequence as one 32-bit word
+// per position holding that letter and the three after it (so that the four
+// placements of a thread read their letters in one aligned read), then the
+// small sequence.
+struct AlignHead {
+    int8_t matT[kNsym * kNsym];
     uint64_t wbest[kAlWavesMax];
-    uint8_t L[kAlMaxLen], S[kAlMaxLen];
+    int32_t best_round, last;
+};
+__host__ __device__ constexpr size_t al_lds_bytes(int32_t cap) {
+    return sizeof(AlignHead) + 5 * (size_t)((cap + 15) & ~15);
+}
+struct AlignLds {
+    AlignHead* h;
+    int8_t* matT;
+    uint64_t* wbest;
+    uint32_t* L4;
+    uint8_t* S;
+    __device__ AlignLds(uint8_t* base, int32_t cap) {
+        h = (AlignHead*)base;
+        matT = h->matT;
+        wbest = h->wbest;
+        L4 = (uint32_t*)(base + sizeof(AlignHead));
+        S = (uint8_t*)(L4 + ((cap + 15) & ~15));
+    }
 };
 
 // Largest 64-bit key over the wavefront (all lanes active), by two 32-bit
@@ -74,9 +102,10 @@ __device__ __forceinline__ void al_emit(uint32_t* ops, int32_t& n_ops, uint32_t 
 
 // One round of pair `id` by the whole workgroup of kT threads: the round's
 // score (SCORE of its aligned rows, streamed step by step) and, with kEmit,
-// its ops written by thread 0.  L / S (lengths nl >= ns) are in LDS; tl: the
-// target is L.
-template <int kT, bool kEmit>
+// its ops written by thread 0; kQuad: four placements per thread.  The
+// large sequence (nl letters, as L4) and the small one (ns <= nl, as S) are
+// in LDS; tl: the target is the large one.
+template <int kT, bool kEmit, bool kQuad>
 __device__ int32_t al_round(AlignLds& A, int32_t nl, int32_t ns, bool tl, const KParams& kp,
                             int32_t id, int32_t round, uint32_t* ops, int32_t* n_ops_out) {
     const int32_t tid = threadIdx.x, lane = tid & (kLanes - 1), wave = tid / kLanes;
@@ -97,16 +126,68 @@ __device__ int32_t al_round(AlignLds& A, int32_t nl, int32_t ns, bool tl, const 
         // other are small j in [max(0, -k), min(ss, ls - k))
         const int32_t np = ls + ss - 1;
         uint64_t best = 0;
-        for (int32_t i = tid; i < np; i += kT) {
-            const int32_t k = i - ss + 1;
-            const int32_t j0 = k < 0 ? -k : 0;
-            const int32_t j1 = ss < ls - k ? ss : ls - k;
-            const uint8_t* Lk = A.L + pL + k;
+        if (!kQuad) {
+            // one placement per thread
+            for (int32_t i = tid; i < np; i += kT) {
+                const int32_t k = i - ss + 1;
+                const int32_t j0 = k < 0 ? -k : 0;
+                const int32_t j1 = ss < ls - k ? ss : ls - k;
+                const int32_t lb = pL + k;
+                const uint8_t* Sj = A.S + pS;
+                int32_t D = 0;
+                for (int32_t j = j0; j < j1; ++j) D += A.matT[Sj[j] * kNsym + (A.L4[lb + j] & 0xFFu)];
+                const uint64_t key = shift_key(D, i);
+                best = key > best ? key : best;
+            }
+        }
+        for (int32_t i0 = 4 * tid; kQuad && i0 < np; i0 += 4 * kT) {
+            // placements i0 .. i0 + 3 (those below np): placement i0 + m
+            // faces small letters [j0_m, j1_m); both ends fall with m by at
+            // most one per placement, so [j0_0, j1_3) is faced by all four
+            // (the interior) and each has at most three letters outside it
+            const int32_t k0 = i0 - ss + 1;
+            const int32_t n4 = np - i0 < 4 ? np - i0 : 4;
+            const int32_t J0 = k0 < 0 ? -k0 : 0;
+            const int32_t J1 = ss < ls - k0 - 3 ? ss : ls - k0 - 3;
+            const int32_t lb = pL + k0;              // L4[lb + j]: letters lb + j + m, m = 0..3
             const uint8_t* Sj = A.S + pS;
-            int32_t D = 0;
-            for (int32_t j = j0; j < j1; ++j) D += A.mat[Lk[j] * kNsym + Sj[j]];
-            const uint64_t key = shift_key(D, i);
-            best = key > best ? key : best;
+            int32_t D0 = 0, D1 = 0, D2 = 0, D3 = 0;
+            if (n4 == 4) {
+                for (int32_t j = J0; j < J1; ++j) {
+                    const uint32_t w = A.L4[lb + j];
+                    const int8_t* row = A.matT + Sj[j] * kNsym;
+                    D0 += row[w & 0xFFu];
+                    D1 += row[(w >> 8) & 0xFFu];
+                    D2 += row[(w >> 16) & 0xFFu];
+                    D3 += row[w >> 24];
+                }
+            }
+            // the letters of each placement outside the interior: at most
+            // three before it and three after it, read as independent
+            // predicated loads (a loop here would chain their latencies);
+            // without an interior (fewer than four placements left, or a
+            // window of a few letters) each placement sums its own range
+            const bool in = n4 == 4 && J0 < J1;
+#define HS_AL_EDGE(m, D)                                                              \
+            if (m < n4) {                                                             \
+                const int32_t km = k0 + m;                                            \
+                const int32_t a = km < 0 ? -km : 0;                                   \
+                const int32_t b = ss < ls - km ? ss : ls - km;                        \
+                if (in) {                                                             \
+                    _Pragma("unroll") for (int e = 1; e <= 3; ++e) {                  \
+                        const int32_t jh = J0 - e, jt = J1 - 1 + e;                   \
+                        if (jh >= a) D += A.matT[Sj[jh] * kNsym + (A.L4[lb + jh + m] & 0xFFu)]; \
+                        if (jt < b) D += A.matT[Sj[jt] * kNsym + (A.L4[lb + jt + m] & 0xFFu)];  \
+                    }                                                                 \
+                } else {                                                              \
+                    for (int32_t j = a; j < b; ++j)                                   \
+                        D += A.matT[Sj[j] * kNsym + (A.L4[lb + j + m] & 0xFFu)];      \
+                }                                                                     \
+                const uint64_t key = shift_key(D, i0 + m);                            \
+                best = key > best ? key : best;                                       \
+            }
+            HS_AL_EDGE(0, D0) HS_AL_EDGE(1, D1) HS_AL_EDGE(2, D2) HS_AL_EDGE(3, D3)
+#undef HS_AL_EDGE
         }
         best = al_wave_max(best);
         if (lane == 0) A.wbest[wave] = best;
@@ -167,55 +248,88 @@ __device__ __forceinline__ void al_stage(AlignLds& A, const AlignPair& P, const 
     ns = tl ? P.qlen : P.tlen;
     const uint8_t* src_l = codes + (tl ? P.toff : P.qoff);
     const uint8_t* src_s = codes + (tl ? P.qoff : P.toff);
-    for (int32_t i = threadIdx.x; i < nl; i += kT) A.L[i] = src_l[i];
+    for (int32_t i = threadIdx.x; i < nl; i += kT) {
+        // letters i .. i + 3 (past the end: 0, never summed)
+        uint32_t w = src_l[i];
+        if (i + 1 < nl) w |= (uint32_t)src_l[i + 1] << 8;
+        if (i + 2 < nl) w |= (uint32_t)src_l[i + 2] << 16;
+        if (i + 3 < nl) w |= (uint32_t)src_l[i + 3] << 24;
+        A.L4[i] = w;
+    }
     for (int32_t i = threadIdx.x; i < ns; i += kT) A.S[i] = src_s[i];
-    for (int32_t i = threadIdx.x; i < kNsym * kNsym; i += kT) A.mat[i] = km.m[i];
+    // matT[s * kNsym + l] = score of large letter l against small letter s
+    for (int32_t i = threadIdx.x; i < kNsym * kNsym; i += kT)
+        A.matT[i] = km.m[(i % kNsym) * kNsym + i / kNsym];
     __syncthreads();
 }
 
-// Round blockIdx.x % rounds of pair blockIdx.x / rounds: its score to
-// round_scores[pair * rounds + round].  kT threads per workgroup.
+// Workgroup b scores round b % rounds of pair order[b / rounds] (pairs
+// in order of decreasing work, so that the longest chains start first) into
+// round_scores[pair * rounds + round].  The workgroup that completes a
+// pair's rounds (the pair's counter in `done`, zero at launch, reaching
+// rounds) replays the best round (the first with the highest score) with
+// its sequences still in LDS: score, round, op count and ops at
+// ops + pairs[pair].ops_off.  kT threads per workgroup; no sequence longer
+// than cap letters; al_lds_bytes(cap) bytes of dynamic LDS.
 template <int kT>
-__global__ __launch_bounds__(kT) void k_align_rounds(const AlignPair* __restrict__ pairs,
-                                                             const uint8_t* __restrict__ codes,
-                                                             KParams kp, KMatrix km,
-                                                             int32_t* __restrict__ round_scores) {
-    __shared__ AlignLds A;
-    const int32_t pair = blockIdx.x / kp.rounds, round = blockIdx.x % kp.rounds;
-    int32_t nl, ns;
-    bool tl;
-    al_stage<kT>(A, pairs[pair], codes, km, nl, ns, tl);
-    const int32_t s = al_round<kT, false>(A, nl, ns, tl, kp, pair, round, nullptr, nullptr);
-    if (threadIdx.x == 0) round_scores[(int64_t)pair * kp.rounds + round] = s;
-}
-
-// Pair blockIdx.x: its best round (the first with the highest score),
-// replayed into ops at ops + pairs[p].ops_off; score, round and op count out.
-template <int kT>
-__global__ __launch_bounds__(kT) void k_align_replay(const AlignPair* __restrict__ pairs,
-                                                             const uint8_t* __restrict__ codes,
-                                                             KParams kp, KMatrix km,
-                                                             const int32_t* __restrict__ round_scores,
-                                                             int32_t* __restrict__ scores,
-                                                             int32_t* __restrict__ rounds,
-                                                             int32_t* __restrict__ n_ops,
-                                                             uint32_t* __restrict__ ops) {
-    __shared__ AlignLds A;
-    const int32_t pair = blockIdx.x;
-    const int32_t* rs = round_scores + (int64_t)pair * kp.rounds;
-    int32_t best = rs[0], best_r = 0;
-    for (int32_t r = 1; r < kp.rounds; ++r)
-        if (rs[r] > best) {
-            best = rs[r];
-            best_r = r;
-        }
-    int32_t nl, ns;
-    bool tl;
+__global__ __launch_bounds__(kT) void k_align_pairs(const AlignPair* __restrict__ pairs,
+                                                    const int32_t* __restrict__ order,
+                                                    const uint8_t* __restrict__ codes, int32_t cap,
+                                                    KParams kp, KMatrix km,
+                                                    int32_t* __restrict__ round_scores,
+                                                    uint32_t* __restrict__ done,
+                                                    int32_t* __restrict__ scores,
+                                                    int32_t* __restrict__ rounds,
+                                                    int32_t* __restrict__ n_ops,
+                                                    uint32_t* __restrict__ ops) {
+    // four placements per thread in the long mode, whose steps have thousands
+    // of placements (the 5,600-letter pair at Rounds 20: 1.53 -> 0.99 ms);
+    // one per thread for short pairs, whose steps leave threads idle at four
+    // (1,000 pairs of up to 2,000 letters: 1.07 ms, against 1.46 ms)
+    constexpr bool kQuad = kT == kAlThreadsLong;
+    extern __shared__ __align__(16) uint8_t al_lds[];
+    AlignLds A(al_lds, cap);
+    const int32_t pair = order[blockIdx.x / kp.rounds], round = blockIdx.x % kp.rounds;
     const AlignPair P = pairs[pair];
+    int32_t nl, ns;
+    bool tl;
     al_stage<kT>(A, P, codes, km, nl, ns, tl);
-    const int32_t s = al_round<kT, true>(A, nl, ns, tl, kp, pair, best_r, ops + P.ops_off, n_ops + pair);
+    if (kp.rounds == 1) {
+        // the only round is the best: scored and written in one pass
+        const int32_t s1 = al_round<kT, true, kQuad>(A, nl, ns, tl, kp, pair, 0, ops + P.ops_off, n_ops + pair);
+        if (threadIdx.x == 0) {
+            scores[pair] = s1;
+            rounds[pair] = 0;
+        }
+        return;
+    }
+    const int32_t s = al_round<kT, false, kQuad>(A, nl, ns, tl, kp, pair, round, nullptr, nullptr);
+    int32_t* rs = round_scores + (int64_t)pair * kp.rounds;
     if (threadIdx.x == 0) {
-        scores[pair] = s;        // equal to best: the replay is the same round
+        rs[round] = s;
+        __threadfence();                               // the score before the count
+        const uint32_t prev = atomicAdd(done + pair, 1u);
+        A.h->last = prev == (uint32_t)kp.rounds - 1u;
+        if (A.h->last) {
+            __threadfence();                           // every round's score after the count
+            int32_t best = INT32_MIN, best_r = 0;
+            for (int32_t r = 0; r < kp.rounds; ++r) {
+                const int32_t v = r == round ? s : __hip_atomic_load(rs + r, __ATOMIC_RELAXED,
+                                                                     __HIP_MEMORY_SCOPE_AGENT);
+                if (v > best) {
+                    best = v;
+                    best_r = r;
+                }
+            }
+            A.h->best_round = best_r;
+        }
+    }
+    __syncthreads();
+    if (!A.h->last) return;                            // the same for the whole workgroup
+    const int32_t best_r = A.h->best_round;
+    const int32_t s2 = al_round<kT, true, kQuad>(A, nl, ns, tl, kp, pair, best_r, ops + P.ops_off, n_ops + pair);
+    if (threadIdx.x == 0) {
+        scores[pair] = s2;       // equal to the round's score: the replay is the same round
         rounds[pair] = best_r;
     }
 }

@@ -1634,13 +1634,24 @@ int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char*
         ct += P.tlen;
         co += P.qlen + P.tlen;
     }
+    // workgroups take the pairs with the most cells per round first (a
+    // round's cells grow with the product of the lengths), so that the
+    // longest chains of steps start at once
+    std::vector<int32_t> order((size_t)n);
+    for (int32_t i = 0; i < n; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return (int64_t)pairs[(size_t)a].qlen * pairs[(size_t)a].tlen >
+               (int64_t)pairs[(size_t)b].qlen * pairs[(size_t)b].tlen;
+    });
     hipStream_t st = (hipStream_t)stream;
-    // device layout: codes, pairs, per-round scores, then one region of
-    // scores, rounds and packed offsets (read back by one copy), op counts,
-    // ops in per-pair slots, packed ops
+    // device layout: codes, pairs and their order, per-round scores, pair
+    // counters, then one region of scores, rounds and packed offsets (read
+    // back by one copy), op counts, ops in per-pair slots, packed ops
     const size_t o_codes = 0, o_pairs = align_up(codes.size()),
-                 o_rs = o_pairs + align_up(sizeof(AlignPair) * (size_t)n),
-                 o_sc = o_rs + align_up(sizeof(int32_t) * (size_t)n * params->rounds),
+                 o_order = o_pairs + align_up(sizeof(AlignPair) * (size_t)n),
+                 o_rs = o_order + align_up(sizeof(int32_t) * (size_t)n),
+                 o_done = o_rs + align_up(sizeof(int32_t) * (size_t)n * params->rounds),
+                 o_sc = o_done + align_up(sizeof(uint32_t) * (size_t)n),
                  o_rd = o_sc + sizeof(int32_t) * (size_t)n,
                  o_off = (o_rd + sizeof(int32_t) * (size_t)n + 7) & ~(size_t)7,
                  o_no = align_up(o_off + sizeof(int64_t) * ((size_t)n + 1)),
@@ -1656,7 +1667,10 @@ int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char*
     rc = HS_OK;
     if (hipMemcpyAsync(d + o_codes, codes.data(), codes.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(d + o_pairs, pairs.data(), sizeof(AlignPair) * (size_t)n, hipMemcpyHostToDevice,
-                       st) != hipSuccess)
+                       st) != hipSuccess ||
+        hipMemcpyAsync(d + o_order, order.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipMemsetAsync(d + o_done, 0, sizeof(uint32_t) * (size_t)n, st) != hipSuccess)
         rc = fail(HS_EDEVICE, "pair upload failed");
     if (!rc) {
         const AlignPair* d_pairs = (const AlignPair*)(d + o_pairs);
@@ -1667,20 +1681,21 @@ int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char*
         // placements (the 5,600 x 5,600 pair at Rounds 20: 5.8 ms with 256
         // threads, 1.6 ms with 1,024); batches of shorter pairs keep 256 (1,000
         // pairs of up to 2,000 letters took 3.9 ms instead of 2.0 with 1,024)
+        const int32_t* d_order = (const int32_t*)(d + o_order);
+        // LDS sized to the longest sequence, so that batches of short pairs
+        // keep many workgroups on a compute unit
+        const int32_t cap = (int32_t)longest;
+        const size_t lds = al_lds_bytes(cap);
         if (longest >= kAlLongPair) {
-            hipLaunchKernelGGL(k_align_rounds<kAlThreadsLong>, dim3(nr), dim3(kAlThreadsLong), 0, st,
-                               d_pairs, d_codes, kp, km, (int32_t*)(d + o_rs));
-            hipLaunchKernelGGL(k_align_replay<kAlThreadsLong>, dim3((unsigned)n), dim3(kAlThreadsLong), 0,
-                               st, d_pairs, d_codes, kp, km, (const int32_t*)(d + o_rs),
-                               (int32_t*)(d + o_sc), (int32_t*)(d + o_rd), (int32_t*)(d + o_no),
-                               (uint32_t*)(d + o_ops));
+            hipLaunchKernelGGL(k_align_pairs<kAlThreadsLong>, dim3(nr), dim3(kAlThreadsLong), lds, st,
+                               d_pairs, d_order, d_codes, cap, kp, km, (int32_t*)(d + o_rs),
+                               (uint32_t*)(d + o_done), (int32_t*)(d + o_sc), (int32_t*)(d + o_rd),
+                               (int32_t*)(d + o_no), (uint32_t*)(d + o_ops));
         } else {
-            hipLaunchKernelGGL(k_align_rounds<kAlThreads>, dim3(nr), dim3(kAlThreads), 0, st, d_pairs,
-                               d_codes, kp, km, (int32_t*)(d + o_rs));
-            hipLaunchKernelGGL(k_align_replay<kAlThreads>, dim3((unsigned)n), dim3(kAlThreads), 0, st,
-                               d_pairs, d_codes, kp, km, (const int32_t*)(d + o_rs),
-                               (int32_t*)(d + o_sc), (int32_t*)(d + o_rd), (int32_t*)(d + o_no),
-                               (uint32_t*)(d + o_ops));
+            hipLaunchKernelGGL(k_align_pairs<kAlThreads>, dim3(nr), dim3(kAlThreads), lds, st, d_pairs,
+                               d_order, d_codes, cap, kp, km, (int32_t*)(d + o_rs),
+                               (uint32_t*)(d + o_done), (int32_t*)(d + o_sc), (int32_t*)(d + o_rd),
+                               (int32_t*)(d + o_no), (uint32_t*)(d + o_ops));
         }
         hipLaunchKernelGGL(k_align_ops_scan, dim3(1), dim3(kAlScanThreads), 0, st,
                            (const int32_t*)(d + o_no), n, (int64_t*)(d + o_off));

@@ -114,6 +114,21 @@ def test_longest_pairs():
     check_pairs(pairs, H().Params(rounds=20))
 
 
+def test_thousand_pairs_of_mixed_lengths():
+    """1,000 pairs of log-normal lengths (median 300, up to 2,000), the
+    pairwise benchmark's mix: many pairs in flight, their rounds finishing in
+    any order, each pair replayed by the workgroup of its last round."""
+    rng = np.random.default_rng(35)
+    pairs = []
+    for L in synth.lognormal_lengths(rng, 1000, 300, 0.6, 20, 2000):
+        q = synth.random_protein(rng, int(L))
+        tl = int(synth.lognormal_lengths(rng, 1, 300, 0.6, 20, 2000)[0])
+        pairs.append((q, synth.embed(rng, synth.mutate(rng, q, rng.uniform(0.2, 0.9)), tl)))
+    say("pairwise: 1,000 pairs of mixed lengths, Rounds 20")
+    got = check_pairs(pairs, H().Params(rounds=20, seed=21))
+    assert len({g.round for g in got}) > 10        # the best round varies over the pairs
+
+
 def test_single_equals_batch():
     rng = np.random.default_rng(34)
     q, t = synth.random_protein(rng, 120), synth.random_protein(rng, 90)
