@@ -465,7 +465,7 @@ __device__ __forceinline__ uint64_t score_block(const uint8_t* prof, int32_t ps,
                 const int32_t base = (i & 3) == 0 ? Bs.v0 : (i & 3) == 1 ? Bs.v1 : (i & 3) == 2 ? Bs.v2 : Bs.v3; \
                 const uint32_t r = LT::template at<i>(f.ramp_in);                          \
                 const uint2 x = lds8<kCopies>(prof, (int32_t)(__umul24(r, (uint32_t)ps) + (uint32_t)base) + 4 * (i >> 2)); \
-                const uint64_t lo = i < 7 ? (~0ull << (8 * (7 - i))) : ~0ull;              \
+                const uint64_t lo = i < 7 ? (~0ull << (8 * ((7 - i) & 7))) : ~0ull;        \
                 const uint64_t hi = n >= 8 ? ~0ull : ((1ull << (8 * n)) - 1ull);           \
                 const uint64_t m = lo & hi;                                                \
                 b0 += x.x & (uint32_t)m;                                                   \

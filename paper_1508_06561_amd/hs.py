@@ -418,13 +418,17 @@ class DeviceSearch:
         return Result(hits, alns, np.concatenate(chunks) if chunks else np.zeros(0, np.uint32))
 
 
+def _as_bytes(q):
+    return q if type(q) is bytes else q.encode() if isinstance(q, str) else bytes(q)
+
+
 def _pack_queries(queries):
-    """(concatenated ASCII bytes as uint8, int64 offsets) of a list of queries."""
-    bs = [q if isinstance(q, bytes) else q.encode() if isinstance(q, str) else bytes(q) for q in queries]
+    """(concatenated ASCII bytes as a read-only uint8 array, int64 offsets) of
+    a list of queries."""
+    bs = list(map(_as_bytes, queries))
     off = np.zeros(len(bs) + 1, dtype=np.int64)
-    off[1:] = np.cumsum([len(b) for b in bs])
-    res = np.frombuffer(b"".join(bs), dtype=np.uint8).copy()
-    return res, off
+    np.cumsum(np.fromiter(map(len, bs), dtype=np.int64, count=len(bs)), out=off[1:])
+    return np.frombuffer(b"".join(bs), dtype=np.uint8), off
 
 
 def _params_array(params, nq):
@@ -562,7 +566,7 @@ def search_batch(db, queries, params=None, k=50, n_aln=50, stream=None):
     return _split_batch(nq, k, n_aln, hits, n_hits, alns, n_alns, ops)
 
 
-@dataclasses.dataclass
+@dataclasses.dataclass(slots=True)
 class Alignment:
     score: int
     round: int
@@ -591,8 +595,9 @@ def align_batch(pairs, params=None, stream=None):
                                 rounds.ctypes.data_as(P), ops.ctypes.data, cap,
                                 ops_off.ctypes.data_as(P64), ctypes.byref(used)))
     # one buffer holds every pair's ops; each Alignment keeps a view of its run
-    o, s, r = ops_off.tolist(), scores.tolist(), rounds.tolist()
-    return [Alignment(s[i], r[i], ops[o[i]:o[i + 1]]) for i in range(n)]
+    o = ops_off.tolist()
+    return list(map(Alignment, scores.tolist(), rounds.tolist(),
+                    [ops[a:b] for a, b in zip(o[:-1], o[1:])]))
 
 
 def align(query, target, params=None, stream=None):
