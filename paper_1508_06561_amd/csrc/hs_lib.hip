@@ -1246,10 +1246,19 @@ void hs_builtin_matrix(int8_t* out) {
 
 int hs_encode(const char* ascii, int64_t n, uint8_t* codes) {
     if (n < 0 || (n > 0 && (!ascii || !codes))) return fail(HS_EINVAL, "bad arguments to hs_encode");
+    // one pass without a branch per letter (invalid letters map to -1, so
+    // the OR of all codes is negative exactly when one is); the position of
+    // the first bad letter is looked up only then
+    int bad = 0;
     for (int64_t i = 0; i < n; ++i) {
         const int c = kCodes.t[(unsigned char)ascii[i]];
-        if (c < 0) return fail(HS_EINVAL, "residue outside the alphabet at position " + std::to_string(i));
+        bad |= c;
         codes[i] = (uint8_t)c;
+    }
+    if (bad < 0) {
+        int64_t i = 0;
+        while (kCodes.t[(unsigned char)ascii[i]] >= 0) ++i;
+        return fail(HS_EINVAL, "residue outside the alphabet at position " + std::to_string(i));
     }
     return HS_OK;
 }
