@@ -9,9 +9,9 @@
 // the large window goes back to large (Section III.B.2).
 //
 // One workgroup per (pair, round) scores that round: its threads share each
-// step's placements (one to a thread, or for long pairs four neighbouring
-// ones, which share their letter reads), summing the letters that face each
-// other from the two sequences staged in LDS.  The
+// step's placements, four neighbouring ones to a thread (they share their
+// letter reads), summing the letters that face each other from the two
+// sequences staged in LDS.  The
 // workgroup that finishes a pair's last round then replays the pair's best
 // round (its sequences are still staged) and writes its run-length ops, so
 // that a long pair's replay follows its own rounds rather than waiting for
@@ -23,8 +23,9 @@
 
 namespace hs {
 
-constexpr int kAlThreads = 256;                  // threads per (pair, round) of short pairs
+constexpr int kAlThreads = 256;                  // threads per workgroup of the op packing
 constexpr int kAlWaves = kAlThreads / kLanes;
+constexpr int kAlThreadsShort = 128;             // threads per (pair, round) of short pairs
 constexpr int kAlThreadsLong = 1024;             // of batches holding a long pair
 constexpr int kAlWavesMax = kAlThreadsLong / kLanes;
 constexpr int kAlLongPair = 4000;                // letters: a long pair
@@ -102,10 +103,12 @@ __device__ __forceinline__ void al_emit(uint32_t* ops, int32_t& n_ops, uint32_t 
 
 // One round of pair `id` by the whole workgroup of kT threads: the round's
 // score (SCORE of its aligned rows, streamed step by step) and, with kEmit,
-// its ops written by thread 0; kQuad: four placements per thread.  The
+// its ops written by thread 0.  Each thread takes four neighbouring
+// placements at a time, which read their large letters as one word and
+// share the small letter.  The
 // large sequence (nl letters, as L4) and the small one (ns <= nl, as S) are
 // in LDS; tl: the target is the large one.
-template <int kT, bool kEmit, bool kQuad>
+template <int kT, bool kEmit>
 __device__ int32_t al_round(AlignLds& A, int32_t nl, int32_t ns, bool tl, const KParams& kp,
                             int32_t id, int32_t round, uint32_t* ops, int32_t* n_ops_out) {
     const int32_t tid = threadIdx.x, lane = tid & (kLanes - 1), wave = tid / kLanes;
@@ -126,21 +129,7 @@ __device__ int32_t al_round(AlignLds& A, int32_t nl, int32_t ns, bool tl, const 
         // other are small j in [max(0, -k), min(ss, ls - k))
         const int32_t np = ls + ss - 1;
         uint64_t best = 0;
-        if (!kQuad) {
-            // one placement per thread
-            for (int32_t i = tid; i < np; i += kT) {
-                const int32_t k = i - ss + 1;
-                const int32_t j0 = k < 0 ? -k : 0;
-                const int32_t j1 = ss < ls - k ? ss : ls - k;
-                const int32_t lb = pL + k;
-                const uint8_t* Sj = A.S + pS;
-                int32_t D = 0;
-                for (int32_t j = j0; j < j1; ++j) D += A.matT[Sj[j] * kNsym + (A.L4[lb + j] & 0xFFu)];
-                const uint64_t key = shift_key(D, i);
-                best = key > best ? key : best;
-            }
-        }
-        for (int32_t i0 = 4 * tid; kQuad && i0 < np; i0 += 4 * kT) {
+        for (int32_t i0 = 4 * tid; i0 < np; i0 += 4 * kT) {
             // placements i0 .. i0 + 3 (those below np): placement i0 + m
             // faces small letters [j0_m, j1_m); both ends fall with m by at
             // most one per placement, so [j0_0, j1_3) is faced by all four
@@ -282,11 +271,6 @@ __global__ __launch_bounds__(kT) void k_align_pairs(const AlignPair* __restrict_
                                                     int32_t* __restrict__ rounds,
                                                     int32_t* __restrict__ n_ops,
                                                     uint32_t* __restrict__ ops) {
-    // four placements per thread in the long mode, whose steps have thousands
-    // of placements (the 5,600-letter pair at Rounds 20: 1.53 -> 0.99 ms);
-    // one per thread for short pairs, whose steps leave threads idle at four
-    // (1,000 pairs of up to 2,000 letters: 1.07 ms, against 1.46 ms)
-    constexpr bool kQuad = kT == kAlThreadsLong;
     extern __shared__ __align__(16) uint8_t al_lds[];
     AlignLds A(al_lds, cap);
     const int32_t pair = order[blockIdx.x / kp.rounds], round = blockIdx.x % kp.rounds;
@@ -296,14 +280,14 @@ __global__ __launch_bounds__(kT) void k_align_pairs(const AlignPair* __restrict_
     al_stage<kT>(A, P, codes, km, nl, ns, tl);
     if (kp.rounds == 1) {
         // the only round is the best: scored and written in one pass
-        const int32_t s1 = al_round<kT, true, kQuad>(A, nl, ns, tl, kp, pair, 0, ops + P.ops_off, n_ops + pair);
+        const int32_t s1 = al_round<kT, true>(A, nl, ns, tl, kp, pair, 0, ops + P.ops_off, n_ops + pair);
         if (threadIdx.x == 0) {
             scores[pair] = s1;
             rounds[pair] = 0;
         }
         return;
     }
-    const int32_t s = al_round<kT, false, kQuad>(A, nl, ns, tl, kp, pair, round, nullptr, nullptr);
+    const int32_t s = al_round<kT, false>(A, nl, ns, tl, kp, pair, round, nullptr, nullptr);
     int32_t* rs = round_scores + (int64_t)pair * kp.rounds;
     if (threadIdx.x == 0) {
         rs[round] = s;
@@ -327,7 +311,7 @@ __global__ __launch_bounds__(kT) void k_align_pairs(const AlignPair* __restrict_
     __syncthreads();
     if (!A.h->last) return;                            // the same for the whole workgroup
     const int32_t best_r = A.h->best_round;
-    const int32_t s2 = al_round<kT, true, kQuad>(A, nl, ns, tl, kp, pair, best_r, ops + P.ops_off, n_ops + pair);
+    const int32_t s2 = al_round<kT, true>(A, nl, ns, tl, kp, pair, best_r, ops + P.ops_off, n_ops + pair);
     if (threadIdx.x == 0) {
         scores[pair] = s2;       // equal to the round's score: the replay is the same round
         rounds[pair] = best_r;

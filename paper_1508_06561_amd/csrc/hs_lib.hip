@@ -1688,8 +1688,11 @@ int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char*
         // a batch holding a pair of kAlLongPair letters or more gives each
         // (pair, round) 1,024 threads: a step of a long pair has thousands of
         // placements (the 5,600 x 5,600 pair at Rounds 20: 5.8 ms with 256
-        // threads, 1.6 ms with 1,024); batches of shorter pairs keep 256 (1,000
-        // pairs of up to 2,000 letters took 3.9 ms instead of 2.0 with 1,024)
+        // threads, 1.6 ms with 1,024, before the four placements per thread);
+        // batches of shorter pairs take 128 threads, enough for the few
+        // hundred placements of their steps (1,000 pairs of up to 2,000
+        // letters: kernel 0.87 ms, against 1.07 with 256 threads taking one
+        // placement each, 1.46 with 256 taking four, 1.23 with 64)
         const int32_t* d_order = (const int32_t*)(d + o_order);
         // LDS sized to the longest sequence, so that batches of short pairs
         // keep many workgroups on a compute unit
@@ -1701,7 +1704,7 @@ int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char*
                                (uint32_t*)(d + o_done), (int32_t*)(d + o_sc), (int32_t*)(d + o_rd),
                                (int32_t*)(d + o_no), (uint32_t*)(d + o_ops));
         } else {
-            hipLaunchKernelGGL(k_align_pairs<kAlThreads>, dim3(nr), dim3(kAlThreads), lds, st, d_pairs,
+            hipLaunchKernelGGL(k_align_pairs<kAlThreadsShort>, dim3(nr), dim3(kAlThreadsShort), lds, st, d_pairs,
                                d_order, d_codes, cap, kp, km, (int32_t*)(d + o_rs),
                                (uint32_t*)(d + o_done), (int32_t*)(d + o_sc), (int32_t*)(d + o_rd),
                                (int32_t*)(d + o_no), (uint32_t*)(d + o_ops));
