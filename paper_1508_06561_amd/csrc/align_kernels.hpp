@@ -11,11 +11,10 @@
 // One workgroup per (pair, round) scores that round: its threads share each
 // step's placements, four neighbouring ones to a thread (they share their
 // letter reads), summing the letters that face each other from the two
-// sequences staged in LDS.  The
-// workgroup that finishes a pair's last round then replays the pair's best
-// round (its sequences are still staged) and writes its run-length ops, so
-// that a long pair's replay follows its own rounds rather than waiting for
-// every pair's.
+// sequences staged in LDS.  The workgroup that finishes a pair's last round
+// then replays the pair's best round (its sequences are still staged) and
+// writes its run-length ops, so that a long pair's replay follows its own
+// rounds rather than waiting for every pair's.
 #pragma once
 
 #include "device_common.hpp"
@@ -29,7 +28,7 @@ constexpr int kAlThreadsShort = 128;             // threads per (pair, round) of
 constexpr int kAlThreadsLong = 1024;             // of batches holding a long pair
 constexpr int kAlWavesMax = kAlThreadsLong / kLanes;
 constexpr int kAlLongPair = 4000;                // letters: a long pair
-constexpr int kAlMaxLen = 5600;    // longest sequence of the pairwise mode
+constexpr int kAlMaxLen = 5600;                  // longest sequence of the pairwise mode
 
 // One pair of a pairwise batch: query codes at qoff, target codes at toff.
 struct AlignPair {
@@ -105,9 +104,8 @@ __device__ __forceinline__ void al_emit(uint32_t* ops, int32_t& n_ops, uint32_t 
 // score (SCORE of its aligned rows, streamed step by step) and, with kEmit,
 // its ops written by thread 0.  Each thread takes four neighbouring
 // placements at a time, which read their large letters as one word and
-// share the small letter.  The
-// large sequence (nl letters, as L4) and the small one (ns <= nl, as S) are
-// in LDS; tl: the target is the large one.
+// share the small letter.  The large sequence (nl letters, as L4) and the
+// small one (ns <= nl, as S) are in LDS; tl: the target is the large one.
 template <int kT, bool kEmit>
 __device__ int32_t al_round(AlignLds& A, int32_t nl, int32_t ns, bool tl, const KParams& kp,
                             int32_t id, int32_t round, uint32_t* ops, int32_t* n_ops_out) {

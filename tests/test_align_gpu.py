@@ -80,6 +80,23 @@ def test_random_pairs_rounds20(name):
     check_pairs(pairs, p)
 
 
+@pytest.mark.parametrize("rounds", [1, 2])
+def test_few_rounds(rounds):
+    """Rounds = 1 (each round's workgroup writes its ops in the same pass)
+    and Rounds = 2 (the second finisher replays the better round)."""
+    rng = np.random.default_rng(50 + rounds)
+    pairs = rand_pairs(rng, 80, 1, 400)
+    for _ in range(20):
+        q = synth.random_protein(rng, int(rng.integers(50, 400)))
+        pairs.append((q, synth.embed(rng, synth.mutate(rng, q, rng.uniform(0.3, 0.9)),
+                                     int(rng.integers(len(q), 600)))))
+    say(f"pairwise: {len(pairs)} pairs, Rounds {rounds}")
+    check_pairs(pairs, H().Params(rounds=rounds, seed=rounds))
+    L = H().hs.MAX_ALIGN
+    check_pairs([(synth.random_protein(rng, L), synth.random_protein(rng, L - 7))],
+                H().Params(rounds=rounds, seed=9))
+
+
 def test_homologs_rounds20():
     """Mutated copies with indels (the paper's distant-homology use)."""
     rng = np.random.default_rng(31)
