@@ -295,6 +295,37 @@ int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char*
                    int32_t* rounds, uint32_t* ops, int64_t ops_cap, int64_t* ops_off,
                    int64_t* ops_used);
 
+/* Device workspace bytes of hs_align_batch_dev for n pairs at `rounds`
+ * rounds (about 16 + 4 * rounds bytes per pair); 0 when n or rounds is out
+ * of range. */
+int64_t hs_align_workspace_bytes(int32_t n, int32_t rounds);
+
+/* Device form of hs_align_batch (the pairwise mode of Fig. 1, best of
+ * Rounds; Section III.B.2, Section V): the letters are already in device
+ * memory and the results stay there.  Queues the work on `stream` and
+ * returns; only the pair table (32 bytes per pair, built from the host
+ * offsets) is copied from the host.
+ *   d_codes          device letter codes (as hs_encode writes them, 0..23;
+ *                    larger values read as 23)
+ *   qoff, toff       host offsets into d_codes, n + 1 each: pair i's query is
+ *                    d_codes[qoff[i] .. qoff[i+1]), its target
+ *                    d_codes[toff[i] .. toff[i+1]), each 1..HS_MAX_ALIGN
+ *                    letters; pair i's draws are keyed by i
+ *   d_ws, ws_bytes   device workspace of at least
+ *                    hs_align_workspace_bytes(n, params->rounds) bytes
+ *   d_scores         device int32[n]: each pair's score
+ *   d_rounds         device int32[n]: the best round (may be NULL)
+ *   d_ops            device uint32 array of sum(qlen + tlen) entries: pair
+ *                    i's run-length ops, oriented (query, target), from entry
+ *                    (qoff[i] - qoff[0]) + (toff[i] - toff[0]) on, in a slot
+ *                    of its qlen + tlen entries
+ *   d_n_ops          device int32[n]: each pair's op count
+ * Pair i's results equal hs_align_batch's.  Errors: HS_EINVAL (arguments),
+ * HS_ENOSPC (workspace too small), HS_EDEVICE. */
+int hs_align_batch_dev(int32_t n, const uint8_t* d_codes, const int64_t* qoff, const int64_t* toff,
+                       const hs_params* params, void* stream, void* d_ws, size_t ws_bytes,
+                       int32_t* d_scores, int32_t* d_rounds, uint32_t* d_ops, int32_t* d_n_ops);
+
 /* One pair: hs_align_batch with n = 1; *n_ops receives the op count (also on
  * HS_ENOSPC). */
 int hs_align(const char* query, int32_t qlen, const char* target, int32_t tlen,

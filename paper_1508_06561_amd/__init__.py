@@ -4,9 +4,9 @@ database, ranked, with alignments for the best hits.  The work runs in the
 HIP kernels of libhs.so behind the C ABI of include/hs.h; this package is the
 Python binding of that ABI."""
 from .hs import (ALPHABET, Alignment, Batch, HSError, Database, DeviceSearch, Params, Result,
-                 Server, align, align_batch, builtin_matrix, encode, lib, params_default,
-                 search_batch)
+                 Server, align, align_batch, align_batch_dev, align_workspace_bytes, builtin_matrix,
+                 encode, lib, params_default, search_batch)
 
 __all__ = ["ALPHABET", "Alignment", "Batch", "HSError", "Database", "DeviceSearch", "Params",
-           "Result", "Server", "align", "align_batch", "builtin_matrix", "encode", "lib",
-           "params_default", "search_batch"]
+           "Result", "Server", "align", "align_batch", "align_batch_dev", "align_workspace_bytes",
+           "builtin_matrix", "encode", "lib", "params_default", "search_batch"]

@@ -235,15 +235,17 @@ __device__ __forceinline__ void al_stage(AlignLds& A, const AlignPair& P, const 
     ns = tl ? P.qlen : P.tlen;
     const uint8_t* src_l = codes + (tl ? P.toff : P.qoff);
     const uint8_t* src_s = codes + (tl ? P.qoff : P.toff);
+    // codes above the alphabet's last (possible in device input) read as it
+    auto code = [](uint8_t c) { return (uint32_t)(c < kNsym ? c : kNsym - 1); };
     for (int32_t i = threadIdx.x; i < nl; i += kT) {
         // letters i .. i + 3 (past the end: 0, never summed)
-        uint32_t w = src_l[i];
-        if (i + 1 < nl) w |= (uint32_t)src_l[i + 1] << 8;
-        if (i + 2 < nl) w |= (uint32_t)src_l[i + 2] << 16;
-        if (i + 3 < nl) w |= (uint32_t)src_l[i + 3] << 24;
+        uint32_t w = code(src_l[i]);
+        if (i + 1 < nl) w |= code(src_l[i + 1]) << 8;
+        if (i + 2 < nl) w |= code(src_l[i + 2]) << 16;
+        if (i + 3 < nl) w |= code(src_l[i + 3]) << 24;
         A.L4[i] = w;
     }
-    for (int32_t i = threadIdx.x; i < ns; i += kT) A.S[i] = src_s[i];
+    for (int32_t i = threadIdx.x; i < ns; i += kT) A.S[i] = (uint8_t)code(src_s[i]);
     // matT[s * kNsym + l] = score of large letter l against small letter s
     for (int32_t i = threadIdx.x; i < kNsym * kNsym; i += kT)
         A.matT[i] = km.m[(i % kNsym) * kNsym + i / kNsym];
@@ -256,8 +258,9 @@ __device__ __forceinline__ void al_stage(AlignLds& A, const AlignPair& P, const 
 // pair's rounds (the pair's counter in `done`, zero at launch, reaching
 // rounds) replays the best round (the first with the highest score) with
 // its sequences still in LDS: score, round, op count and ops at
-// ops + pairs[pair].ops_off.  kT threads per workgroup; no sequence longer
-// than cap letters; al_lds_bytes(cap) bytes of dynamic LDS.
+// ops + pairs[pair].ops_off (rounds may be NULL).  kT threads per
+// workgroup; no sequence longer than cap letters; al_lds_bytes(cap) bytes of
+// dynamic LDS.
 template <int kT>
 __global__ __launch_bounds__(kT) void k_align_pairs(const AlignPair* __restrict__ pairs,
                                                     const int32_t* __restrict__ order,
@@ -281,7 +284,7 @@ __global__ __launch_bounds__(kT) void k_align_pairs(const AlignPair* __restrict_
         const int32_t s1 = al_round<kT, true>(A, nl, ns, tl, kp, pair, 0, ops + P.ops_off, n_ops + pair);
         if (threadIdx.x == 0) {
             scores[pair] = s1;
-            rounds[pair] = 0;
+            if (rounds) rounds[pair] = 0;
         }
         return;
     }
@@ -312,7 +315,7 @@ __global__ __launch_bounds__(kT) void k_align_pairs(const AlignPair* __restrict_
     const int32_t s2 = al_round<kT, true>(A, nl, ns, tl, kp, pair, best_r, ops + P.ops_off, n_ops + pair);
     if (threadIdx.x == 0) {
         scores[pair] = s2;       // equal to the round's score: the replay is the same round
-        rounds[pair] = best_r;
+        if (rounds) rounds[pair] = best_r;
     }
 }
 

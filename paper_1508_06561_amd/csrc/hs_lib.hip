@@ -1607,42 +1607,58 @@ int hs_search_threshold(const hs_db* db, const char* query, int32_t qlen, const 
     return HS_OK;
 }
 
-int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char* tres,
-                   const int64_t* toff, const hs_params* params, void* stream, int32_t* scores,
-                   int32_t* rounds, uint32_t* ops, int64_t ops_cap, int64_t* ops_off,
-                   int64_t* ops_used) {
+namespace {
+
+// Pairwise workspace: pair table, work order, per-round scores, pair counters.
+struct AlignWs {
+    size_t o_pairs, o_order, o_rs, o_done, total;
+    AlignWs(int32_t n, int32_t rounds) {
+        o_pairs = 0;
+        o_order = align_up(sizeof(AlignPair) * (size_t)n);
+        o_rs = o_order + align_up(sizeof(int32_t) * (size_t)n);
+        o_done = o_rs + align_up(sizeof(int32_t) * (size_t)n * (size_t)rounds);
+        total = o_done + align_up(sizeof(uint32_t) * (size_t)n);
+    }
+};
+
+// Checks the pairs' lengths (host offsets) and fills their table: codes at
+// qoff[i] / toff[i] relative to `base`, each pair's op slot after the
+// previous pairs' (qlen + tlen entries each).  Returns the longest sequence
+// in *longest.
+int align_pairs_table(int32_t n, const int64_t* qoff, const int64_t* toff, const hs_params* params,
+                      std::vector<AlignPair>& pairs, int64_t* longest) {
     if (n < 1 || n > HS_MAX_ALIGN_PAIRS) return fail(HS_EINVAL, "n must lie in [1, HS_MAX_ALIGN_PAIRS]");
-    if (!qres || !qoff || !tres || !toff || !scores || !ops_off || !ops_used)
-        return fail(HS_EINVAL, "NULL pointer");
+    if (!qoff || !toff) return fail(HS_EINVAL, "NULL offsets");
     int rc = check_params(params);
     if (rc) return rc;
     if ((int64_t)n * params->rounds > 0x7FFFFFFF) return fail(HS_EINVAL, "n * rounds too large");
-    int64_t nq = 0, nt = 0, nops = 0, longest = 0;
+    pairs.resize((size_t)n);
+    int64_t co = 0, lo = 0;
     for (int32_t i = 0; i < n; ++i) {
         const int64_t a = qoff[i + 1] - qoff[i], b = toff[i + 1] - toff[i];
-        longest = std::max(longest, std::max(a, b));
         if (a < 1 || a > HS_MAX_ALIGN || b < 1 || b > HS_MAX_ALIGN)
             return fail(HS_EINVAL, "pair " + std::to_string(i) + ": lengths must lie in [1, HS_MAX_ALIGN]");
-        nq += a;
-        nt += b;
-        nops += a + b;          // runs never outnumber columns
-    }
-    std::vector<uint8_t> codes((size_t)(nq + nt));
-    std::vector<AlignPair> pairs((size_t)n);
-    int64_t cq = 0, ct = nq, co = 0;
-    for (int32_t i = 0; i < n; ++i) {
         AlignPair& P = pairs[(size_t)i];
-        P.qlen = (int32_t)(qoff[i + 1] - qoff[i]);
-        P.tlen = (int32_t)(toff[i + 1] - toff[i]);
-        if ((rc = hs_encode(qres + qoff[i], P.qlen, codes.data() + cq))) return rc;
-        if ((rc = hs_encode(tres + toff[i], P.tlen, codes.data() + ct))) return rc;
-        P.qoff = cq;
-        P.toff = ct;
+        P.qlen = (int32_t)a;
+        P.tlen = (int32_t)b;
+        P.qoff = qoff[i];
+        P.toff = toff[i];
         P.ops_off = co;
-        cq += P.qlen;
-        ct += P.tlen;
-        co += P.qlen + P.tlen;
+        co += a + b;          // runs never outnumber columns
+        lo = std::max(lo, std::max(a, b));
     }
+    *longest = lo;
+    return HS_OK;
+}
+
+// Queues the pairwise rounds and replays of the pairs (table `pairs`, codes
+// relative to d_codes) on st, with the workspace at ws (AlignWs layout):
+// scores, rounds (may be NULL), op counts and ops in the pairs' slots.
+int align_queue(const std::vector<AlignPair>& pairs, int64_t longest, const uint8_t* d_codes,
+                const hs_params* params, hipStream_t st, char* ws, int32_t* d_scores,
+                int32_t* d_rounds, int32_t* d_n_ops, uint32_t* d_ops) {
+    const int32_t n = (int32_t)pairs.size();
+    const AlignWs L(n, params->rounds);
     // workgroups take the pairs with the most cells per round first (a
     // round's cells grow with the product of the lengths), so that the
     // longest chains of steps start at once
@@ -1652,15 +1668,89 @@ int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char*
         return (int64_t)pairs[(size_t)a].qlen * pairs[(size_t)a].tlen >
                (int64_t)pairs[(size_t)b].qlen * pairs[(size_t)b].tlen;
     });
+    if (hipMemcpyAsync(ws + L.o_pairs, pairs.data(), sizeof(AlignPair) * (size_t)n, hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipMemcpyAsync(ws + L.o_order, order.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipMemsetAsync(ws + L.o_done, 0, sizeof(uint32_t) * (size_t)n, st) != hipSuccess)
+        return fail(HS_EDEVICE, "pair upload failed");
+    const KParams kp = kparams(params);
+    const KMatrix km = kmatrix(params);
+    const AlignPair* d_pairs = (const AlignPair*)(ws + L.o_pairs);
+    const int32_t* d_order = (const int32_t*)(ws + L.o_order);
+    int32_t* d_rs = (int32_t*)(ws + L.o_rs);
+    uint32_t* d_done = (uint32_t*)(ws + L.o_done);
+    const unsigned nr = (unsigned)((int64_t)n * params->rounds);
+    // LDS sized to the longest sequence, so that batches of short pairs
+    // keep many workgroups on a compute unit
+    const int32_t cap = (int32_t)longest;
+    const size_t lds = al_lds_bytes(cap);
+    // a batch holding a pair of kAlLongPair letters or more gives each
+    // (pair, round) 1,024 threads: a step of a long pair has thousands of
+    // placements (the 5,600 x 5,600 pair at Rounds 20: 5.8 ms with 256
+    // threads, 1.6 ms with 1,024, before the four placements per thread);
+    // batches of shorter pairs take 128 threads, enough for the few
+    // hundred placements of their steps (1,000 pairs of up to 2,000
+    // letters: kernel 0.87 ms, against 1.07 with 256 threads taking one
+    // placement each, 1.46 with 256 taking four, 1.23 with 64)
+    if (longest >= kAlLongPair)
+        hipLaunchKernelGGL(k_align_pairs<kAlThreadsLong>, dim3(nr), dim3(kAlThreadsLong), lds, st, d_pairs,
+                           d_order, d_codes, cap, kp, km, d_rs, d_done, d_scores, d_rounds, d_n_ops, d_ops);
+    else
+        hipLaunchKernelGGL(k_align_pairs<kAlThreadsShort>, dim3(nr), dim3(kAlThreadsShort), lds, st, d_pairs,
+                           d_order, d_codes, cap, kp, km, d_rs, d_done, d_scores, d_rounds, d_n_ops, d_ops);
+    if (hipGetLastError() != hipSuccess) return fail(HS_EDEVICE, "pairwise kernel failed to launch");
+    return HS_OK;
+}
+
+}  // namespace
+
+int64_t hs_align_workspace_bytes(int32_t n, int32_t rounds) {
+    if (n < 1 || n > HS_MAX_ALIGN_PAIRS || rounds < 1 || rounds > 1024) return 0;
+    return (int64_t)AlignWs(n, rounds).total;
+}
+
+int hs_align_batch_dev(int32_t n, const uint8_t* d_codes, const int64_t* qoff, const int64_t* toff,
+                       const hs_params* params, void* stream, void* d_ws, size_t ws_bytes,
+                       int32_t* d_scores, int32_t* d_rounds, uint32_t* d_ops, int32_t* d_n_ops) {
+    std::vector<AlignPair> pairs;
+    int64_t longest = 0;
+    int rc = align_pairs_table(n, qoff, toff, params, pairs, &longest);
+    if (rc) return rc;
+    if (!d_codes || !d_ws || !d_scores || !d_ops || !d_n_ops) return fail(HS_EINVAL, "NULL device pointer");
+    if (ws_bytes < AlignWs(n, params->rounds).total) return fail(HS_ENOSPC, "workspace too small");
+    return align_queue(pairs, longest, d_codes, params, (hipStream_t)stream, (char*)d_ws, d_scores,
+                       d_rounds, d_n_ops, d_ops);
+}
+
+int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char* tres,
+                   const int64_t* toff, const hs_params* params, void* stream, int32_t* scores,
+                   int32_t* rounds, uint32_t* ops, int64_t ops_cap, int64_t* ops_off,
+                   int64_t* ops_used) {
+    if (!qres || !tres || !scores || !ops_off || !ops_used) return fail(HS_EINVAL, "NULL pointer");
+    // the pairs' letters go to the device back to back, queries first: their
+    // offsets there are the host offsets less the first, targets after the
+    // queries
+    std::vector<AlignPair> pairs;
+    int64_t longest = 0;
+    int rc = align_pairs_table(n, qoff, toff, params, pairs, &longest);
+    if (rc) return rc;
+    const int64_t nq = qoff[n] - qoff[0], nt = toff[n] - toff[0];
+    for (AlignPair& P : pairs) {
+        P.qoff -= qoff[0];
+        P.toff += nq - toff[0];
+    }
+    const int64_t nops = nq + nt;
+    std::vector<uint8_t> codes((size_t)(nq + nt));
+    if ((rc = hs_encode(qres + qoff[0], nq, codes.data()))) return rc;
+    if ((rc = hs_encode(tres + toff[0], nt, codes.data() + nq))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    // device layout: codes, pairs and their order, per-round scores, pair
-    // counters, then one region of scores, rounds and packed offsets (read
-    // back by one copy), op counts, ops in per-pair slots, packed ops
-    const size_t o_codes = 0, o_pairs = align_up(codes.size()),
-                 o_order = o_pairs + align_up(sizeof(AlignPair) * (size_t)n),
-                 o_rs = o_order + align_up(sizeof(int32_t) * (size_t)n),
-                 o_done = o_rs + align_up(sizeof(int32_t) * (size_t)n * params->rounds),
-                 o_sc = o_done + align_up(sizeof(uint32_t) * (size_t)n),
+    // device layout: codes, the pairwise workspace, then one region of
+    // scores, rounds and packed offsets (read back by one copy), op counts,
+    // ops in per-pair slots, packed ops
+    const AlignWs W(n, params->rounds);
+    const size_t o_codes = 0, o_ws = align_up(codes.size()),
+                 o_sc = o_ws + W.total,
                  o_rd = o_sc + sizeof(int32_t) * (size_t)n,
                  o_off = (o_rd + sizeof(int32_t) * (size_t)n + 7) & ~(size_t)7,
                  o_no = align_up(o_off + sizeof(int64_t) * ((size_t)n + 1)),
@@ -1671,44 +1761,15 @@ int hs_align_batch(int32_t n, const char* qres, const int64_t* qoff, const char*
     if (hipMallocAsync((void**)&d, total, st) != hipSuccess)
         return fail(HS_ENOMEM, "device allocation failed");
     std::vector<char> h_head(o_no - o_sc);
-    const KParams kp = kparams(params);
-    const KMatrix km = kmatrix(params);
-    rc = HS_OK;
-    if (hipMemcpyAsync(d + o_codes, codes.data(), codes.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(d + o_pairs, pairs.data(), sizeof(AlignPair) * (size_t)n, hipMemcpyHostToDevice,
-                       st) != hipSuccess ||
-        hipMemcpyAsync(d + o_order, order.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice,
-                       st) != hipSuccess ||
-        hipMemsetAsync(d + o_done, 0, sizeof(uint32_t) * (size_t)n, st) != hipSuccess)
-        rc = fail(HS_EDEVICE, "pair upload failed");
+    if (hipMemcpyAsync(d + o_codes, codes.data(), codes.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = fail(HS_EDEVICE, "letter upload failed");
+    if (!rc)
+        rc = align_queue(pairs, longest, (const uint8_t*)(d + o_codes), params, st, d + o_ws,
+                         (int32_t*)(d + o_sc), (int32_t*)(d + o_rd), (int32_t*)(d + o_no),
+                         (uint32_t*)(d + o_ops));
     if (!rc) {
-        const AlignPair* d_pairs = (const AlignPair*)(d + o_pairs);
-        const uint8_t* d_codes = (const uint8_t*)(d + o_codes);
-        const unsigned nr = (unsigned)((int64_t)n * params->rounds);
-        // a batch holding a pair of kAlLongPair letters or more gives each
-        // (pair, round) 1,024 threads: a step of a long pair has thousands of
-        // placements (the 5,600 x 5,600 pair at Rounds 20: 5.8 ms with 256
-        // threads, 1.6 ms with 1,024, before the four placements per thread);
-        // batches of shorter pairs take 128 threads, enough for the few
-        // hundred placements of their steps (1,000 pairs of up to 2,000
-        // letters: kernel 0.87 ms, against 1.07 with 256 threads taking one
-        // placement each, 1.46 with 256 taking four, 1.23 with 64)
-        const int32_t* d_order = (const int32_t*)(d + o_order);
-        // LDS sized to the longest sequence, so that batches of short pairs
-        // keep many workgroups on a compute unit
-        const int32_t cap = (int32_t)longest;
-        const size_t lds = al_lds_bytes(cap);
-        if (longest >= kAlLongPair) {
-            hipLaunchKernelGGL(k_align_pairs<kAlThreadsLong>, dim3(nr), dim3(kAlThreadsLong), lds, st,
-                               d_pairs, d_order, d_codes, cap, kp, km, (int32_t*)(d + o_rs),
-                               (uint32_t*)(d + o_done), (int32_t*)(d + o_sc), (int32_t*)(d + o_rd),
-                               (int32_t*)(d + o_no), (uint32_t*)(d + o_ops));
-        } else {
-            hipLaunchKernelGGL(k_align_pairs<kAlThreadsShort>, dim3(nr), dim3(kAlThreadsShort), lds, st, d_pairs,
-                               d_order, d_codes, cap, kp, km, (int32_t*)(d + o_rs),
-                               (uint32_t*)(d + o_done), (int32_t*)(d + o_sc), (int32_t*)(d + o_rd),
-                               (int32_t*)(d + o_no), (uint32_t*)(d + o_ops));
-        }
+        // pack: a scan over the pairs' op counts, then one wavefront per pair
+        const AlignPair* d_pairs = (const AlignPair*)(d + o_ws + W.o_pairs);
         hipLaunchKernelGGL(k_align_ops_scan, dim3(1), dim3(kAlScanThreads), 0, st,
                            (const int32_t*)(d + o_no), n, (int64_t*)(d + o_off));
         hipLaunchKernelGGL(k_align_ops_pack, dim3((unsigned)((n + kAlWaves - 1) / kAlWaves)), dim3(kAlThreads),

@@ -130,6 +130,10 @@ def lib():
                                      vp, pi32, pi32, vp, i64, P(ctypes.c_int64), P(ctypes.c_int64)]
         L.hs_align.argtypes = [ctypes.c_char_p, i32, ctypes.c_char_p, i32, P(_CParams), vp, pi32,
                                pi32, vp, i64, P(ctypes.c_int64)]
+        L.hs_align_workspace_bytes.argtypes = [i32, i32]
+        L.hs_align_workspace_bytes.restype = ctypes.c_int64
+        L.hs_align_batch_dev.argtypes = [i32, vp, P(ctypes.c_int64), P(ctypes.c_int64), P(_CParams), vp,
+                                         vp, ctypes.c_size_t, vp, vp, vp, vp]
         L.hs_server_create.argtypes = [vp, i32, i32, i64, i32, i32, P(vp)]
         L.hs_server_create_workers.argtypes = [vp, i32, i32, i64, i32, i32, i32, P(vp)]
         L.hs_server_free.argtypes = [vp]
@@ -598,6 +602,32 @@ def align_batch(pairs, params=None, stream=None):
     o = ops_off.tolist()
     return list(map(Alignment, scores.tolist(), rounds.tolist(),
                     [ops[a:b] for a, b in zip(o[:-1], o[1:])]))
+
+
+def align_workspace_bytes(n, rounds):
+    """Device workspace bytes of align_batch_dev (hs_align_workspace_bytes)."""
+    b = lib().hs_align_workspace_bytes(n, rounds)
+    if b <= 0:
+        raise HSError(HS_EINVAL, "n or rounds out of range")
+    return int(b)
+
+
+def align_batch_dev(d_codes, qoff, toff, params, d_ws, d_scores, d_rounds, d_ops, d_n_ops,
+                    stream=None):
+    """Queues hs_align_batch_dev: pair i's query d_codes[qoff[i]:qoff[i+1]]
+    against its target d_codes[toff[i]:toff[i+1]] (device uint8 codes, host
+    int64 offsets); results into the device tensors (d_rounds may be None),
+    pair i's ops from (qoff[i] - qoff[0]) + (toff[i] - toff[0]) on."""
+    qoff = np.ascontiguousarray(qoff, dtype=np.int64)
+    toff = np.ascontiguousarray(toff, dtype=np.int64)
+    p = (params or Params()).c()
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    _check(lib().hs_align_batch_dev(len(qoff) - 1, d_codes.data_ptr(), qoff.ctypes.data_as(P64),
+                                    toff.ctypes.data_as(P64), ctypes.byref(p), _stream(stream),
+                                    d_ws.data_ptr(), d_ws.numel() * d_ws.element_size(),
+                                    d_scores.data_ptr(),
+                                    d_rounds.data_ptr() if d_rounds is not None else None,
+                                    d_ops.data_ptr(), d_n_ops.data_ptr()))
 
 
 def align(query, target, params=None, stream=None):

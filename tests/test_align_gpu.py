@@ -146,6 +146,59 @@ def test_thousand_pairs_of_mixed_lengths():
     assert len({g.round for g in got}) > 10        # the best round varies over the pairs
 
 
+def test_device_form_equals_host_form():
+    """hs_align_batch_dev (letters and results in device memory) gives what
+    hs_align_batch gives, pair by pair, at Rounds 20 and 1 (rounds output
+    omitted), on short pairs and on a batch holding a longest pair; codes
+    above the alphabet's last read as it; a short workspace is refused."""
+    import torch
+    Hm = H()
+    rng = np.random.default_rng(36)
+    short = rand_pairs(rng, 200, 1, 500)
+    longp = short[:20] + [(synth.random_protein(rng, Hm.hs.MAX_ALIGN), synth.random_protein(rng, 4500))]
+    for pairs, rounds in ((short, 20), (short, 1), (longp, 20)):
+        p = Hm.Params(rounds=rounds, seed=17)
+        host = Hm.align_batch(pairs, p)
+        qs = [Hm.encode(bytes(q)) for q, _ in pairs]
+        ts = [Hm.encode(bytes(t)) for _, t in pairs]
+        # targets first, queries after them, to check that offsets are honoured
+        tl = np.cumsum([0] + [len(t) for t in ts])
+        ql = np.cumsum([0] + [len(q) for q in qs]) + tl[-1]
+        codes = torch.from_numpy(np.concatenate(ts + qs)).cuda()
+        n = len(pairs)
+        ws = torch.empty(Hm.align_workspace_bytes(n, rounds), dtype=torch.uint8, device="cuda")
+        sc = torch.empty(n, dtype=torch.int32, device="cuda")
+        rd = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+        total = int(tl[-1] + ql[-1] - ql[0])
+        ops = torch.zeros(total, dtype=torch.int32, device="cuda")
+        nops = torch.empty(n, dtype=torch.int32, device="cuda")
+        Hm.align_batch_dev(codes, ql, tl, p, ws, sc, rd if rounds > 1 else None, ops, nops)
+        torch.cuda.synchronize()
+        sc, rd, ops, nops = sc.cpu().numpy(), rd.cpu().numpy(), ops.cpu().numpy().view(np.uint32), nops.cpu().numpy()
+        for i, h in enumerate(host):
+            slot = int(ql[i] - ql[0] + tl[i] - tl[0])
+            assert sc[i] == h.score, f"pair {i}"
+            assert rd[i] == (h.round if rounds > 1 else -7), f"pair {i}"
+            assert np.array_equal(ops[slot:slot + nops[i]], h.ops), f"ops of pair {i}"
+    # a code above 23 reads as 23 ('*')
+    q, t = Hm.encode(b"ACDW*"), Hm.encode(b"WACD*")
+    bad = torch.from_numpy(np.concatenate([q[:4], np.array([200], np.uint8), t])).cuda()
+    assert bad.dtype == torch.uint8
+    ref = Hm.align(b"ACDW*", b"WACD*", Hm.Params(rounds=3))
+    ws = torch.empty(Hm.align_workspace_bytes(1, 3), dtype=torch.uint8, device="cuda")
+    sc = torch.empty(1, dtype=torch.int32, device="cuda")
+    ops = torch.zeros(10, dtype=torch.int32, device="cuda")
+    nops = torch.empty(1, dtype=torch.int32, device="cuda")
+    Hm.align_batch_dev(bad, [0, 5], [5, 10], Hm.Params(rounds=3), ws, sc, None, ops, nops)
+    torch.cuda.synchronize()
+    assert int(sc.cpu()[0]) == ref.score
+    assert np.array_equal(ops.cpu().numpy().view(np.uint32)[:int(nops.cpu()[0])], ref.ops)
+    with pytest.raises(Hm.HSError):
+        Hm.align_batch_dev(bad, [0, 5], [5, 10], Hm.Params(rounds=3), ws[:8], sc, None, ops, nops)
+    with pytest.raises(Hm.HSError):
+        Hm.align_batch_dev(bad, [0, 5], [5, 5], Hm.Params(rounds=3), ws, sc, None, ops, nops)
+
+
 def test_single_equals_batch():
     rng = np.random.default_rng(34)
     q, t = synth.random_protein(rng, 120), synth.random_protein(rng, 90)
