@@ -319,6 +319,14 @@ __global__ __launch_bounds__(kT) void k_align_pairs(const AlignPair* __restrict_
     }
 }
 
+// Zeroes the pairs' round counters before k_align_pairs (a kernel rather
+// than a memset, so that work queued on a stream being captured into a
+// graph holds no memset node).
+__global__ __launch_bounds__(256) void k_align_reset(uint32_t* __restrict__ done, int32_t n) {
+    const int32_t i = (int32_t)blockIdx.x * 256 + (int32_t)threadIdx.x;
+    if (i < n) done[i] = 0;
+}
+
 // Exclusive prefix sums of the pairs' op counts, one workgroup: off[i] is
 // the first packed op of pair i, off[n] the total.  Each thread sums a run of
 // consecutive counts, the run totals are scanned in LDS, and each thread

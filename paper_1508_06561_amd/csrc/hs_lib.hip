@@ -1671,9 +1671,10 @@ int align_queue(const std::vector<AlignPair>& pairs, int64_t longest, const uint
     if (hipMemcpyAsync(ws + L.o_pairs, pairs.data(), sizeof(AlignPair) * (size_t)n, hipMemcpyHostToDevice,
                        st) != hipSuccess ||
         hipMemcpyAsync(ws + L.o_order, order.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice,
-                       st) != hipSuccess ||
-        hipMemsetAsync(ws + L.o_done, 0, sizeof(uint32_t) * (size_t)n, st) != hipSuccess)
+                       st) != hipSuccess)
         return fail(HS_EDEVICE, "pair upload failed");
+    hipLaunchKernelGGL(k_align_reset, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       (uint32_t*)(ws + L.o_done), n);
     const KParams kp = kparams(params);
     const KMatrix km = kmatrix(params);
     const AlignPair* d_pairs = (const AlignPair*)(ws + L.o_pairs);
