@@ -65,8 +65,10 @@ extern "C" {
  * not reported).  `seed` keys the random stream: draws depend only on
  * (seed, target index, round, draw index), never on batching or order.
  * `matrix` is a host pointer to a 24x24 row-major int8 substitution matrix in
- * alphabet order, or NULL for the built-in BLOSUM62; its largest and smallest
- * entries may differ by at most 15 (BLOSUM62: -4..11). */
+ * alphabet order, or NULL for the built-in BLOSUM62; entry [a][b] scores
+ * query letter a against target letter b (whichever sequence is the longer);
+ * its largest and smallest entries may differ by at most 15 (BLOSUM62:
+ * -4..11). */
 typedef struct hs_params {
     int32_t gop;            /* gap opening penalty */
     int32_t gep;            /* gap extension penalty */

@@ -153,7 +153,9 @@ def rows_to_ops(qrow, trow):
 
 
 def align_pair(q, t, target_id=0, params=None, matrix=None, trace=False):
-    """Search-mode heuristic alignment of query q against target t (codes).
+    """Search-mode heuristic alignment of query q against target t (codes);
+    `matrix` (24 x 24, default BLOSUM62) scores a query letter (row) against a
+    target letter (column).
 
     Returns dict(score, round, qrow, trow (codes, GAP for gaps), ops, cells,
     trace) where trace lists (pL, pS, ls, ss, kstar, dscore) per step of the
@@ -185,7 +187,8 @@ def align_pair(q, t, target_id=0, params=None, matrix=None, trace=False):
 
 
 def score_rows(row_a, row_b, params=None, matrix=None):
-    """SCORE of two aligned rows of codes (GAP = gap)."""
+    """SCORE of two aligned rows of codes (GAP = gap); the matrix scores a
+    row_a letter (row) against a row_b letter (column)."""
     p = params or Params()
     a = np.ascontiguousarray(row_a, dtype=np.uint8)
     b = np.ascontiguousarray(row_b, dtype=np.uint8)

@@ -45,6 +45,9 @@
  *     (strict '>' in Fig. 1).
  *   - A gap run of g columns inside the gapped sequence costs GOP+(g-1)*GEP;
  *     every leading or trailing gap column costs PGP.
+ *   - A substitution matrix scores a query letter (row) against a target
+ *     letter (column), whichever of the two is the large sequence (the paper
+ *     uses only the symmetric BLOSUM62, where the order does not matter).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -180,7 +183,7 @@ typedef struct {
 } orc_step;
 
 typedef struct {
-    const int8_t* B;            /* 24 x 24 substitution matrix */
+    const int8_t* B;            /* 24 x 24, looked up as [large letter][small letter] */
     const orc_params* p;
     uint64_t target_id;
     int64_t cells;              /* residue pairs scored on diagonals */
@@ -329,8 +332,18 @@ int orc_align_pair(const uint8_t* q, int32_t qlen, const uint8_t* tg, int32_t tl
                    orc_step* trace, int32_t trace_cap, int32_t* n_steps,
                    int64_t* cells) {
     if (qlen <= 0 || tlen <= 0 || p->rounds < 1) return -1;
-    orc_ctx cx = {matrix ? matrix : &orc_blosum62[0][0], p, target_id, 0};
+    /* The matrix scores a query letter (row) against a target letter
+     * (column).  The rounds look it up as [large letter][small letter], so
+     * it is transposed when the target is the large sequence. */
+    const int8_t* M = matrix ? matrix : &orc_blosum62[0][0];
     int target_is_large = tlen >= qlen;
+    int8_t MT[ORC_NSYM * ORC_NSYM];
+    if (target_is_large) {
+        for (int a = 0; a < ORC_NSYM; ++a)
+            for (int b = 0; b < ORC_NSYM; ++b) MT[b * ORC_NSYM + a] = M[a * ORC_NSYM + b];
+        M = MT;
+    }
+    orc_ctx cx = {M, p, target_id, 0};
     const uint8_t* large = target_is_large ? tg : q;
     const uint8_t* small = target_is_large ? q : tg;
     int32_t nl = target_is_large ? tlen : qlen;
@@ -423,7 +436,8 @@ int orc_search_subset(const uint8_t* db, const int64_t* offsets, const int64_t* 
     return 0;
 }
 
-/* Score of two given aligned rows (codes, ORC_GAP for gaps) under SCORE. */
+/* Score of two given aligned rows (codes, ORC_GAP for gaps) under SCORE;
+ * the matrix is looked up as [row_a letter][row_b letter] (query row first). */
 int64_t orc_score_rows(const uint8_t* row_a, const uint8_t* row_b, int32_t n,
                        const orc_params* p, const int8_t* matrix) {
     return score_columns(matrix ? matrix : &orc_blosum62[0][0], row_a, row_b, n, p);

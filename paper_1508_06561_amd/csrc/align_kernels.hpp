@@ -246,9 +246,12 @@ __device__ __forceinline__ void al_stage(AlignLds& A, const AlignPair& P, const 
         A.L4[i] = w;
     }
     for (int32_t i = threadIdx.x; i < ns; i += kT) A.S[i] = (uint8_t)code(src_s[i]);
-    // matT[s * kNsym + l] = score of large letter l against small letter s
+    // matT[s * kNsym + l] = score of small letter s against large letter l:
+    // the matrix scores a query letter (its row) against a target letter (its
+    // column), so this is the matrix itself when the query is the small
+    // sequence and its transpose otherwise
     for (int32_t i = threadIdx.x; i < kNsym * kNsym; i += kT)
-        A.matT[i] = km.m[(i % kNsym) * kNsym + i / kNsym];
+        A.matT[i] = tl ? km.m[i] : km.m[(i % kNsym) * kNsym + i / kNsym];
     __syncthreads();
 }
 

@@ -69,8 +69,11 @@ template <int kCopies>
 __device__ __forceinline__ void build_profile(uint8_t* prof, int32_t ps, const uint8_t* qcodes,
                                               int32_t qlen, const int8_t* mat, int32_t bias,
                                               uint8_t* tmp, int32_t tid, int32_t nthreads) {
+    // row r of tmp: the scores of every query letter against target letter
+    // r, i.e. column r of the matrix (it scores a query letter, its row,
+    // against a target letter, its column)
     for (int32_t i = tid; i < kProfRows * kNsym; i += nthreads)
-        tmp[i] = i < kNsym * kNsym ? (uint8_t)(mat[i] + bias) : (uint8_t)0;
+        tmp[i] = i < kNsym * kNsym ? (uint8_t)(mat[(i % kNsym) * kNsym + i / kNsym] + bias) : (uint8_t)0;
     __syncthreads();
     const int32_t cpb = profile_copy_bytes(ps);
     uint32_t* p32 = (uint32_t*)prof;

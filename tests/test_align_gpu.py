@@ -97,6 +97,21 @@ def test_few_rounds(rounds):
                 H().Params(rounds=rounds, seed=9))
 
 
+def test_asymmetric_matrix():
+    """A matrix that is not symmetric scores query letters (rows) against
+    target letters (columns), whichever sequence is the large one."""
+    rng = np.random.default_rng(37)
+    m = rng.integers(-5, 11, size=(24, 24)).astype(np.int8)
+    pairs = rand_pairs(rng, 60, 1, 300)
+    p = H().Params(rounds=20, matrix=m, seed=2)
+    got = H().align_batch(pairs, p)
+    op = oparams(p)
+    for i, ((q, t), g) in enumerate(zip(pairs, got)):
+        r = O.align_pair(O.encode(bytes(q)), O.encode(bytes(t)), i, op, matrix=m)
+        assert (g.score, g.round) == (r["score"], r["round"]), f"pair {i} ({len(q)} x {len(t)})"
+        assert [int(x) for x in g.ops] == r["ops"], f"ops of pair {i}"
+
+
 def test_homologs_rounds20():
     """Mutated copies with indels (the paper's distant-homology use)."""
     rng = np.random.default_rng(31)

@@ -245,6 +245,21 @@ def test_per_query_parameters(small):
         same_result(res_b[i], ref, f"query {i} with {p}")
 
 
+def test_asymmetric_matrix_in_batch(small):
+    """Queries of one batch with a matrix that is not symmetric (and its
+    transpose, and the built-in one) equal the oracle."""
+    q0, res, off, codes, db = small
+    rng = np.random.default_rng(38)
+    m = rng.integers(-5, 11, size=(24, 24)).astype(np.int8)
+    qs = [bytes(synth.random_protein(rng, int(n))) for n in (40, 120, 260, 480)]
+    ps = [H().Params(matrix=m), H().Params(matrix=np.ascontiguousarray(m.T)),
+          H().Params(matrix=m, seed=3), H().Params()]
+    got = H().search_batch(db, qs, ps, k=50, n_aln=10)
+    for i, (q, p) in enumerate(zip(qs, ps)):
+        ref = oracle_search(codes, off, q, p, k=50, n_aln=10, matrix=p.matrix)
+        same_result(got[i], ref, f"query {i}")
+
+
 def test_edge_batches(small):
     q0, res, off, codes, db = small
     rng = np.random.default_rng(8)

@@ -153,9 +153,14 @@ def test_single_letter(case):
 # ----------------------------------------------------------------------------
 # P3 + P4: every step re-derived by brute force, draws from numpy
 # ----------------------------------------------------------------------------
-def check_trace(q, t, tid, p, r):
+def check_trace(q, t, tid, p, r, matrix=None):
     target_large = len(t) >= len(q)
     L, S = (t, q) if target_large else (q, t)
+    # the matrix scores a query letter (row) against a target letter
+    # (column): seen from (large, small) it is transposed when the target is
+    # the large one
+    M = B if matrix is None else matrix.astype(np.int64)
+    BLS = M.T if target_large else M
     tr = r["trace"]
     # round actually reported: recompute its factors from numpy draws
     rnd = r["round"]
@@ -174,7 +179,7 @@ def check_trace(q, t, tid, p, r):
         assert ls == max(1, (nL * LF) >> 16)
         assert ss == min(ls, max(1, (nS * SF * u) >> 32))
         assert 1 <= ss <= ls <= nL and ss <= nS
-        Ds = [int(B[L[pL + kk:pL + kk + ss], S[pS:pS + ss]].sum()) for kk in range(ls - ss + 1)]
+        Ds = [int(BLS[L[pL + kk:pL + kk + ss], S[pS:pS + ss]].sum()) for kk in range(ls - ss + 1)]
         assert D == max(Ds) and k == Ds.index(max(Ds))
         total += D
         if step == 0:
@@ -223,6 +228,62 @@ def test_steps_full_factors():
         for (pL, pS, ls, ss, k, D) in r["trace"]:
             assert ls == len(t) - pL
         check_trace(q, t, i, p, r)
+
+
+# ----------------------------------------------------------------------------
+# P4b: a matrix that is not symmetric scores query letters (rows) against
+# target letters (columns), whichever sequence is the large one
+# ----------------------------------------------------------------------------
+def asym_matrix(rng):
+    m = rng.integers(-5, 11, size=(24, 24)).astype(np.int8)    # span 15
+    assert (m != m.T).any()
+    return m
+
+
+@pytest.mark.parametrize("case", range(20))
+def test_asymmetric_single_letter(case):
+    """One-letter small sequence, LF = 1: the first best letter of the
+    matrix column (target large) or row (query large), in closed form."""
+    rng = np.random.default_rng(560 + case)
+    m = asym_matrix(rng)
+    p = rand_params(rng)
+    p.lfactor_q16 = p.minfactor_q16 = 65536
+    L = rand_seq(rng, int(rng.integers(2, 40)), 24)
+    s = rand_seq(rng, 1, 24)
+    col = m[s[0], L].astype(np.int64)        # query s, targets L[k]
+    r = O.align_pair(s, L, 3, p, matrix=m)
+    assert r["score"] == int(col.max()) - p.pgp * (len(L) - 1)
+    row = m[L, s[0]].astype(np.int64)        # query letters L[k], target s
+    r = O.align_pair(L, s, 4, p, matrix=m)
+    assert r["score"] == int(row.max()) - p.pgp * (len(L) - 1)
+
+
+@pytest.mark.parametrize("case", range(20))
+def test_asymmetric_swap(case):
+    """Swapping query and target and transposing the matrix leaves every
+    letter pair's score, and so the alignment's score, unchanged (unequal
+    lengths, so that the large sequence is the same one)."""
+    rng = np.random.default_rng(600 + case)
+    m = asym_matrix(rng)
+    p = rand_params(rng)
+    q = rand_seq(rng, int(rng.integers(1, 80)), 24)
+    t = rand_seq(rng, int(rng.integers(1, 120)), 24)
+    if len(q) == len(t):
+        t = np.concatenate([t, rand_seq(rng, 1, 24)])
+    a = O.align_pair(q, t, case, p, matrix=m)
+    b = O.align_pair(t, q, case, p, matrix=np.ascontiguousarray(m.T))
+    assert (a["score"], a["round"]) == (b["score"], b["round"])
+
+
+@pytest.mark.parametrize("case", range(20))
+def test_asymmetric_steps_brute_force(case):
+    rng = np.random.default_rng(640 + case)
+    m = asym_matrix(rng)
+    p = rand_params(rng)
+    q = rand_seq(rng, int(rng.integers(1, 90)), 24)
+    t = rand_seq(rng, int(rng.integers(1, 140)), 24)
+    r = O.align_pair(q, t, case, p, matrix=m, trace=True)
+    check_trace(q, t, case, p, r, matrix=m)
 
 
 # ----------------------------------------------------------------------------

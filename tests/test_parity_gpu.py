@@ -146,6 +146,29 @@ def test_custom_matrix(small):
     check_search(db, codes, off, q, p, k=60, n_aln=20, matrix=m)
 
 
+@pytest.mark.parametrize("qlen", [70, 300])
+def test_asymmetric_matrix(small, qlen):
+    """A matrix that is not symmetric scores query letters (rows) against
+    target letters (columns): every pair score, the ranking and the
+    alignments equal the oracle's, for targets shorter and longer than the
+    query; the transposed matrix gives other scores."""
+    q0, res, off, codes, db = small
+    rng = np.random.default_rng(71 + qlen)
+    q = q0 if qlen == len(q0) else synth.random_protein(rng, qlen)
+    m = rng.integers(-5, 11, size=(24, 24)).astype(np.int8)     # span 15
+    p = H().Params(matrix=m, pgp=1, seed=4)
+    lens = np.diff(off)
+    say(f"asymmetric matrix, query {len(q)}: {(lens < len(q)).sum()} shorter targets, "
+        f"{(lens >= len(q)).sum()} longer")
+    assert (lens < len(q)).sum() >= 20 and (lens >= len(q)).sum() >= 20
+    s, _, _ = db.scores(bytes(q), p)
+    ref = O.score_all(codes, off, O.encode(bytes(q)), to_oparams(p), matrix=m)[0]
+    assert (s == ref).all(), f"{(s != ref).sum()} pair scores differ"
+    check_search(db, codes, off, q, p, k=60, n_aln=30, matrix=m)
+    st, _, _ = db.scores(bytes(q), H().Params(matrix=np.ascontiguousarray(m.T), pgp=1, seed=4))
+    assert (st != s).any()
+
+
 def test_threshold_and_counts(small):
     q, res, off, codes, db = small
     ref = O.score_all(codes, off, O.encode(bytes(q)), O.Params())[0]
